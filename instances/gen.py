@@ -1,0 +1,330 @@
+"""Pseudo-random numbers, graphs and formulas for the #CSP workloads.
+
+Formulas follow the usual conjunctive layout: ``n_vars`` boolean variables
+numbered 1..n and a list of clauses, each a clause kind plus a list of
+DIMACS-style literals (+v for the variable, -v for its negation). Two clause
+kinds are used, the OR clause of Eq. 3 and the exactly-one clause of Eq. 6
+(Sec. 3.2; there monotone, here negation is allowed as in Sec. 2.1).
+
+Workloads (Sec. 3.2):
+* monotone 1-in-3 with clauses of three distinct variables drawn uniformly;
+* vertex cover of a random 3-regular graph written as 2-variable OR clauses,
+  one per edge, one variable per vertex (the #Cubic-Vertex-Cover encoding);
+* 1-in-3 on a cubic graph with one variable per edge and one clause per
+  vertex (the paper's own 1-in-3 family, every variable in two clauses).
+
+Random cubic graphs come from the configuration model (3n stubs, uniform
+perfect matching of stubs by a Fisher-Yates shuffle) with rejection of the
+whole draw on a self-loop or a repeated edge, which samples simple cubic
+graphs uniformly. The paper samples with the Viger-Latapy Markov chain
+instead; both target the uniform distribution over simple cubic graphs.
+
+Random numbers: SplitMix64 expands a 64-bit seed into the state of
+xoshiro256** (Blackman and Vigna); bounded draws use rejection so they are
+unbiased.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Sequence, Tuple
+
+OR = 0
+EXACTLY_ONE = 1
+
+_M64 = (1 << 64) - 1
+
+
+def _splitmix64_next(state: int) -> Tuple[int, int]:
+    state = (state + 0x9E3779B97F4A7C15) & _M64
+    z = state
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return state, z ^ (z >> 31)
+
+
+def instance_seed(family: int, index: int, master: int = 0) -> int:
+    """64-bit seed of instance ``index`` of workload ``family``."""
+    _, a = _splitmix64_next((master ^ (family << 40) ^ index) & _M64)
+    return a
+
+
+def _rotl(x: int, k: int) -> int:
+    return ((x << k) | (x >> (64 - k))) & _M64
+
+
+class Rng:
+    """xoshiro256** seeded through SplitMix64."""
+
+    def __init__(self, seed: int):
+        st = seed & _M64
+        s = []
+        for _ in range(4):
+            st, v = _splitmix64_next(st)
+            s.append(v)
+        self.s = s
+
+    def next_u64(self) -> int:
+        s0, s1, s2, s3 = self.s
+        result = (_rotl((s1 * 5) & _M64, 7) * 9) & _M64
+        t = (s1 << 17) & _M64
+        s2 ^= s0
+        s3 ^= s1
+        s1 ^= s2
+        s0 ^= s3
+        s2 ^= t
+        s3 = _rotl(s3, 45)
+        self.s = [s0, s1, s2, s3]
+        return result
+
+    def below(self, n: int) -> int:
+        """Uniform integer in [0, n) by rejection of the biased low range."""
+        if n <= 0:
+            raise ValueError("n must be positive")
+        limit = (1 << 64) - ((1 << 64) % n)
+        while True:
+            x = self.next_u64()
+            if x < limit:
+                return x % n
+
+    def uniform_int(self, lo: int, hi: int) -> int:
+        """Uniform integer in [lo, hi] inclusive."""
+        return lo + self.below(hi - lo + 1)
+
+    def coin(self) -> int:
+        return self.next_u64() >> 63
+
+
+@dataclass
+class Formula:
+    """A CNF-like formula: ``clauses[i] = (kind, [literals])``."""
+
+    n_vars: int
+    clauses: List[Tuple[int, List[int]]] = field(default_factory=list)
+    name: str = ""
+
+    @property
+    def n_clauses(self) -> int:
+        return len(self.clauses)
+
+    def arrays(self):
+        """(clause_ptr, lits, kinds) flat lists in the C-ABI layout."""
+        ptr = [0]
+        lits: List[int] = []
+        kinds: List[int] = []
+        for kind, cl in self.clauses:
+            lits.extend(int(x) for x in cl)
+            ptr.append(len(lits))
+            kinds.append(int(kind))
+        return ptr, lits, kinds
+
+    def occurrences(self) -> List[int]:
+        occ = [0] * (self.n_vars + 1)
+        for _, cl in self.clauses:
+            for lit in cl:
+                occ[abs(lit)] += 1
+        return occ[1:]
+
+
+# --------------------------------------------------------------------------
+# graphs (vertex labels 0..n-1, edge lists of (u, v) pairs)
+# --------------------------------------------------------------------------
+
+def cubic_graph(n: int, rng: Rng, max_tries: int = 100000) -> List[Tuple[int, int]]:
+    """Uniform simple 3-regular graph on ``n`` (even) vertices."""
+    if n % 2 or n < 4:
+        raise ValueError("a cubic graph needs an even n >= 4")
+    for _ in range(max_tries):
+        stubs = [v for v in range(n) for _ in range(3)]
+        for i in range(len(stubs) - 1, 0, -1):
+            j = rng.below(i + 1)
+            stubs[i], stubs[j] = stubs[j], stubs[i]
+        edges = []
+        seen = set()
+        ok = True
+        for i in range(0, len(stubs), 2):
+            u, v = stubs[i], stubs[i + 1]
+            if u == v:
+                ok = False
+                break
+            key = (min(u, v), max(u, v))
+            if key in seen:
+                ok = False
+                break
+            seen.add(key)
+            edges.append(key)
+        if ok:
+            return edges
+    raise RuntimeError("configuration model did not produce a simple graph")
+
+
+def cycle_graph(k: int) -> List[Tuple[int, int]]:
+    return [(i, (i + 1) % k) for i in range(k)]
+
+
+def complete_graph(k: int) -> List[Tuple[int, int]]:
+    return [(i, j) for i in range(k) for j in range(i + 1, k)]
+
+
+def complete_bipartite_graph(a: int, b: int) -> List[Tuple[int, int]]:
+    return [(i, a + j) for i in range(a) for j in range(b)]
+
+
+def prism_graph(k: int) -> List[Tuple[int, int]]:
+    """C_k x K_2: two k-cycles (0..k-1 and k..2k-1) joined by rungs."""
+    e = [(i, (i + 1) % k) for i in range(k)]
+    e += [(k + i, k + (i + 1) % k) for i in range(k)]
+    e += [(i, k + i) for i in range(k)]
+    return e
+
+
+def petersen_graph() -> List[Tuple[int, int]]:
+    outer = [(i, (i + 1) % 5) for i in range(5)]
+    spokes = [(i, 5 + i) for i in range(5)]
+    inner = [(5 + i, 5 + (i + 2) % 5) for i in range(5)]
+    return outer + spokes + inner
+
+
+def cube_graph() -> List[Tuple[int, int]]:
+    """The 3-cube Q3: vertices 0..7, edges between labels at Hamming distance 1."""
+    return [(u, u ^ (1 << b)) for u in range(8) for b in range(3) if u < u ^ (1 << b)]
+
+
+# --------------------------------------------------------------------------
+# formulas
+# --------------------------------------------------------------------------
+
+def vertex_cover_formula(edges: Sequence[Tuple[int, int]], n_vertices: int = None,
+                         name: str = "") -> Formula:
+    """#Vertex-Cover as #2SAT: variable per vertex, OR clause per edge."""
+    if n_vertices is None:
+        n_vertices = 1 + max(max(u, v) for u, v in edges) if edges else 0
+    f = Formula(n_vertices, name=name)
+    for u, v in edges:
+        f.clauses.append((OR, [u + 1, v + 1]))
+    return f
+
+
+def perfect_matching_formula(edges: Sequence[Tuple[int, int]], n_vertices: int = None,
+                             name: str = "") -> Formula:
+    """Exactly-one clause per vertex over the variables of its incident edges."""
+    if n_vertices is None:
+        n_vertices = 1 + max(max(u, v) for u, v in edges) if edges else 0
+    inc: List[List[int]] = [[] for _ in range(n_vertices)]
+    for i, (u, v) in enumerate(edges):
+        inc[u].append(i + 1)
+        inc[v].append(i + 1)
+    f = Formula(len(edges), name=name)
+    for v in range(n_vertices):
+        f.clauses.append((EXACTLY_ONE, inc[v]))
+    return f
+
+
+def exactly_one_3(n: int, m: int, rng: Rng, name: str = "") -> Formula:
+    """Monotone 1-in-3: m clauses, each 3 distinct variables drawn uniformly."""
+    if n < 3 and m > 0:
+        raise ValueError("need n >= 3")
+    f = Formula(n, name=name)
+    for _ in range(m):
+        a = rng.below(n)
+        b = rng.below(n)
+        while b == a:
+            b = rng.below(n)
+        c = rng.below(n)
+        while c == a or c == b:
+            c = rng.below(n)
+        f.clauses.append((EXACTLY_ONE, [a + 1, b + 1, c + 1]))
+    return f
+
+
+def cnf_of_exactly_one(f: Formula) -> Formula:
+    """Rewrite every 3-literal exactly-one clause as the five OR clauses of Sec. 3.2.
+
+    For literals (a, b, c) the clauses are (a|b|c), (a|~b|~c), (~a|~b|c),
+    (~a|b|~c), (~a|~b|~c). Other clauses are kept as they are.
+    """
+    g = Formula(f.n_vars, name=(f.name + "-cnf") if f.name else "")
+    for kind, cl in f.clauses:
+        if kind == EXACTLY_ONE and len(cl) == 3:
+            a, b, c = cl
+            g.clauses += [(OR, [a, b, c]), (OR, [a, -b, -c]), (OR, [-a, -b, c]),
+                          (OR, [-a, b, -c]), (OR, [-a, -b, -c])]
+        else:
+            g.clauses.append((kind, list(cl)))
+    return g
+
+
+def random_mixed_formula(n: int, m: int, rng: Rng, max_len: int = 4,
+                         allow_repeats: bool = True, name: str = "") -> Formula:
+    """Small mixed formulas for property tests: OR and exactly-one clauses of
+    length 0..max_len with random negations; repeated and complementary
+    literals inside a clause are allowed when ``allow_repeats``."""
+    f = Formula(n, name=name)
+    for _ in range(m):
+        kind = rng.below(2)
+        length = rng.below(max_len + 1)
+        cl = []
+        while len(cl) < length:
+            v = rng.below(n) + 1
+            if not allow_repeats and any(abs(x) == v for x in cl):
+                continue
+            cl.append(v if rng.coin() else -v)
+        f.clauses.append((kind, cl))
+    return f
+
+
+def disjoint_union(a: Formula, b: Formula) -> Formula:
+    """Formula on a.n_vars + b.n_vars variables; b's variables are shifted."""
+    f = Formula(a.n_vars + b.n_vars, name=f"{a.name}+{b.name}")
+    f.clauses = [(k, list(c)) for k, c in a.clauses]
+    sh = a.n_vars
+    for k, c in b.clauses:
+        f.clauses.append((k, [x + sh if x > 0 else x - sh for x in c]))
+    return f
+
+
+# --------------------------------------------------------------------------
+# named workloads
+# --------------------------------------------------------------------------
+
+FAMILY_SMALL_1IN3 = 0     # monotone 1-in-3, n=20, m=14
+FAMILY_CVC = 1            # vertex cover of random cubic graphs
+FAMILY_LARGE_1IN3 = 2     # monotone 1-in-3, n=150..300, alpha 0.62..0.70
+FAMILY_BATCH = 3          # mixed batch, n in [30, 120]
+FAMILY_LEARNED = 4        # training / held-out 1-in-3, n in [100, 250]
+
+
+def small_1in3(index: int) -> Formula:
+    rng = Rng(instance_seed(FAMILY_SMALL_1IN3, index))
+    return exactly_one_3(20, 14, rng, name=f"1in3-n20-m14-s{index}")
+
+
+def cvc(n: int, index: int) -> Formula:
+    rng = Rng(instance_seed(FAMILY_CVC, (n << 20) | index))
+    return vertex_cover_formula(cubic_graph(n, rng), n, name=f"cvc-n{n}-s{index}")
+
+
+def large_1in3(n: int, alpha: float, index: int) -> Formula:
+    m = int(round(alpha * n))
+    rng = Rng(instance_seed(FAMILY_LARGE_1IN3, (n << 24) | (int(round(alpha * 100)) << 16) | index))
+    return exactly_one_3(n, m, rng, name=f"1in3-n{n}-a{alpha:.2f}-s{index}")
+
+
+def batch_instance(index: int, master: int = 0) -> Formula:
+    """Instance ``index`` of the mixed batch: even -> monotone 1-in-3 with
+    n ~ U[30,120], m = round(0.66 n); odd -> vertex cover of a random cubic
+    graph with n ~ U[30,120] rounded up to even."""
+    rng = Rng(instance_seed(FAMILY_BATCH, index, master))
+    n = rng.uniform_int(30, 120)
+    if index % 2 == 0:
+        return exactly_one_3(n, int(round(0.66 * n)), rng, name=f"batch{index}-1in3-n{n}")
+    n += n % 2
+    return vertex_cover_formula(cubic_graph(n, rng), n, name=f"batch{index}-cvc-n{n}")
+
+
+def learned_instance(index: int, split: str = "train", n: int = None) -> Formula:
+    """1-in-3 at alpha = 0.66 with n ~ U[100, 250] (or a fixed n)."""
+    fam_index = index if split == "train" else (1 << 30) | index
+    rng = Rng(instance_seed(FAMILY_LEARNED, fam_index))
+    if n is None:
+        n = rng.uniform_int(100, 250)
+    return exactly_one_3(n, int(round(0.66 * n)), rng, name=f"learn-{split}{index}-n{n}")
