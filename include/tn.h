@@ -1,0 +1,198 @@
+/*
+ * tn.h -- exact model counting of #CSP formulas by tensor-network
+ * contraction on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Kourtis, Chamon, Mucciolo, Ruckenstein, "Fast counting with
+ * tensor networks", Sec. 2.1 and Sec. 3): a formula becomes a network of
+ * boolean tensors -- a COPY tensor on every variable (Eq. 4), an OR (Eq. 3)
+ * or exactly-one (Eq. 6) tensor on every clause, one bond of dimension 2 per
+ * literal occurrence, a negated literal reversing its index -- and the full
+ * contraction of the network (Eq. 2 at zero temperature) is the number of
+ * satisfying assignments. A host-side order (Sec. 3.1.1: tensor-greedy,
+ * tensor-METIS style recursive bisection, tensor-GN community detection, or
+ * a learned scorer) fixes the sequence of pairwise contractions; HIP kernels
+ * run them on the GPU. Counts are exact: 64-bit unsigned arithmetic while the
+ * formula has at most 63 variables, otherwise residues modulo 31-bit primes
+ * combined on the host by the Chinese remainder theorem (the exact-precision
+ * remark of Sec. 3.2, at a cost linear in the number of primes).
+ *
+ * Conventions for every call:
+ *  - Plain C ABI, no exceptions cross it; every call returns a tn_status.
+ *  - Host arrays passed in are borrowed for the call and copied; nothing the
+ *    caller passes is retained unless stated.
+ *  - Opaque handles are owned by the caller and released with *_free.
+ *  - Device memory on the contraction path is never allocated by the
+ *    library: it sub-allocates the caller's workspace (device pointer).
+ *  - GPU work is queued on the caller's stream (hipStream_t passed as
+ *    void*; NULL = the null stream); calls that return host results
+ *    synchronize that stream before returning.
+ *  - Distinct handles may be used from different threads; one handle must
+ *    not be used by two threads at once.
+ */
+#ifndef TN_H
+#define TN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TN_OK = 0,
+    TN_EINVAL = -1,        /* malformed argument (bad literal, null pointer, ...) */
+    TN_ENOMEM = -2,        /* host allocation failed */
+    TN_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+    TN_ETOOBIG = -4,       /* the plan's peak memory exceeds the workspace */
+    TN_ERANK = -5,         /* a tensor rank exceeds TN_MAX_RANK */
+    TN_EBUFSIZE = -6,      /* output buffer too small; the needed size is returned */
+    TN_EUNSUPPORTED = -7   /* a valid request this build does not handle */
+} tn_status;
+
+/* Largest tensor rank the contraction kernels accept: 2^34 entries. */
+#define TN_MAX_RANK 34
+/* Largest rank of an initial (clause or COPY) tensor. */
+#define TN_MAX_INIT_RANK 24
+/* Most primes one contraction may use (counts up to ~2^1900). */
+#define TN_MAX_PRIMES 64
+
+/* Clause kinds: OR (Eq. 3) and exactly-one (Eq. 6, with negation allowed). */
+typedef enum { TN_CLAUSE_OR = 0, TN_CLAUSE_EXACTLY_ONE = 1 } tn_clause_kind;
+
+/* A formula. Variables are 1..n_vars. Clause c owns literals
+ * lits[clause_ptr[c] .. clause_ptr[c+1]-1]; a literal is +v or -v
+ * (negated). kinds[c] is a tn_clause_kind. A clause may repeat a variable
+ * or hold complementary literals (each occurrence is its own bond). An empty
+ * clause is unsatisfiable; a variable in no clause doubles the count. */
+typedef struct {
+    int32_t n_vars;
+    int32_t n_clauses;
+    const int32_t* clause_ptr;  /* n_clauses + 1 entries, clause_ptr[0] = 0 */
+    const int32_t* lits;        /* clause_ptr[n_clauses] entries */
+    const uint8_t* kinds;       /* n_clauses entries */
+} tn_formula;
+
+typedef struct tn_network tn_network;
+typedef struct tn_plan tn_plan;
+typedef struct tn_model tn_model;
+
+typedef enum {
+    TN_ORDER_GREEDY = 0,     /* Sec. 3.1.1 tensor-greedy: smallest result rank first */
+    TN_ORDER_PARTITION = 1,  /* Sec. 3.1.1 tensor-METIS: recursive best-of-2 bisection */
+    TN_ORDER_COMMUNITY = 2,  /* Sec. 3.1.1 tensor-GN: Girvan-Newman split tree */
+    TN_ORDER_LEARNED = 3,    /* MLP pair scorer, judged against greedy and partition */
+    TN_ORDER_BEST = 4        /* cheapest of greedy, partition and community */
+} tn_order_kind;
+
+/* Predicted cost of a plan, known before any tensor entry is touched (the
+ * "lazy" evaluation of Sec. 4). Entries count 32-bit words per prime. */
+typedef struct {
+    int32_t n_steps;
+    int32_t max_rank;              /* largest rank of any tensor in the plan */
+    double entries;                /* sum over steps of 2^rA + 2^rB + 2^rC */
+    double macs;                   /* sum over steps of 2^(rA + rB - s) */
+    double log2_cost;              /* log2 of the cost model used to judge orders */
+    uint64_t peak_elems;           /* arena high-water mark in entries, one prime */
+    int32_t chosen;                /* tn_order_kind that produced the plan */
+    int32_t fallback;              /* 1 when the learned order lost to the judge */
+} tn_plan_stats;
+
+typedef enum { TN_ARITH_AUTO = 0, TN_ARITH_U64 = 1, TN_ARITH_RNS = 2 } tn_arith;
+
+typedef struct {
+    int32_t arith;            /* tn_arith; AUTO = U64 if n_vars <= 63 else RNS */
+    int32_t n_primes;         /* RNS primes; 0 = ceil(n_vars / 31) + 1 */
+    void* workspace;          /* device memory owned by the caller */
+    size_t workspace_bytes;
+    void* stream;             /* hipStream_t; NULL = null stream */
+    int32_t prime_group;      /* primes resident at once; 0 = as many as fit */
+    int32_t flags;            /* TN_FLAG_* */
+} tn_contract_opts;
+
+#define TN_FLAG_GENERIC_ONLY 1   /* use only the generic kernel (testing) */
+#define TN_FLAG_NO_MFMA 2        /* never use the int8-limb MFMA kernel */
+#define TN_FLAG_TIMING 4         /* record per-kernel-class device times */
+#define TN_FLAG_NO_GRAPH 8       /* batch: launch waves directly, no hipGraph */
+
+/* ------------------------------------------------------------------ build
+ * Formula -> network (Sec. 2.1). Validates every literal and clause kind;
+ * returns TN_EINVAL on malformed input and TN_ERANK when a variable occurs
+ * more than TN_MAX_INIT_RANK times or a clause has more literals. */
+tn_status tn_build(const tn_formula* f, tn_network** out);
+void tn_network_free(tn_network* net);
+/* Number of tensors (n_vars COPY tensors first, then one per clause) and
+ * bonds (one per literal occurrence). */
+tn_status tn_network_info(const tn_network* net, int32_t* n_tensors, int32_t* n_bonds);
+
+/* ------------------------------------------------------------------ order
+ * Host-only: chooses a pairwise contraction order and lays out the plan
+ * (bit order of every tensor, arena offsets, kernel choice) and its
+ * predicted cost. ``seed`` drives the randomized bisections. ``model`` is
+ * used by TN_ORDER_LEARNED (may be NULL otherwise; with NULL the learned
+ * order falls back to the judge's choice). */
+tn_status tn_order(const tn_network* net, tn_order_kind kind, uint64_t seed,
+                   const tn_model* model, tn_plan** out, tn_plan_stats* stats);
+void tn_plan_free(tn_plan* plan);
+/* Copy the merges of a plan: pairs[2k], pairs[2k+1] are the tensor ids of
+ * step k, which creates tensor id n_tensors + k. cap = pair capacity. */
+tn_status tn_plan_steps(const tn_plan* plan, int32_t* pairs, int32_t cap, int32_t* n_steps);
+
+/* --------------------------------------------------------------- contract
+ * Device workspace needed for a plan under opts (arith, n_primes,
+ * prime_group; workspace fields ignored). With prime_group = 0 the answer
+ * is for one prime resident at a time. */
+tn_status tn_workspace_bytes(const tn_network* net, const tn_plan* plan,
+                             const tn_contract_opts* opts, size_t* bytes);
+
+/* Runs the plan on the GPU. RNS: writes the count modulo each of the
+ * n_primes primes (see tn_primes) to residues[0..n_primes-1]. U64: writes
+ * the exact count to *u64. Either output pointer may be NULL when unused.
+ * Returns TN_ETOOBIG before any device work when the workspace cannot hold
+ * one prime's arena. */
+tn_status tn_contract(const tn_network* net, const tn_plan* plan, const tn_contract_opts* opts,
+                      uint32_t* residues, int32_t residues_cap, uint64_t* u64);
+
+/* Exact count as little-endian base-2^32 limbs (CRT of the residues or the
+ * 64-bit value). TN_EBUFSIZE with *n_limbs set when cap is too small. */
+tn_status tn_count(const tn_network* net, const tn_plan* plan, const tn_contract_opts* opts,
+                   uint32_t* limbs, size_t cap, size_t* n_limbs);
+
+/* Batched counting of n formulas: build and order on host threads, then
+ * contract all instances together in waves (one persistent launch per wave,
+ * captured in a hipGraph). limbs holds cap_per limbs per instance; n_limbs
+ * receives each instance's limb count. The workspace is split into
+ * sub-batches that fit. stats (nullable) receives n entries. */
+tn_status tn_count_batch(const tn_formula* fs, int32_t n, tn_order_kind kind, uint64_t seed,
+                         const tn_contract_opts* opts, uint32_t* limbs, size_t cap_per,
+                         size_t* n_limbs, tn_plan_stats* stats);
+
+/* Device time per kernel class recorded by the last tn_contract / tn_count /
+ * tn_count_batch call of the calling thread made with TN_FLAG_TIMING
+ * (hipEvents around every launch, on the caller's stream). bytes and macs
+ * are the algorithmic totals of those launches: 2^rA + 2^rB + 2^rC entries
+ * of 4 or 8 bytes and 2^(rA + rB - s) multiply-adds per step and prime. */
+typedef enum { TN_KC_GENERIC = 0, TN_KC_STREAM = 1, TN_KC_ROWDOT = 2, TN_KC_MFMA = 3, TN_KC_BATCH = 4 } tn_kernel_class;
+#define TN_KERNEL_CLASSES 5
+typedef struct {
+    int64_t launches;
+    double ms;
+    double bytes;
+    double macs;
+} tn_kernel_profile;
+tn_status tn_profile_get(tn_kernel_profile* out /* TN_KERNEL_CLASSES entries */);
+
+/* -------------------------------------------------------------- utilities */
+/* The k largest primes below 2^31, descending, as used by the RNS path. */
+tn_status tn_primes(int32_t k, uint32_t* out);
+/* Chinese remaindering of residues modulo the first k primes of tn_primes
+ * into little-endian base-2^32 limbs. */
+tn_status tn_crt(const uint32_t* residues, int32_t k, uint32_t* limbs, size_t cap, size_t* n_limbs);
+const char* tn_status_str(tn_status s);
+/* Library version string. */
+const char* tn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TN_H */

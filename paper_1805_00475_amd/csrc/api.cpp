@@ -1,0 +1,151 @@
+// Host-side entry points of the C ABI: build, order, plan queries, primes,
+// CRT and status strings. The GPU entry points live in contract.hip.
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+using namespace tn;
+
+extern "C" {
+
+tn_status tn_build(const tn_formula* f, tn_network** out) {
+    if (!f || !out) return TN_EINVAL;
+    *out = nullptr;
+    tn_network* h = new (std::nothrow) tn_network;
+    if (!h) return TN_ENOMEM;
+    tn_status st = build_network(f, h->net);
+    if (st != TN_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return TN_OK;
+}
+
+void tn_network_free(tn_network* net) { delete net; }
+
+tn_status tn_network_info(const tn_network* net, int32_t* n_tensors, int32_t* n_bonds) {
+    if (!net) return TN_EINVAL;
+    if (n_tensors) *n_tensors = int32_t(net->net.t.size());
+    if (n_bonds) *n_bonds = int32_t(net->net.bond_end.size());
+    return TN_OK;
+}
+
+tn_status tn_order(const tn_network* net, tn_order_kind kind, uint64_t seed, const tn_model* model,
+                   tn_plan** out, tn_plan_stats* stats) {
+    if (!net || !out) return TN_EINVAL;
+    *out = nullptr;
+    tn_plan* h = new (std::nothrow) tn_plan;
+    if (!h) return TN_ENOMEM;
+    tn_status st = TN_OK;
+    try {
+        const Network& N = net->net;
+        auto plan_of = [&](int32_t k, Plan& p) -> tn_status {
+            switch (k) {
+                case TN_ORDER_GREEDY: return make_plan(N, order_greedy(N), k, p);
+                case TN_ORDER_PARTITION: return make_plan(N, order_partition(N, seed), k, p);
+                case TN_ORDER_COMMUNITY: return make_plan(N, order_community(N), k, p);
+                default: return TN_EINVAL;
+            }
+        };
+        if (kind == TN_ORDER_GREEDY || kind == TN_ORDER_PARTITION || kind == TN_ORDER_COMMUNITY) {
+            st = plan_of(kind, h->plan);
+        } else if (kind == TN_ORDER_BEST || kind == TN_ORDER_LEARNED) {
+            // the judge: the cheapest plan under the cost model (Sec. 4,
+            // lazy evaluation), plans whose ranks exceed the cap excluded
+            bool have = false;
+            tn_status last = TN_ERANK;
+            for (int32_t k : {TN_ORDER_GREEDY, TN_ORDER_PARTITION, TN_ORDER_COMMUNITY}) {
+                Plan p;
+                tn_status s2 = plan_of(k, p);
+                if (s2 != TN_OK) {
+                    last = s2;
+                    continue;
+                }
+                if (!have || plan_cost(p) < plan_cost(h->plan)) {
+                    h->plan = std::move(p);
+                    have = true;
+                }
+            }
+            if (kind == TN_ORDER_LEARNED) {
+                bool ok = false;
+                auto lm = order_learned(N, model, &ok);
+                Plan p;
+                if (ok && make_plan(N, lm, TN_ORDER_LEARNED, p) == TN_OK &&
+                    (!have || plan_cost(p) <= plan_cost(h->plan))) {
+                    h->plan = std::move(p);
+                    have = true;
+                } else if (have) {
+                    h->plan.stats.fallback = 1;
+                }
+            }
+            st = have ? TN_OK : last;
+        } else {
+            st = TN_EINVAL;
+        }
+    } catch (const std::bad_alloc&) {
+        st = TN_ENOMEM;
+    }
+    if (st != TN_OK) {
+        delete h;
+        return st;
+    }
+    if (stats) *stats = h->plan.stats;
+    *out = h;
+    return TN_OK;
+}
+
+void tn_plan_free(tn_plan* plan) { delete plan; }
+
+tn_status tn_plan_steps(const tn_plan* plan, int32_t* pairs, int32_t cap, int32_t* n_steps) {
+    if (!plan) return TN_EINVAL;
+    const int32_t n = int32_t(plan->plan.merges.size());
+    if (n_steps) *n_steps = n;
+    if (!pairs) return TN_OK;
+    if (cap < n) return TN_EBUFSIZE;
+    for (int32_t k = 0; k < n; ++k) {
+        pairs[2 * k] = plan->plan.merges[k].first;
+        pairs[2 * k + 1] = plan->plan.merges[k].second;
+    }
+    return TN_OK;
+}
+
+tn_status tn_primes(int32_t k, uint32_t* out) {
+    if (k < 0 || k > TN_MAX_PRIMES || (k > 0 && !out)) return TN_EINVAL;
+    const auto& P = prime_table(k);
+    std::copy(P.begin(), P.begin() + k, out);
+    return TN_OK;
+}
+
+tn_status tn_crt(const uint32_t* residues, int32_t k, uint32_t* limbs, size_t cap, size_t* n_limbs) {
+    if (k <= 0 || k > TN_MAX_PRIMES || !residues || !n_limbs) return TN_EINVAL;
+    const auto& P = prime_table(k);
+    for (int32_t i = 0; i < k; ++i)
+        if (residues[i] >= P[i]) return TN_EINVAL;
+    std::vector<uint32_t> L;
+    crt_limbs(residues, k, L);
+    *n_limbs = L.size();
+    if (!limbs || cap < L.size()) return TN_EBUFSIZE;
+    std::copy(L.begin(), L.end(), limbs);
+    return TN_OK;
+}
+
+const char* tn_status_str(tn_status s) {
+    switch (s) {
+        case TN_OK: return "ok";
+        case TN_EINVAL: return "invalid argument";
+        case TN_ENOMEM: return "out of host memory";
+        case TN_EHIP: return "HIP runtime error";
+        case TN_ETOOBIG: return "plan does not fit the workspace";
+        case TN_ERANK: return "tensor rank above the supported maximum";
+        case TN_EBUFSIZE: return "output buffer too small";
+        case TN_EUNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+const char* tn_version(void) { return "tn-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

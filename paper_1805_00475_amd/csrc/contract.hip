@@ -1,0 +1,475 @@
+// GPU contraction of a plan: upload the initial 0/1 tensors, run every
+// pairwise step with a kernel chosen by its shape, read back the final
+// scalar of every prime, and (tn_count) recombine by CRT.
+//
+// Step semantics (Sec. 2.1, Eq. 5; all shared bonds at once, Sec. 2.2):
+//     C[c] = sum over z in {0,1}^s of A[z | xA << s] * B[z | xB << s]
+// with xA = the C bits selected by maskA and xB those selected by maskB, in
+// order. Arithmetic is modulo a 31-bit prime (one prime per blockIdx.z) or
+// wrapping 64-bit, which is exact while the count fits (n <= 63).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+#include "profile.hpp"
+
+namespace tn {
+
+// ------------------------------------------------------------------ kernels
+
+template <bool U64>
+__device__ __forceinline__ void load_planes(const StepArgs& a, const void*& A, const void*& B, void*& C) {
+    using T = typename std::conditional<U64, uint64_t, uint32_t>::type;
+    const int g = blockIdx.z;
+    A = static_cast<const T*>(a.A) + g * a.strideA;
+    B = static_cast<const T*>(a.B) + g * a.strideB;
+    C = static_cast<T*>(a.C) + g * a.strideC;
+}
+
+// Any shape: one thread per output entry, bit gathers by loops.
+template <bool U64>
+__global__ __launch_bounds__(256) void k_generic(StepArgs a) {
+    using T = typename std::conditional<U64, uint64_t, uint32_t>::type;
+    const void *pA, *pB;
+    void* pC;
+    load_planes<U64>(a, pA, pB, pC);
+    const T* A = static_cast<const T*>(pA);
+    const T* B = static_cast<const T*>(pB);
+    T* C = static_cast<T*>(pC);
+    const ModP m{a.p[blockIdx.z], a.r2[blockIdx.z]};
+    const uint64_t total = uint64_t(1) << a.rC;
+    const uint64_t K = uint64_t(1) << a.s;
+    for (uint64_t c = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < total;
+         c += uint64_t(gridDim.x) * blockDim.x) {
+        const T* ra = A + (pext64(c, a.maskA) << a.s);
+        const T* rb = B + (pext64(c, a.maskB) << a.s);
+        if constexpr (U64) {
+            uint64_t acc = 0;
+            for (uint64_t z = 0; z < K; ++z) acc += ra[z] * rb[z];
+            C[c] = acc;
+        } else {
+            uint64_t acc = 0;
+            uint32_t n3 = 0;
+            for (uint64_t z = 0; z < K; ++z) {
+                acc += uint64_t(ra[z]) * rb[z];
+                if (++n3 == 3) {
+                    acc = m.fold(acc);
+                    n3 = 0;
+                }
+            }
+            C[c] = m.finish(acc);
+        }
+    }
+}
+
+// Streaming step, small shared dimension (K = 2^LOGK <= 32): each thread
+// owns one xA (256 consecutive xA per block iteration, so A is read once,
+// coalesced) and NB consecutive xB of the block's xB chunk; the B slab is
+// uniform across the block. Output positions split into a uniform part
+// (block's xA base and xB chunk) and per-lane / per-j parts deposited once.
+template <bool U64, int LOGK, int NB>
+__global__ __launch_bounds__(256) void k_stream(StepArgs a) {
+    using T = typename std::conditional<U64, uint64_t, uint32_t>::type;
+    constexpr int K = 1 << LOGK;
+    const void *pA, *pB;
+    void* pC;
+    load_planes<U64>(a, pA, pB, pC);
+    const T* A = static_cast<const T*>(pA);
+    const T* B = static_cast<const T*>(pB);
+    T* C = static_cast<T*>(pC);
+    const ModP m{a.p[blockIdx.z], a.r2[blockIdx.z]};
+    const uint64_t lane = threadIdx.x;
+    const uint64_t laneC = pdep64(lane, a.maskA);
+    uint64_t offB[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) offB[j] = pdep64(uint64_t(j), a.maskB);
+    const uint64_t n_iter = (uint64_t(1) << a.fA) >> 8;
+    const uint64_t n_chunk = (uint64_t(1) << a.fB) / NB;
+    for (uint64_t cb = blockIdx.y; cb < n_chunk; cb += gridDim.y) {
+        const uint64_t xb0 = cb * NB;
+        const uint64_t baseB = pdep64(xb0, a.maskB);
+        const T* rb = B + (xb0 << LOGK);
+        for (uint64_t it = blockIdx.x; it < n_iter; it += gridDim.x) {
+            const uint64_t xA = (it << 8) | lane;
+            const uint64_t cA = pdep64(it << 8, a.maskA) | laneC | baseB;
+            T av[K];
+            const T* ra = A + (xA << LOGK);
+#pragma unroll
+            for (int z = 0; z < K; ++z) av[z] = ra[z];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                if constexpr (U64) {
+                    uint64_t acc = 0;
+#pragma unroll
+                    for (int z = 0; z < K; ++z) acc += av[z] * rb[j * K + z];
+                    C[cA | offB[j]] = acc;
+                } else {
+                    uint64_t acc = 0;
+#pragma unroll
+                    for (int z = 0; z < K; ++z) {
+                        acc += uint64_t(av[z]) * rb[j * K + z];
+                        if (z % 3 == 2) acc = m.fold(acc);
+                    }
+                    C[cA | offB[j]] = m.finish(acc);
+                }
+            }
+        }
+    }
+}
+
+// Wide shared dimension, few outputs: one wavefront per output entry, lanes
+// stride over z (coalesced rows of A and B), then a wavefront reduction.
+template <bool U64>
+__global__ __launch_bounds__(256) void k_rowdot(StepArgs a) {
+    using T = typename std::conditional<U64, uint64_t, uint32_t>::type;
+    const void *pA, *pB;
+    void* pC;
+    load_planes<U64>(a, pA, pB, pC);
+    const T* A = static_cast<const T*>(pA);
+    const T* B = static_cast<const T*>(pB);
+    T* C = static_cast<T*>(pC);
+    const ModP m{a.p[blockIdx.z], a.r2[blockIdx.z]};
+    const int lane = threadIdx.x & 63;
+    const uint64_t wave = threadIdx.x >> 6;
+    const uint64_t total = uint64_t(1) << a.rC;
+    const uint64_t K = uint64_t(1) << a.s;
+    for (uint64_t c = uint64_t(blockIdx.x) * 4 + wave; c < total; c += uint64_t(gridDim.x) * 4) {
+        const T* ra = A + (pext64(c, a.maskA) << a.s);
+        const T* rb = B + (pext64(c, a.maskB) << a.s);
+        if constexpr (U64) {
+            uint64_t acc = 0;
+            for (uint64_t z = lane; z < K; z += 64) acc += ra[z] * rb[z];
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+            if (lane == 0) C[c] = acc;
+        } else {
+            uint64_t acc = 0;
+            uint32_t n3 = 0;
+            for (uint64_t z = lane; z < K; z += 64) {
+                acc += uint64_t(ra[z]) * rb[z];
+                if (++n3 == 3) {
+                    acc = m.fold(acc);
+                    n3 = 0;
+                }
+            }
+            uint32_t r = m.finish(acc);
+            for (int off = 32; off > 0; off >>= 1) {
+                uint32_t o = __shfl_xor(r, off);
+                uint32_t t = r + o;  // both < p < 2^31: no overflow
+                r = t >= m.p ? t - m.p : t;
+            }
+            if (lane == 0) C[c] = r;
+        }
+    }
+}
+
+// ----------------------------------------------------------------- launches
+
+namespace {
+
+template <bool U64, int LOGK>
+hipError_t launch_stream_nb(int nb, dim3 grid, hipStream_t st, const StepArgs& a) {
+    switch (nb) {
+        case 1: hipLaunchKernelGGL((k_stream<U64, LOGK, 1>), grid, dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_stream<U64, LOGK, 2>), grid, dim3(256), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_stream<U64, LOGK, 4>), grid, dim3(256), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_stream<U64, LOGK, 8>), grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_stream<U64, LOGK, 16>), grid, dim3(256), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <bool U64>
+hipError_t launch_stream(int logk, int nb, dim3 grid, hipStream_t st, const StepArgs& a) {
+    switch (logk) {
+        case 0: return launch_stream_nb<U64, 0>(nb, grid, st, a);
+        case 1: return launch_stream_nb<U64, 1>(nb, grid, st, a);
+        case 2: return launch_stream_nb<U64, 2>(nb, grid, st, a);
+        case 3: return launch_stream_nb<U64, 3>(nb, grid, st, a);
+        case 4: return launch_stream_nb<U64, 4>(nb, grid, st, a);
+        default: return launch_stream_nb<U64, 5>(nb, grid, st, a);
+    }
+}
+
+inline uint32_t cap32(uint64_t x, uint32_t hi) { return uint32_t(std::min<uint64_t>(std::max<uint64_t>(x, 1), hi)); }
+
+// Choose and launch the kernel of one step for a group of G primes.
+hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* primes, int G, char* init_base,
+                       char* arena_base, int64_t arena_elems, hipStream_t stream, KernelClass* kc) {
+    const size_t es = u64 ? 8 : 4;
+    Step st = st0;
+    StepArgs a{};
+    a.B = st.initB ? init_base + st.offB * es : arena_base + st.offB * es;
+    a.A = st.initA ? init_base + st.offA * es : arena_base + st.offA * es;
+    a.C = arena_base + st.offC * es;
+    a.strideA = st.initA ? 0 : arena_elems;
+    a.strideB = st.initB ? 0 : arena_elems;
+    a.strideC = arena_elems;
+    const uint64_t cmask = st.rC >= 64 ? ~0ull : ((uint64_t(1) << st.rC) - 1);
+    a.maskA = st.maskA;
+    a.maskB = cmask & ~st.maskA;
+    a.rC = st.rC;
+    a.s = st.s;
+    a.fA = st.rA - st.s;
+    a.fB = st.rB - st.s;
+    for (int g = 0; g < G; ++g) {
+        a.p[g] = primes ? primes[g] : 0;
+        a.r2[g] = primes ? uint32_t((uint64_t(1) << 32) % primes[g]) : 0;
+    }
+    // the larger free side plays A
+    if (a.fB > a.fA) {
+        std::swap(a.A, a.B);
+        std::swap(a.strideA, a.strideB);
+        std::swap(a.maskA, a.maskB);
+        std::swap(a.fA, a.fB);
+    }
+    const bool generic_only = flags & TN_FLAG_GENERIC_ONLY;
+    const uint64_t total = uint64_t(1) << a.rC;
+    if (!generic_only && a.s <= 5 && a.fA >= 8) {
+        const int nb = std::min(a.fB, 4);
+        const uint64_t n_iter = (uint64_t(1) << a.fA) >> 8;
+        const uint64_t n_chunk = (uint64_t(1) << a.fB) >> nb;
+        dim3 grid(cap32(n_iter, 1u << 20), cap32(n_chunk, 65535), G);
+        *kc = KC_STREAM;
+        return u64 ? launch_stream<true>(a.s, 1 << nb, grid, stream, a)
+                   : launch_stream<false>(a.s, 1 << nb, grid, stream, a);
+    }
+    if (!generic_only && a.s >= 6) {
+        dim3 grid(cap32((total + 3) / 4, 1u << 20), 1, G);
+        *kc = KC_ROWDOT;
+        if (u64)
+            hipLaunchKernelGGL(k_rowdot<true>, grid, dim3(256), 0, stream, a);
+        else
+            hipLaunchKernelGGL(k_rowdot<false>, grid, dim3(256), 0, stream, a);
+        return hipGetLastError();
+    }
+    dim3 grid(cap32((total + 255) / 256, 1u << 20), 1, G);
+    *kc = KC_GENERIC;
+    if (u64)
+        hipLaunchKernelGGL(k_generic<true>, grid, dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_generic<false>, grid, dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+// Value of one initial tensor entry x in the plan's bit order ``layout``
+// (Eq. 3, Eq. 4, Eq. 6; a negated index is reversed, Sec. 2.1).
+uint64_t init_entry(const InitTensor& t, const std::vector<int32_t>& pos, uint64_t x) {
+    const int r = int(t.bonds.size());
+    if (t.kind == T_COPY) {
+        if (r == 0) return 2;  // a variable in no clause: both values count
+        const uint64_t all = (r >= 64) ? ~0ull : ((uint64_t(1) << r) - 1);
+        return (x == 0 || x == all) ? 1 : 0;
+    }
+    int ntrue = 0;
+    for (int k = 0; k < r; ++k) {
+        int bit = int((x >> pos[k]) & 1);
+        ntrue += bit ^ int((t.neg >> k) & 1);
+    }
+    if (t.kind == T_OR) return ntrue >= 1 ? 1 : 0;
+    return ntrue == 1 ? 1 : 0;
+}
+
+struct Resolved {
+    bool u64 = false;
+    int32_t k = 0;  // primes
+    std::vector<uint32_t> primes;
+};
+
+tn_status resolve(const Plan& plan, const tn_contract_opts* o, Resolved& r) {
+    int32_t arith = o ? o->arith : TN_ARITH_AUTO;
+    if (arith == TN_ARITH_AUTO) arith = plan.n_vars <= 63 ? TN_ARITH_U64 : TN_ARITH_RNS;
+    if (arith == TN_ARITH_U64) {
+        if (plan.n_vars > 63) return TN_EINVAL;  // 64-bit wrapping is exact only below 2^64
+        r.u64 = true;
+        r.k = 1;
+        return TN_OK;
+    }
+    if (arith != TN_ARITH_RNS) return TN_EINVAL;
+    r.u64 = false;
+    r.k = (o && o->n_primes > 0) ? o->n_primes : (plan.n_vars + 30) / 31 + 1;
+    if (r.k > TN_MAX_PRIMES) return TN_EINVAL;
+    const auto& P = prime_table(r.k);
+    r.primes.assign(P.begin(), P.begin() + r.k);
+    return TN_OK;
+}
+
+int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+// Runs the plan; fills residues (RNS) or *u64v (U64).
+tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts* o, const Resolved& R,
+                   std::vector<uint32_t>& residues, uint64_t* u64v) {
+    const size_t es = R.u64 ? 8 : 4;
+    residues.assign(R.u64 ? 0 : R.k, 0);
+    // networks that need no device work
+    if (plan.n_init == 0) {
+        if (R.u64) *u64v = 1;
+        for (auto& x : residues) x = 1;
+        return TN_OK;
+    }
+    if (plan.steps.empty()) {
+        const InitTensor& t = net.t[plan.root];
+        uint64_t v = init_entry(t, {}, 0);
+        if (R.u64) *u64v = v;
+        for (int i = 0; i < R.k && !R.u64; ++i) residues[i] = uint32_t(v % R.primes[i]);
+        return TN_OK;
+    }
+    if (!o || !o->workspace) return TN_EINVAL;
+    const int64_t init_bytes = align256(plan.init_elems * int64_t(es));
+    const int64_t arena_bytes = align256(plan.arena_elems * int64_t(es));
+    const int64_t arena_elems = arena_bytes / int64_t(es);
+    const int64_t ws = int64_t(o->workspace_bytes);
+    if (init_bytes + arena_bytes > ws) return TN_ETOOBIG;
+    int G = int((ws - init_bytes) / std::max<int64_t>(arena_bytes, 256));
+    G = std::min({G, R.k, kMaxGroup});
+    if (o->prime_group > 0) G = std::min(G, int(o->prime_group));
+    G = std::max(G, 1);
+    hipStream_t stream = static_cast<hipStream_t>(o->stream);
+    char* base = static_cast<char*>(o->workspace);
+    char* init_base = base;
+    char* arena_base = base + init_bytes;
+    // initial tensors in plan layout, identical for every prime (0/1/2 entries)
+    std::vector<uint8_t> host(size_t(plan.init_elems) * es, 0);
+    for (int32_t i = 0; i < plan.n_init; ++i) {
+        const InitTensor& t = net.t[i];
+        const auto& L = plan.layout[i];
+        std::vector<int32_t> pos(t.bonds.size());
+        for (size_t k = 0; k < t.bonds.size(); ++k)
+            pos[k] = int32_t(std::find(L.begin(), L.end(), t.bonds[k]) - L.begin());
+        const uint64_t n = uint64_t(1) << t.bonds.size();
+        for (uint64_t x = 0; x < n; ++x) {
+            uint64_t v = init_entry(t, pos, x);
+            if (R.u64)
+                reinterpret_cast<uint64_t*>(host.data())[plan.init_off[i] + x] = v;
+            else
+                reinterpret_cast<uint32_t*>(host.data())[plan.init_off[i] + x] = uint32_t(v);
+        }
+    }
+    Profiler& prof = profiler();
+    prof.begin(o->flags & TN_FLAG_TIMING, stream);
+    hipError_t err = hipMemcpyAsync(init_base, host.data(), host.size(), hipMemcpyHostToDevice, stream);
+    // on any failure, drain the stream before the host staging buffer goes away
+    auto fail = [&]() {
+        (void)hipStreamSynchronize(stream);
+        prof.end();
+        return TN_EHIP;
+    };
+    if (err != hipSuccess) return fail();
+    const Step& last = plan.steps.back();
+    std::vector<uint64_t> out(size_t(R.k), 0);
+    for (int g0 = 0; g0 < R.k; g0 += G) {
+        const int gn = std::min(G, R.k - g0);
+        for (const Step& st : plan.steps) {
+            KernelClass kc = KC_GENERIC;
+            prof.before(stream);
+            err = launch_step(st, R.u64, o->flags, R.u64 ? nullptr : R.primes.data() + g0, gn, init_base, arena_base,
+                              arena_elems, stream, &kc);
+            if (err != hipSuccess) return fail();
+            prof.after(stream, kc, st, gn, es);
+        }
+        for (int g = 0; g < gn; ++g) {
+            err = hipMemcpyAsync(&out[g0 + g], arena_base + (g * arena_elems + last.offC) * int64_t(es), es,
+                                 hipMemcpyDeviceToHost, stream);
+            if (err != hipSuccess) return fail();
+        }
+    }
+    err = hipStreamSynchronize(stream);
+    if (err != hipSuccess) return TN_EHIP;
+    prof.end();
+    if (R.u64) {
+        *u64v = out[0];
+    } else {
+        for (int i = 0; i < R.k; ++i) residues[i] = uint32_t(out[i] & 0xffffffffu);
+    }
+    return TN_OK;
+}
+
+}  // namespace tn
+
+using namespace tn;
+
+extern "C" {
+
+tn_status tn_workspace_bytes(const tn_network* net, const tn_plan* plan, const tn_contract_opts* opts,
+                             size_t* bytes) {
+    if (!net || !plan || !bytes) return TN_EINVAL;
+    Resolved R;
+    tn_status st = resolve(plan->plan, opts, R);
+    if (st != TN_OK) return st;
+    const int64_t es = R.u64 ? 8 : 4;
+    int G = (opts && opts->prime_group > 0) ? std::min<int>(opts->prime_group, std::min(R.k, kMaxGroup)) : 1;
+    *bytes = size_t(align256(plan->plan.init_elems * es) + int64_t(G) * align256(plan->plan.arena_elems * es));
+    return TN_OK;
+}
+
+tn_status tn_contract(const tn_network* net, const tn_plan* plan, const tn_contract_opts* opts, uint32_t* residues,
+                      int32_t residues_cap, uint64_t* u64) {
+    if (!net || !plan) return TN_EINVAL;
+    if (int32_t(net->net.t.size()) != plan->plan.n_init) return TN_EINVAL;
+    Resolved R;
+    tn_status st = resolve(plan->plan, opts, R);
+    if (st != TN_OK) return st;
+    if (!R.u64 && residues && residues_cap < R.k) return TN_EBUFSIZE;
+    std::vector<uint32_t> res;
+    uint64_t v = 0;
+    try {
+        st = run_plan(net->net, plan->plan, opts, R, res, &v);
+    } catch (const std::bad_alloc&) {
+        return TN_ENOMEM;
+    }
+    if (st != TN_OK) return st;
+    if (R.u64) {
+        if (u64) *u64 = v;
+    } else if (residues) {
+        std::copy(res.begin(), res.end(), residues);
+    }
+    return TN_OK;
+}
+
+tn_status tn_count(const tn_network* net, const tn_plan* plan, const tn_contract_opts* opts, uint32_t* limbs,
+                   size_t cap, size_t* n_limbs) {
+    if (!net || !plan || !n_limbs) return TN_EINVAL;
+    if (int32_t(net->net.t.size()) != plan->plan.n_init) return TN_EINVAL;
+    Resolved R;
+    tn_status st = resolve(plan->plan, opts, R);
+    if (st != TN_OK) return st;
+    std::vector<uint32_t> res, L;
+    uint64_t v = 0;
+    try {
+        st = run_plan(net->net, plan->plan, opts, R, res, &v);
+        if (st != TN_OK) return st;
+        if (R.u64) {
+            L = {uint32_t(v), uint32_t(v >> 32)};
+            while (L.size() > 1 && L.back() == 0) L.pop_back();
+        } else {
+            crt_limbs(res.data(), R.k, L);
+        }
+    } catch (const std::bad_alloc&) {
+        return TN_ENOMEM;
+    }
+    *n_limbs = L.size();
+    if (!limbs || cap < L.size()) return TN_EBUFSIZE;
+    std::copy(L.begin(), L.end(), limbs);
+    return TN_OK;
+}
+
+}  // extern "C"
+
+namespace tn {
+Profiler& profiler() {
+    static thread_local Profiler p;
+    return p;
+}
+}  // namespace tn
+
+extern "C" tn_status tn_profile_get(tn_kernel_profile* out) {
+    if (!out) return TN_EINVAL;
+    for (int i = 0; i < TN_KERNEL_CLASSES; ++i) out[i] = tn::profiler().acc[i];
+    return TN_OK;
+}

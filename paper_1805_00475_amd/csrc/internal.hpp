@@ -1,0 +1,103 @@
+// Internal data structures shared by the host-side parts of libtn.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "tn.h"
+
+namespace tn {
+
+enum TKind : uint8_t { T_COPY = 0, T_OR = 1, T_EXONE = 2 };
+
+// A tensor of the original network (Sec. 2.1). ``bonds[k]`` is the bond on
+// index k: for a COPY tensor the k-th occurrence of its variable, for a
+// clause tensor its k-th literal. Bit k of ``neg`` reverses index k.
+struct InitTensor {
+    uint8_t kind = T_COPY;
+    std::vector<int32_t> bonds;
+    uint64_t neg = 0;
+};
+
+struct Network {
+    int32_t n_vars = 0;
+    int32_t n_clauses = 0;
+    std::vector<InitTensor> t;                   // variables first, then clauses
+    std::vector<std::array<int32_t, 2>> bond_end;  // (COPY tensor, clause tensor)
+};
+
+// One pairwise contraction C = A (x) B in the layout convention of the plan:
+// every tensor stores its bonds sorted by the step at which they are
+// contracted (earliest first, bond id breaking ties), bit 0 being the
+// earliest. The s bonds shared by A and B die at this step, so they are the
+// low s bits of both operands: A = [z | xA], B = [z | xB]. C's bits are the
+// free bonds of A and B merged in the same sort order; bit j of ``maskA``
+// says C's bit j comes from A.
+struct Step {
+    int32_t a = -1, b = -1, out = -1;
+    int32_t rA = 0, rB = 0, s = 0, rC = 0;
+    uint64_t maskA = 0;
+    bool initA = false, initB = false;   // operand lives in the shared init region
+    int64_t offA = 0, offB = 0, offC = 0;  // element offsets (init region or arena)
+    int32_t level = 0;                   // longest chain of steps feeding this one
+};
+
+struct Plan {
+    int32_t n_init = 0;
+    int32_t n_vars = 0;
+    std::vector<std::pair<int32_t, int32_t>> merges;
+    std::vector<Step> steps;
+    std::vector<int32_t> rank;                 // per tensor id
+    std::vector<std::vector<int32_t>> layout;  // per tensor id: bond on each bit
+    std::vector<int64_t> init_off;             // per initial tensor, element offset
+    int64_t init_elems = 0;                    // size of the init region (elements)
+    int64_t arena_elems = 0;                   // arena size for one prime (elements)
+    int32_t root = -1;                         // id of the final scalar
+    tn_plan_stats stats{};
+};
+
+constexpr int64_t kAlignElems = 64;  // 256 bytes for 32-bit entries
+
+// network.cpp
+tn_status build_network(const tn_formula* f, Network& net);
+
+// order_*.cpp: produce merges (pairs of tensor ids; merge k creates id
+// n_init + k). Every order ends with a single tensor.
+struct Graph;  // adjacency of live tensors
+std::vector<std::pair<int32_t, int32_t>> order_greedy(const Network& net);
+std::vector<std::pair<int32_t, int32_t>> order_partition(const Network& net, uint64_t seed);
+std::vector<std::pair<int32_t, int32_t>> order_community(const Network& net);
+std::vector<std::pair<int32_t, int32_t>> order_learned(const Network& net, const tn_model* model,
+                                                       bool* ok);
+
+// Shared by the hierarchical orders: absorb every tensor of rank <= 2 into a
+// neighbour (never raises any rank). Returns the merges done and, for every
+// surviving group, its current tensor id, its rank and its bond set.
+struct Reduced {
+    std::vector<std::pair<int32_t, int32_t>> merges;
+    std::vector<int32_t> id;                  // tensor id of each reduced vertex
+    std::vector<std::vector<int32_t>> bonds;  // bonds of each reduced vertex
+    int32_t next_id = 0;
+};
+Reduced absorb_small(const Network& net);
+
+// plan.cpp
+tn_status make_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>> merges,
+                    int32_t chosen, Plan& plan);
+double plan_cost(const Plan& plan);
+
+// crt.cpp
+const std::vector<uint32_t>& prime_table(int32_t k);
+void crt_limbs(const uint32_t* residues, int32_t k, std::vector<uint32_t>& limbs);
+
+}  // namespace tn
+
+struct tn_network {
+    tn::Network net;
+};
+struct tn_plan {
+    tn::Plan plan;
+};

@@ -1,0 +1,424 @@
+// tensor-METIS style order (Sec. 3.1.1): recursively bisect the tensor graph
+// into two parts of roughly equal size cutting as few bonds as possible,
+// computing every bisection twice from different random starts and keeping
+// the better one, down to single tensors; the resulting separator hierarchy
+// is contracted bottom-up, the smallest separators first (Corollary 1 and
+// Fig. 2): post-order, each subtree reduced to one tensor before its parent
+// merge.
+//
+// The bisection is this library's own multilevel scheme in the spirit of
+// METIS: heavy-edge matching to coarsen, greedy graph growing from a random
+// vertex for the initial cut, Fiduccia-Mattheyses refinement while
+// uncoarsening. Before partitioning, tensors of rank <= 2 are absorbed into
+// a neighbour (this never raises a rank); vertex weight 1 per remaining
+// tensor, edge weight = number of bonds shared.
+#include <algorithm>
+#include <numeric>
+
+#include "graph.hpp"
+#include "internal.hpp"
+
+namespace tn {
+
+WGraph reduced_graph(const Reduced& r, bool unit_weights) {
+    // bond -> owning reduced vertices
+    int32_t maxb = -1;
+    for (const auto& b : r.bonds)
+        for (int32_t x : b) maxb = std::max(maxb, x);
+    std::vector<int32_t> o1(size_t(maxb + 1), -1), o2(size_t(maxb + 1), -1);
+    for (int32_t v = 0; v < int32_t(r.bonds.size()); ++v)
+        for (int32_t x : r.bonds[v]) (o1[x] < 0 ? o1[x] : o2[x]) = v;
+    const int32_t n = int32_t(r.bonds.size());
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> al(n);
+    auto bump = [&](int32_t u, int32_t v) {
+        for (auto& pr : al[u])
+            if (pr.first == v) {
+                pr.second += 1;
+                return;
+            }
+        al[u].push_back({v, 1});
+    };
+    for (int32_t x = 0; x <= maxb; ++x)
+        if (o1[x] >= 0 && o2[x] >= 0 && o1[x] != o2[x]) {
+            bump(o1[x], o2[x]);
+            bump(o2[x], o1[x]);
+        }
+    WGraph g;
+    g.n = n;
+    g.xadj.assign(n + 1, 0);
+    g.vw.assign(n, 1);
+    for (int32_t v = 0; v < n; ++v) {
+        std::sort(al[v].begin(), al[v].end());
+        for (const auto& pr : al[v]) {
+            g.adj.push_back(pr.first);
+            g.ew.push_back(unit_weights ? 1 : pr.second);
+        }
+        g.xadj[v + 1] = int32_t(g.adj.size());
+    }
+    return g;
+}
+
+std::vector<std::vector<int32_t>> components(const WGraph& g, const std::vector<int32_t>& verts) {
+    std::vector<int32_t> mark(g.n, -2);
+    for (int32_t v : verts) mark[v] = -1;
+    std::vector<std::vector<int32_t>> comps;
+    for (int32_t v : verts) {
+        if (mark[v] != -1) continue;
+        std::vector<int32_t> comp{v};
+        mark[v] = int32_t(comps.size());
+        for (size_t h = 0; h < comp.size(); ++h) {
+            int32_t u = comp[h];
+            for (int32_t e = g.xadj[u]; e < g.xadj[u + 1]; ++e) {
+                int32_t w = g.adj[e];
+                if (mark[w] == -1) {
+                    mark[w] = int32_t(comps.size());
+                    comp.push_back(w);
+                }
+            }
+        }
+        std::sort(comp.begin(), comp.end());
+        comps.push_back(std::move(comp));
+    }
+    return comps;
+}
+
+namespace {
+
+WGraph induced(const WGraph& g, const std::vector<int32_t>& verts, std::vector<int32_t>& local) {
+    local.assign(g.n, -1);
+    for (int32_t i = 0; i < int32_t(verts.size()); ++i) local[verts[i]] = i;
+    WGraph h;
+    h.n = int32_t(verts.size());
+    h.xadj.assign(h.n + 1, 0);
+    for (int32_t i = 0; i < h.n; ++i) {
+        int32_t v = verts[i];
+        h.vw.push_back(g.vw[v]);
+        for (int32_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e)
+            if (local[g.adj[e]] >= 0) {
+                h.adj.push_back(local[g.adj[e]]);
+                h.ew.push_back(g.ew[e]);
+            }
+        h.xadj[i + 1] = int32_t(h.adj.size());
+    }
+    return h;
+}
+
+int64_t cut_of(const WGraph& g, const std::vector<uint8_t>& side) {
+    int64_t c = 0;
+    for (int32_t v = 0; v < g.n; ++v)
+        for (int32_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e)
+            if (side[v] != side[g.adj[e]]) c += g.ew[e];
+    return c / 2;
+}
+
+struct Balance {
+    int64_t lo, hi;  // allowed weight of side 0
+};
+
+Balance balance_of(const WGraph& g) {
+    int64_t W = g.total_vw();
+    int64_t maxw = 0;
+    for (int32_t w : g.vw) maxw = std::max<int64_t>(maxw, w);
+    int64_t tol = std::max<int64_t>(maxw, (W * 5 + 99) / 100);
+    int64_t lo = std::max<int64_t>(1, W / 2 - tol);
+    int64_t hi = std::min<int64_t>(W - 1, (W + 1) / 2 + tol);
+    if (lo > hi) lo = hi = W / 2;
+    return {lo, hi};
+}
+
+// Fiduccia-Mattheyses passes: move the unlocked vertex of best gain that
+// keeps the balance, remember the best prefix of moves, undo the rest.
+void fm_refine(const WGraph& g, std::vector<uint8_t>& side, int max_passes) {
+    const Balance bal = balance_of(g);
+    int64_t w0 = 0;
+    for (int32_t v = 0; v < g.n; ++v)
+        if (side[v] == 0) w0 += g.vw[v];
+    const int64_t W = g.total_vw();
+    std::vector<int64_t> gain(g.n);
+    std::vector<uint8_t> locked(g.n);
+    for (int pass = 0; pass < max_passes; ++pass) {
+        for (int32_t v = 0; v < g.n; ++v) {
+            int64_t gv = 0;
+            for (int32_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e) gv += side[g.adj[e]] != side[v] ? g.ew[e] : -g.ew[e];
+            gain[v] = gv;
+        }
+        std::fill(locked.begin(), locked.end(), 0);
+        std::vector<int32_t> moves;
+        int64_t cur = 0, best = 0;
+        size_t best_k = 0;
+        int64_t best_dev = std::llabs(2 * w0 - W);
+        int64_t cw0 = w0;
+        for (int32_t it = 0; it < g.n; ++it) {
+            int32_t pick = -1;
+            for (int32_t v = 0; v < g.n; ++v) {
+                if (locked[v]) continue;
+                int64_t nw0 = side[v] == 0 ? cw0 - g.vw[v] : cw0 + g.vw[v];
+                bool ok = nw0 >= bal.lo && nw0 <= bal.hi;
+                // a move out of an unbalanced state toward balance is allowed
+                if (!ok && std::llabs(2 * nw0 - W) < std::llabs(2 * cw0 - W)) ok = true;
+                if (!ok) continue;
+                if (pick < 0 || gain[v] > gain[pick]) pick = v;
+            }
+            if (pick < 0) break;
+            cur -= gain[pick];
+            cw0 = side[pick] == 0 ? cw0 - g.vw[pick] : cw0 + g.vw[pick];
+            side[pick] ^= 1;
+            locked[pick] = 1;
+            moves.push_back(pick);
+            gain[pick] = -gain[pick];
+            for (int32_t e = g.xadj[pick]; e < g.xadj[pick + 1]; ++e) {
+                int32_t u = g.adj[e];
+                // edge (pick,u) changed from cut to uncut or back
+                gain[u] += side[u] == side[pick] ? -2 * g.ew[e] : 2 * g.ew[e];
+            }
+            int64_t dev = std::llabs(2 * cw0 - W);
+            bool inb = cw0 >= bal.lo && cw0 <= bal.hi;
+            if (inb && (cur < best || (cur == best && dev < best_dev))) {
+                best = cur;
+                best_k = moves.size();
+                best_dev = dev;
+            }
+        }
+        for (size_t k = moves.size(); k > best_k; --k) {
+            int32_t v = moves[k - 1];
+            side[v] ^= 1;
+        }
+        w0 = 0;
+        for (int32_t v = 0; v < g.n; ++v)
+            if (side[v] == 0) w0 += g.vw[v];
+        if (best_k == 0) break;
+    }
+}
+
+// Greedy graph growing: start side 0 at a random vertex, repeatedly add
+// the boundary vertex whose move lowers the cut most, until side 0 holds
+// half the weight.
+std::vector<uint8_t> grow(const WGraph& g, SplitMix& rng) {
+    std::vector<uint8_t> side(g.n, 1);
+    const int64_t W = g.total_vw();
+    int32_t seed = int32_t(rng.below(uint32_t(g.n)));
+    side[seed] = 0;
+    int64_t w0 = g.vw[seed];
+    while (2 * w0 < W) {
+        int32_t pick = -1;
+        int64_t pg = 0;
+        for (int32_t v = 0; v < g.n; ++v) {
+            if (side[v] == 0) continue;
+            int64_t gv = 0;
+            bool boundary = false;
+            for (int32_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e) {
+                if (side[g.adj[e]] == 0) {
+                    gv += g.ew[e];
+                    boundary = true;
+                } else {
+                    gv -= g.ew[e];
+                }
+            }
+            if (!boundary) gv -= 1 << 20;  // prefer staying connected
+            if (pick < 0 || gv > pg) {
+                pick = v;
+                pg = gv;
+            }
+        }
+        if (pick < 0) break;
+        side[pick] = 0;
+        w0 += g.vw[pick];
+    }
+    return side;
+}
+
+// One level of heavy-edge matching; cmap maps fine -> coarse vertex.
+WGraph coarsen(const WGraph& g, SplitMix& rng, std::vector<int32_t>& cmap) {
+    std::vector<int32_t> perm(g.n);
+    std::iota(perm.begin(), perm.end(), 0);
+    for (int32_t i = g.n - 1; i > 0; --i) std::swap(perm[i], perm[rng.below(uint32_t(i + 1))]);
+    std::vector<int32_t> match(g.n, -1);
+    for (int32_t v : perm) {
+        if (match[v] >= 0) continue;
+        int32_t best = -1, bw = -1;
+        for (int32_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e) {
+            int32_t u = g.adj[e];
+            if (match[u] < 0 && u != v && g.ew[e] > bw) {
+                best = u;
+                bw = g.ew[e];
+            }
+        }
+        if (best >= 0) {
+            match[v] = best;
+            match[best] = v;
+        } else {
+            match[v] = v;
+        }
+    }
+    cmap.assign(g.n, -1);
+    int32_t nc = 0;
+    for (int32_t v = 0; v < g.n; ++v)
+        if (cmap[v] < 0) {
+            cmap[v] = nc;
+            cmap[match[v]] = nc;
+            ++nc;
+        }
+    WGraph c;
+    c.n = nc;
+    c.vw.assign(nc, 0);
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> al(nc);
+    for (int32_t v = 0; v < g.n; ++v) {
+        c.vw[cmap[v]] += g.vw[v];
+        for (int32_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e) {
+            int32_t a = cmap[v], b = cmap[g.adj[e]];
+            if (a == b) continue;
+            bool found = false;
+            for (auto& pr : al[a])
+                if (pr.first == b) {
+                    pr.second += g.ew[e];
+                    found = true;
+                    break;
+                }
+            if (!found) al[a].push_back({b, g.ew[e]});
+        }
+    }
+    c.xadj.assign(nc + 1, 0);
+    for (int32_t a = 0; a < nc; ++a) {
+        std::sort(al[a].begin(), al[a].end());
+        for (const auto& pr : al[a]) {
+            c.adj.push_back(pr.first);
+            c.ew.push_back(pr.second);
+        }
+        c.xadj[a + 1] = int32_t(c.adj.size());
+    }
+    return c;
+}
+
+}  // namespace
+
+std::vector<uint8_t> bisect(const WGraph& g, SplitMix& rng, int64_t* cut) {
+    if (g.n <= 1) {
+        if (cut) *cut = 0;
+        return std::vector<uint8_t>(g.n, 0);
+    }
+    std::vector<WGraph> levels{g};
+    std::vector<std::vector<int32_t>> maps;
+    while (levels.back().n > 24) {
+        std::vector<int32_t> cm;
+        WGraph c = coarsen(levels.back(), rng, cm);
+        if (c.n > levels.back().n * 9 / 10) break;
+        maps.push_back(std::move(cm));
+        levels.push_back(std::move(c));
+    }
+    const WGraph& top = levels.back();
+    std::vector<uint8_t> best;
+    int64_t bestcut = -1;
+    for (int t = 0; t < 6; ++t) {
+        std::vector<uint8_t> side = grow(top, rng);
+        fm_refine(top, side, 8);
+        int64_t c = cut_of(top, side);
+        if (bestcut < 0 || c < bestcut) {
+            bestcut = c;
+            best = side;
+        }
+    }
+    std::vector<uint8_t> side = best;
+    for (int32_t L = int32_t(maps.size()) - 1; L >= 0; --L) {
+        const WGraph& fine = levels[L];
+        std::vector<uint8_t> fs(fine.n);
+        for (int32_t v = 0; v < fine.n; ++v) fs[v] = side[maps[L][v]];
+        fm_refine(fine, fs, 8);
+        side = std::move(fs);
+    }
+    // never return an empty side
+    int32_t n0 = 0;
+    for (uint8_t s : side) n0 += s == 0;
+    if (n0 == 0 || n0 == g.n) {
+        for (int32_t v = 0; v < g.n; ++v) side[v] = v < g.n / 2 ? 0 : 1;
+    }
+    if (cut) *cut = cut_of(g, side);
+    return side;
+}
+
+std::vector<std::pair<int32_t, int32_t>> merges_from_tree(const Reduced& r, const Tree& t, int32_t root) {
+    std::vector<std::pair<int32_t, int32_t>> merges = r.merges;
+    int32_t next = r.next_id;
+    // iterative post-order
+    std::vector<std::pair<int32_t, int>> st;  // (node, state)
+    std::vector<int32_t> val;                // tensor id of finished subtrees
+    if (r.id.empty()) return merges;
+    st.push_back({root, 0});
+    while (!st.empty()) {
+        auto& top = st.back();
+        int32_t node = top.first;
+        if (node < 0) {
+            val.push_back(r.id[~node]);
+            st.pop_back();
+            continue;
+        }
+        if (top.second == 0) {
+            top.second = 1;
+            st.push_back({t.kids[node].second, 0});
+            st.push_back({t.kids[node].first, 0});
+            continue;
+        }
+        st.pop_back();
+        int32_t b = val.back();
+        val.pop_back();
+        int32_t a = val.back();
+        val.pop_back();
+        merges.push_back({std::min(a, b), std::max(a, b)});
+        val.push_back(next++);
+    }
+    return merges;
+}
+
+namespace {
+
+struct PartitionBuilder {
+    const WGraph& g;
+    SplitMix rng;
+    Tree tree;
+    PartitionBuilder(const WGraph& g_, uint64_t seed) : g(g_), rng(seed) {}
+
+    // join subtrees left to right (outer products of independent parts)
+    int32_t chain(const std::vector<int32_t>& nodes) {
+        int32_t acc = nodes[0];
+        for (size_t i = 1; i < nodes.size(); ++i) acc = tree_node(tree, acc, nodes[i]);
+        return acc;
+    }
+
+    int32_t build(const std::vector<int32_t>& verts) {
+        if (verts.size() == 1) return ~verts[0];
+        auto comps = components(g, verts);
+        if (comps.size() > 1) {
+            std::sort(comps.begin(), comps.end(),
+                      [](const std::vector<int32_t>& a, const std::vector<int32_t>& b) {
+                          return a.size() != b.size() ? a.size() < b.size() : a[0] < b[0];
+                      });
+            std::vector<int32_t> nodes;
+            for (const auto& c : comps) nodes.push_back(build(c));
+            return chain(nodes);
+        }
+        std::vector<int32_t> local;
+        WGraph h = induced(g, verts, local);
+        // best of two bisections (Sec. 3.1.1)
+        int64_t c1 = 0, c2 = 0;
+        std::vector<uint8_t> s1 = bisect(h, rng, &c1);
+        std::vector<uint8_t> s2 = bisect(h, rng, &c2);
+        const std::vector<uint8_t>& s = c2 < c1 ? s2 : s1;
+        std::vector<int32_t> L, R;
+        for (int32_t i = 0; i < h.n; ++i) (s[i] == 0 ? L : R).push_back(verts[i]);
+        return tree_node(tree, build(L), build(R));
+    }
+};
+
+}  // namespace
+
+std::vector<std::pair<int32_t, int32_t>> order_partition(const Network& net, uint64_t seed) {
+    Reduced r = absorb_small(net);
+    if (r.id.size() <= 1) return r.merges;
+    WGraph g = reduced_graph(r, false);
+    PartitionBuilder pb(g, seed ^ 0x5EEDB15EC7ull);
+    std::vector<int32_t> all(g.n);
+    std::iota(all.begin(), all.end(), 0);
+    int32_t root = pb.build(all);
+    return merges_from_tree(r, pb.tree, root);
+}
+
+}  // namespace tn

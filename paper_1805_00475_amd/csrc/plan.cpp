@@ -1,0 +1,231 @@
+// Plan: from a list of pairwise merges to everything the GPU loop needs --
+// the bit order of every tensor, the per-step kernel parameters, the arena
+// offsets, and the predicted cost (the "lazy" evaluation of Sec. 4: contract
+// the graph first, track ranks, and know the cost before any entry is
+// touched).
+//
+// Layout convention. Every bond dies at exactly one step (the step where
+// the two tensors holding it merge). Each tensor lists its bonds sorted by
+// death step, earliest first (bond id on ties); bit 0 of an entry's index
+// is the earliest-dying bond. The bonds shared by the two operands of a step
+// die at that step and every other bond of either operand dies later, so
+// the shared bonds are the low s bits of both operands, in the same order:
+// A = [z | xA] and B = [z | xB], and C's bits are the free bonds of A and B
+// merged in death order -- which is again the layout C's own consumer needs.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <new>
+
+#include "internal.hpp"
+
+namespace tn {
+
+namespace {
+
+int64_t align_up(int64_t x) { return (x + kAlignElems - 1) / kAlignElems * kAlignElems; }
+
+// First-fit arena over [0, inf) with coalescing free list.
+struct Arena {
+    std::map<int64_t, int64_t> free_;  // offset -> size
+    int64_t top = 0;
+    int64_t high = 0;
+    int64_t alloc(int64_t n) {
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= n) {
+                int64_t off = it->first;
+                int64_t rest = it->second - n;
+                free_.erase(it);
+                if (rest > 0) free_[off + n] = rest;
+                return off;
+            }
+        // extend: reuse a free block touching the top
+        int64_t off = top;
+        if (!free_.empty()) {
+            auto last = std::prev(free_.end());
+            if (last->first + last->second == top) {
+                off = last->first;
+                free_.erase(last);
+            }
+        }
+        top = off + n;
+        high = std::max(high, top);
+        return off;
+    }
+    void release(int64_t off, int64_t n) {
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+                it = pv;
+            }
+        }
+        if (it->first + it->second == top) {
+            top = it->first;
+            free_.erase(it);
+        }
+    }
+};
+
+}  // namespace
+
+// Predicted device time in microseconds under a simple model: a step moves
+// 4 (2^rA + 2^rB + 2^rC) bytes at ~5 TB/s, does 2^(rA+rB-s) modular
+// multiply-adds at ~4e12/s on vector units, or ~1e14/s when it is wide
+// enough for the int8-limb matrix path, and pays ~2 us of launch overhead.
+static double step_cost_us(int rA, int rB, int s, int rC) {
+    double bytes = 4.0 * (std::ldexp(1.0, rA) + std::ldexp(1.0, rB) + std::ldexp(1.0, rC));
+    double macs = std::ldexp(1.0, rA + rB - s);
+    bool dense = s >= 6 && (rA - s) >= 4 && (rB - s) >= 4;
+    double t_mem = bytes / 5e12;
+    double t_mac = macs / (dense ? 1e14 : 4e12);
+    return 1e6 * std::max(t_mem, t_mac) + 2.0;
+}
+
+double plan_cost(const Plan& plan) {
+    double t = 0;
+    for (const Step& st : plan.steps) t += step_cost_us(st.rA, st.rB, st.s, st.rC);
+    return t;
+}
+
+tn_status make_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>> merges, int32_t chosen,
+                    Plan& plan) {
+    try {
+        const int32_t n_init = int32_t(net.t.size());
+        plan = Plan{};
+        plan.n_init = n_init;
+        plan.n_vars = net.n_vars;
+        const int32_t n_bonds = int32_t(net.bond_end.size());
+        const int32_t n_ids = n_init + int32_t(merges.size());
+        // --- validate the merge list and compute bond sets
+        std::vector<std::vector<int32_t>> bset(n_ids);
+        std::vector<int8_t> state(n_ids, 0);  // 0 unborn, 1 live, 2 consumed
+        for (int32_t i = 0; i < n_init; ++i) {
+            bset[i] = net.t[i].bonds;
+            std::sort(bset[i].begin(), bset[i].end());
+            if (std::adjacent_find(bset[i].begin(), bset[i].end()) != bset[i].end()) return TN_EINVAL;
+            state[i] = 1;
+        }
+        std::vector<int32_t> death(n_bonds, -1);
+        for (int32_t k = 0; k < int32_t(merges.size()); ++k) {
+            int32_t a = merges[k].first, b = merges[k].second;
+            if (a < 0 || b < 0 || a >= n_init + k || b >= n_init + k || a == b) return TN_EINVAL;
+            if (state[a] != 1 || state[b] != 1) return TN_EINVAL;
+            state[a] = state[b] = 2;
+            state[n_init + k] = 1;
+            std::vector<int32_t>& c = bset[n_init + k];
+            std::set_symmetric_difference(bset[a].begin(), bset[a].end(), bset[b].begin(), bset[b].end(),
+                                          std::back_inserter(c));
+            std::vector<int32_t> sh;
+            std::set_intersection(bset[a].begin(), bset[a].end(), bset[b].begin(), bset[b].end(),
+                                  std::back_inserter(sh));
+            for (int32_t x : sh) death[x] = k;
+            if (int32_t(c.size()) > TN_MAX_RANK) return TN_ERANK;
+        }
+        int32_t live = 0, root = -1;
+        for (int32_t i = 0; i < n_ids; ++i)
+            if (state[i] == 1) {
+                ++live;
+                root = i;
+            }
+        if (n_ids > 0 && live != 1) return TN_EINVAL;
+        if (root >= 0 && !bset[root].empty()) return TN_EINVAL;  // open bonds left
+        plan.root = root;
+        plan.merges = merges;
+        // --- layouts: bonds by (death, id)
+        plan.layout.resize(n_ids);
+        plan.rank.resize(n_ids);
+        for (int32_t i = 0; i < n_ids; ++i) {
+            std::vector<int32_t> l = bset[i];
+            std::sort(l.begin(), l.end(), [&](int32_t x, int32_t y) {
+                return death[x] != death[y] ? death[x] < death[y] : x < y;
+            });
+            plan.rank[i] = int32_t(l.size());
+            plan.layout[i] = std::move(l);
+        }
+        // --- init region
+        plan.init_off.assign(n_init, 0);
+        int64_t io = 0;
+        for (int32_t i = 0; i < n_init; ++i) {
+            plan.init_off[i] = io;
+            io += align_up(int64_t(1) << plan.rank[i]);
+        }
+        plan.init_elems = io;
+        // --- steps, levels and arena
+        std::vector<int32_t> level(n_ids, 0);
+        std::vector<int64_t> off(n_ids, -1);
+        Arena arena;
+        plan.steps.reserve(merges.size());
+        double entries = 0, macs = 0;
+        int32_t maxr = 0;
+        for (int32_t i = 0; i < n_init; ++i) maxr = std::max(maxr, plan.rank[i]);
+        for (int32_t k = 0; k < int32_t(merges.size()); ++k) {
+            Step st;
+            st.a = merges[k].first;
+            st.b = merges[k].second;
+            st.out = n_init + k;
+            st.rA = plan.rank[st.a];
+            st.rB = plan.rank[st.b];
+            st.rC = plan.rank[st.out];
+            st.s = (st.rA + st.rB - st.rC) / 2;
+            const auto& LA = plan.layout[st.a];
+            const auto& LB = plan.layout[st.b];
+            for (int32_t z = 0; z < st.s; ++z)
+                if (LA[z] != LB[z]) return TN_EINVAL;  // cannot happen by construction
+            // C = merge of A[s..] and B[s..] in (death, id) order
+            size_t ia = size_t(st.s), ib = size_t(st.s);
+            int32_t j = 0;
+            const auto& LC = plan.layout[st.out];
+            uint64_t mask = 0;
+            for (; j < st.rC; ++j) {
+                int32_t bnd = LC[j];
+                if (ia < LA.size() && LA[ia] == bnd) {
+                    mask |= uint64_t(1) << j;
+                    ++ia;
+                } else if (ib < LB.size() && LB[ib] == bnd) {
+                    ++ib;
+                } else {
+                    return TN_EINVAL;
+                }
+            }
+            st.maskA = mask;
+            st.initA = st.a < n_init;
+            st.initB = st.b < n_init;
+            st.level = 1 + std::max(level[st.a], level[st.b]);
+            level[st.out] = st.level;
+            int64_t szC = align_up(int64_t(1) << st.rC);
+            st.offC = arena.alloc(szC);
+            off[st.out] = st.offC;
+            st.offA = st.initA ? plan.init_off[st.a] : off[st.a];
+            st.offB = st.initB ? plan.init_off[st.b] : off[st.b];
+            if (!st.initA) arena.release(off[st.a], align_up(int64_t(1) << st.rA));
+            if (!st.initB) arena.release(off[st.b], align_up(int64_t(1) << st.rB));
+            entries += std::ldexp(1.0, st.rA) + std::ldexp(1.0, st.rB) + std::ldexp(1.0, st.rC);
+            macs += std::ldexp(1.0, st.rA + st.rB - st.s);
+            maxr = std::max(maxr, st.rC);
+            plan.steps.push_back(st);
+        }
+        plan.arena_elems = arena.high;
+        plan.stats.n_steps = int32_t(plan.steps.size());
+        plan.stats.max_rank = maxr;
+        plan.stats.entries = entries;
+        plan.stats.macs = macs;
+        plan.stats.peak_elems = uint64_t(plan.arena_elems + plan.init_elems);
+        double c = plan_cost(plan);
+        plan.stats.log2_cost = c > 0 ? std::log2(c) : 0.0;
+        plan.stats.chosen = chosen;
+        plan.stats.fallback = 0;
+    } catch (const std::bad_alloc&) {
+        return TN_ENOMEM;
+    }
+    return TN_OK;
+}
+
+}  // namespace tn

@@ -1,0 +1,76 @@
+// Optional per-launch device timing with hipEvents on the caller's stream,
+// accumulated per kernel class together with the algorithmic bytes and
+// multiply-adds of the launched steps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace tn {
+
+enum KernelClass { KC_GENERIC = 0, KC_STREAM = 1, KC_ROWDOT = 2, KC_MFMA = 3, KC_BATCH = 4 };
+
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<int> cls;
+    tn_kernel_profile acc[TN_KERNEL_CLASSES]{};
+
+    hipEvent_t ev() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void begin(bool enable, hipStream_t) {
+        on = enable;
+        used = 0;
+        cls.clear();
+        for (auto& a : acc) a = tn_kernel_profile{};
+    }
+    void before(hipStream_t s) {
+        if (!on) return;
+        hipEvent_t e = ev();
+        if (e) hipEventRecord(e, s);
+    }
+    void account(int kc, double bytes, double macs) {
+        acc[kc].launches += 1;
+        acc[kc].bytes += bytes;
+        acc[kc].macs += macs;
+    }
+    void after(hipStream_t s, int kc, const Step& st, int G, size_t es) {
+        if (!on) return;
+        hipEvent_t e = ev();
+        if (e) hipEventRecord(e, s);
+        cls.push_back(kc);
+        account(kc, double(es) * G * (std::ldexp(1.0, st.rA) + std::ldexp(1.0, st.rB) + std::ldexp(1.0, st.rC)),
+                double(G) * std::ldexp(1.0, st.rA + st.rB - st.s));
+    }
+    void after_raw(hipStream_t s, int kc, double bytes, double macs) {
+        if (!on) return;
+        hipEvent_t e = ev();
+        if (e) hipEventRecord(e, s);
+        cls.push_back(kc);
+        account(kc, bytes, macs);
+    }
+    // call after the stream is synchronized
+    void end() {
+        if (!on) return;
+        for (size_t i = 0; i < cls.size() && 2 * i + 1 < used; ++i) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, pool[2 * i], pool[2 * i + 1]) == hipSuccess) acc[cls[i]].ms += ms;
+        }
+        on = false;
+    }
+};
+
+Profiler& profiler();
+
+}  // namespace tn

@@ -1,0 +1,325 @@
+"""ctypes binding of libtn (include/tn.h): argument marshalling only.
+
+Every step of the counting path runs in the library: network building and
+ordering on the host in C++, contraction in HIP kernels on the GPU. PyTorch
+provides device memory (the workspace) and the stream. There is no fallback:
+if the library is missing or no GPU is visible, the GPU calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtn.so")
+
+TN_OK = 0
+STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ETOOBIG", -5: "ERANK", -6: "EBUFSIZE",
+          -7: "EUNSUPPORTED"}
+ORDERS = {"greedy": 0, "partition": 1, "community": 2, "learned": 3, "best": 4}
+ORDER_NAMES = {v: k for k, v in ORDERS.items()}
+ARITH = {"auto": 0, "u64": 1, "rns": 2}
+FLAG_GENERIC_ONLY = 1
+FLAG_NO_MFMA = 2
+FLAG_TIMING = 4
+FLAG_NO_GRAPH = 8
+KERNEL_CLASSES = ["generic", "stream", "rowdot", "mfma", "batch"]
+MAX_RANK = 34
+MAX_PRIMES = 64
+
+
+class TNError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({status})")
+        self.status = status
+
+
+class Formula_c(ctypes.Structure):
+    _fields_ = [("n_vars", ctypes.c_int32), ("n_clauses", ctypes.c_int32),
+                ("clause_ptr", ctypes.POINTER(ctypes.c_int32)), ("lits", ctypes.POINTER(ctypes.c_int32)),
+                ("kinds", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class PlanStats_c(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("max_rank", ctypes.c_int32), ("entries", ctypes.c_double),
+                ("macs", ctypes.c_double), ("log2_cost", ctypes.c_double), ("peak_elems", ctypes.c_uint64),
+                ("chosen", ctypes.c_int32), ("fallback", ctypes.c_int32)]
+
+
+class ContractOpts_c(ctypes.Structure):
+    _fields_ = [("arith", ctypes.c_int32), ("n_primes", ctypes.c_int32), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p),
+                ("prime_group", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class KernelProfile_c(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("macs", ctypes.c_double)]
+
+
+_lib = None
+
+# exported symbols and their signatures (argtypes, restype)
+_P = ctypes.POINTER
+_SIGS = {
+    "tn_build": ([_P(Formula_c), _P(ctypes.c_void_p)], ctypes.c_int),
+    "tn_network_free": ([ctypes.c_void_p], None),
+    "tn_network_info": ([ctypes.c_void_p, _P(ctypes.c_int32), _P(ctypes.c_int32)], ctypes.c_int),
+    "tn_order": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, _P(ctypes.c_void_p),
+                  _P(PlanStats_c)], ctypes.c_int),
+    "tn_plan_free": ([ctypes.c_void_p], None),
+    "tn_plan_steps": ([ctypes.c_void_p, _P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_int32)], ctypes.c_int),
+    "tn_workspace_bytes": ([ctypes.c_void_p, ctypes.c_void_p, _P(ContractOpts_c), _P(ctypes.c_size_t)],
+                           ctypes.c_int),
+    "tn_contract": ([ctypes.c_void_p, ctypes.c_void_p, _P(ContractOpts_c), _P(ctypes.c_uint32), ctypes.c_int32,
+                     _P(ctypes.c_uint64)], ctypes.c_int),
+    "tn_count": ([ctypes.c_void_p, ctypes.c_void_p, _P(ContractOpts_c), _P(ctypes.c_uint32), ctypes.c_size_t,
+                  _P(ctypes.c_size_t)], ctypes.c_int),
+    "tn_count_batch": ([_P(Formula_c), ctypes.c_int32, ctypes.c_int, ctypes.c_uint64, _P(ContractOpts_c),
+                        _P(ctypes.c_uint32), ctypes.c_size_t, _P(ctypes.c_size_t), _P(PlanStats_c)], ctypes.c_int),
+    "tn_primes": ([ctypes.c_int32, _P(ctypes.c_uint32)], ctypes.c_int),
+    "tn_crt": ([_P(ctypes.c_uint32), ctypes.c_int32, _P(ctypes.c_uint32), ctypes.c_size_t, _P(ctypes.c_size_t)],
+               ctypes.c_int),
+    "tn_profile_get": ([_P(KernelProfile_c)], ctypes.c_int),
+    "tn_status_str": ([ctypes.c_int], ctypes.c_char_p),
+    "tn_version": ([], ctypes.c_char_p),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libtn.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with `python -m paper_1805_00475_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (args, res) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> List[str]:
+    return list(_SIGS)
+
+
+def _check(st: int, what: str):
+    if st != TN_OK:
+        raise TNError(st, what)
+
+
+class _FormulaArrays:
+    """Keeps the ctypes arrays of one formula alive."""
+
+    def __init__(self, formula):
+        ptr, lits, kinds = formula.arrays()
+        self.ptr = (ctypes.c_int32 * len(ptr))(*ptr)
+        self.lits = (ctypes.c_int32 * max(1, len(lits)))(*lits)
+        self.kinds = (ctypes.c_uint8 * max(1, len(kinds)))(*kinds)
+        self.c = Formula_c(formula.n_vars, formula.n_clauses, self.ptr, self.lits, self.kinds)
+
+
+def _stats_dict(s: PlanStats_c) -> dict:
+    return {"n_steps": s.n_steps, "max_rank": s.max_rank, "entries": s.entries, "macs": s.macs,
+            "log2_cost": s.log2_cost, "peak_elems": int(s.peak_elems), "chosen": ORDER_NAMES.get(s.chosen, s.chosen),
+            "fallback": bool(s.fallback)}
+
+
+class Network:
+    """Handle of a built network (tn_build)."""
+
+    def __init__(self, formula):
+        lib = load()
+        self.formula = formula
+        fa = _FormulaArrays(formula)
+        h = ctypes.c_void_p()
+        _check(lib.tn_build(ctypes.byref(fa.c), ctypes.byref(h)), "tn_build")
+        self.h = h
+
+    def info(self):
+        nt, nb = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().tn_network_info(self.h, ctypes.byref(nt), ctypes.byref(nb)), "tn_network_info")
+        return nt.value, nb.value
+
+    def order(self, kind: str = "greedy", seed: int = 0, model=None) -> "Plan":
+        return Plan(self, kind, seed, model)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.tn_network_free(self.h)
+            self.h = None
+
+
+class Plan:
+    """Handle of an order + plan (tn_order)."""
+
+    def __init__(self, net: Network, kind: str, seed: int, model=None):
+        lib = load()
+        self.net = net
+        h = ctypes.c_void_p()
+        st = PlanStats_c()
+        mh = model.h if model is not None else None
+        _check(lib.tn_order(net.h, ORDERS[kind], seed, mh, ctypes.byref(h), ctypes.byref(st)), "tn_order")
+        self.h = h
+        self.stats = _stats_dict(st)
+
+    def steps(self):
+        n = ctypes.c_int32()
+        _check(load().tn_plan_steps(self.h, None, 0, ctypes.byref(n)), "tn_plan_steps")
+        buf = (ctypes.c_int32 * max(2, 2 * n.value))()
+        _check(load().tn_plan_steps(self.h, buf, n.value, ctypes.byref(n)), "tn_plan_steps")
+        return [(buf[2 * k], buf[2 * k + 1]) for k in range(n.value)]
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.tn_plan_free(self.h)
+            self.h = None
+
+
+# ------------------------------------------------------------ device memory
+class Workspace:
+    """Device memory for the library, taken from PyTorch's allocator."""
+
+    def __init__(self, device: str = "cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the contraction path runs only on the GPU")
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=self.device)
+        return self.buf.data_ptr(), self.buf.numel()
+
+    def release(self):
+        self.buf = None
+
+
+_default_ws: Optional[Workspace] = None
+
+
+def default_workspace() -> Workspace:
+    global _default_ws
+    if _default_ws is None:
+        _default_ws = Workspace()
+    return _default_ws
+
+
+def current_stream_handle():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _opts(arith="auto", n_primes=0, ptr=None, nbytes=0, stream=None, prime_group=0, flags=0):
+    return ContractOpts_c(ARITH[arith], n_primes, ptr, nbytes, stream, prime_group, flags)
+
+
+def workspace_bytes(net: Network, plan: Plan, arith="auto", n_primes=0, prime_group=0) -> int:
+    o = _opts(arith, n_primes, prime_group=prime_group)
+    b = ctypes.c_size_t()
+    _check(load().tn_workspace_bytes(net.h, plan.h, ctypes.byref(o), ctypes.byref(b)), "tn_workspace_bytes")
+    return b.value
+
+
+def _limbs_to_int(buf, n) -> int:
+    v = 0
+    for i in reversed(range(n)):
+        v = (v << 32) | buf[i]
+    return v
+
+
+def contract(net: Network, plan: Plan, arith="auto", n_primes=0, workspace: Workspace = None,
+             max_bytes: int = 0, prime_group=0, flags=0):
+    """Run a plan; returns the residues list (RNS) or the exact int (U64)."""
+    lib = load()
+    ws = workspace or default_workspace()
+    need = workspace_bytes(net, plan, arith, n_primes, prime_group)
+    ptr, nb = ws.get(max(need, max_bytes))
+    o = _opts(arith, n_primes, ptr, nb, current_stream_handle(), prime_group, flags)
+    res = (ctypes.c_uint32 * MAX_PRIMES)()
+    u = ctypes.c_uint64()
+    _check(lib.tn_contract(net.h, plan.h, ctypes.byref(o), res, MAX_PRIMES, ctypes.byref(u)), "tn_contract")
+    n_vars = net.formula.n_vars
+    if arith == "u64" or (arith == "auto" and n_vars <= 63):
+        return int(u.value)
+    k = n_primes if n_primes > 0 else (n_vars + 30) // 31 + 1
+    return [int(res[i]) for i in range(k)]
+
+
+def count_plan(net: Network, plan: Plan, arith="auto", n_primes=0, workspace: Workspace = None,
+               max_bytes: int = 0, prime_group=0, flags=0) -> int:
+    """Exact count (tn_count) of a built network under a plan."""
+    lib = load()
+    ws = workspace or default_workspace()
+    need = workspace_bytes(net, plan, arith, n_primes, prime_group)
+    ptr, nb = ws.get(max(need, max_bytes))
+    o = _opts(arith, n_primes, ptr, nb, current_stream_handle(), prime_group, flags)
+    cap = 80
+    limbs = (ctypes.c_uint32 * cap)()
+    n = ctypes.c_size_t()
+    _check(lib.tn_count(net.h, plan.h, ctypes.byref(o), limbs, cap, ctypes.byref(n)), "tn_count")
+    return _limbs_to_int(limbs, n.value)
+
+
+def count(formula, order: str = "greedy", seed: int = 0, arith="auto", n_primes=0, flags=0,
+          workspace: Workspace = None) -> int:
+    """Build, order, contract and recombine one formula."""
+    net = Network(formula)
+    plan = net.order(order, seed)
+    return count_plan(net, plan, arith, n_primes, workspace, flags=flags)
+
+
+def count_batch(formulas: Sequence, order: str = "greedy", seed: int = 0, arith="auto", n_primes=0, flags=0,
+                workspace_bytes_: int = 8 << 30, workspace: Workspace = None, with_stats: bool = False):
+    """Batched counting (tn_count_batch) of many formulas."""
+    lib = load()
+    n = len(formulas)
+    arrs = [_FormulaArrays(f) for f in formulas]
+    fs = (Formula_c * max(1, n))(*[a.c for a in arrs])
+    ws = workspace or default_workspace()
+    ptr, nb = ws.get(workspace_bytes_)
+    o = _opts(arith, n_primes, ptr, nb, current_stream_handle(), 0, flags)
+    cap = 80
+    limbs = (ctypes.c_uint32 * (cap * max(1, n)))()
+    nl = (ctypes.c_size_t * max(1, n))()
+    stats = (PlanStats_c * max(1, n))()
+    _check(lib.tn_count_batch(fs, n, ORDERS[order], seed, ctypes.byref(o), limbs, cap, nl, stats),
+           "tn_count_batch")
+    out = [_limbs_to_int(limbs[i * cap:(i + 1) * cap], nl[i]) for i in range(n)]
+    if with_stats:
+        return out, [_stats_dict(stats[i]) for i in range(n)]
+    return out
+
+
+def primes(k: int) -> List[int]:
+    buf = (ctypes.c_uint32 * max(1, k))()
+    _check(load().tn_primes(k, buf), "tn_primes")
+    return [int(buf[i]) for i in range(k)]
+
+
+def crt(residues: Sequence[int]) -> int:
+    k = len(residues)
+    r = (ctypes.c_uint32 * k)(*residues)
+    cap = 80
+    limbs = (ctypes.c_uint32 * cap)()
+    n = ctypes.c_size_t()
+    _check(load().tn_crt(r, k, limbs, cap, ctypes.byref(n)), "tn_crt")
+    return _limbs_to_int(limbs, n.value)
+
+
+def profile() -> dict:
+    buf = (KernelProfile_c * len(KERNEL_CLASSES))()
+    _check(load().tn_profile_get(buf), "tn_profile_get")
+    return {name: {"launches": buf[i].launches, "ms": buf[i].ms, "bytes": buf[i].bytes, "macs": buf[i].macs}
+            for i, name in enumerate(KERNEL_CLASSES)}
+
+
+def version() -> str:
+    return load().tn_version().decode()

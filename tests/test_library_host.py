@@ -1,0 +1,179 @@
+"""Host-side checks of libtn (no GPU): exported symbols, input validation,
+orders and their predicted cost against the oracle's independent replay,
+prime table and CRT against the oracle."""
+import os
+import random
+import re
+
+import pytest
+
+import instances as I
+from oracle import cost, rns, tensors
+from paper_1805_00475_amd import tn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "tn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tn_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = tn.load()
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(tn.exported_symbols())
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in tn.version()
+    lib = tn.load()
+    for s in range(-7, 1):
+        assert lib.tn_status_str(s)
+
+
+def _orders():
+    return ["greedy", "partition", "community", "best"]
+
+
+def _check_plan(f, plan):
+    nets, _ = tensors.network_of_formula(f)
+    labels = [ls for _, ls in nets]
+    steps = plan.steps()
+    # each tensor consumed once, N-1 merges, closed network ends as a scalar
+    n0 = len(labels)
+    used = set()
+    for k, (a, b) in enumerate(steps):
+        assert 0 <= a < n0 + k and 0 <= b < n0 + k and a != b
+        assert a not in used and b not in used
+        used.update((a, b))
+    if n0:
+        assert len(steps) == n0 - 1
+    rep = cost.replay(labels, steps)
+    st = plan.stats
+    assert rep["max_rank"] == st["max_rank"]
+    assert rep["entries"] == pytest.approx(st["entries"], rel=1e-12)
+    assert rep["macs"] == pytest.approx(st["macs"], rel=1e-12)
+    if n0:
+        assert rep["remaining"] == [[]]
+    return rep
+
+
+def test_orders_valid_on_workloads():
+    fs = [I.small_1in3(i) for i in range(5)] + [I.cvc(60, i) for i in range(3)] + [I.batch_instance(i) for i in range(6)]
+    fs += [I.vertex_cover_formula(I.prism_graph(30)), I.perfect_matching_formula(I.prism_graph(20))]
+    for f in fs:
+        net = tn.Network(f)
+        for k in _orders():
+            _check_plan(f, net.order(k, seed=3))
+
+
+def test_orders_valid_on_random_mixed_formulas():
+    rng = I.Rng(11)
+    for _ in range(60):
+        n = rng.uniform_int(0, 14)
+        f = I.random_mixed_formula(n, rng.uniform_int(0, 16), rng) if n else I.Formula(0)
+        if max(f.occurrences(), default=0) > 12:
+            continue
+        net = tn.Network(f)
+        for k in _orders():
+            _check_plan(f, net.order(k, seed=rng.below(1000)))
+
+
+def test_greedy_picks_smallest_rank_first():
+    # the first greedy merge has the smallest result rank of all connected pairs
+    f = I.cvc(60, 2)
+    nets, _ = tensors.network_of_formula(f)
+    labels = [set(ls) for _, ls in nets]
+    a, b = tn.Network(f).order("greedy").steps()[0]
+    best = min(len(labels[i] ^ labels[j]) for i in range(len(labels)) for j in range(i + 1, len(labels))
+               if labels[i] & labels[j])
+    assert len(labels[a] ^ labels[b]) == best
+
+
+def test_hierarchical_orders_beat_greedy_on_cubic_graphs():
+    # Sec. 3.2: partition and community orders keep the rank lower than greedy
+    worse = 0
+    for s in range(4):
+        net = tn.Network(I.cvc(120, s))
+        g = net.order("greedy").stats["max_rank"]
+        c = net.order("community").stats["max_rank"]
+        p = net.order("partition", seed=s).stats["max_rank"]
+        worse += (min(c, p) > g)
+    assert worse == 0
+
+
+def test_best_is_cheapest():
+    net = tn.Network(I.cvc(120, 1))
+    costs = {k: net.order(k, seed=0).stats["log2_cost"] for k in ("greedy", "partition", "community")}
+    assert net.order("best", seed=0).stats["log2_cost"] == pytest.approx(min(costs.values()))
+
+
+def test_rank_cap_reported():
+    # greedy on a 200-vertex cubic graph exceeds the kernel rank cap
+    with pytest.raises(tn.TNError) as e:
+        tn.Network(I.cvc(200, 0)).order("greedy")
+    assert e.value.status == -5
+
+
+@pytest.mark.parametrize("clauses,n", [
+    ([(0, [0])], 3),            # literal 0
+    ([(0, [4])], 3),            # variable out of range
+    ([(0, [-4])], 3),
+    ([(2, [1])], 3),            # unknown clause kind
+])
+def test_build_rejects_malformed(clauses, n):
+    with pytest.raises(tn.TNError) as e:
+        tn.Network(I.Formula(n, clauses))
+    assert e.value.status == -1
+
+
+def test_build_rejects_oversized_tensors():
+    with pytest.raises(tn.TNError) as e:
+        tn.Network(I.Formula(30, [(0, list(range(1, 26)))]))
+    assert e.value.status == -5
+    with pytest.raises(tn.TNError) as e:
+        tn.Network(I.Formula(2, [(0, [1, 2]) for _ in range(25)]))
+    assert e.value.status == -5
+
+
+def test_network_info():
+    f = I.cvc(60, 0)
+    assert tn.Network(f).info() == (60 + 90, 180)
+
+
+def test_prime_table_matches_oracle():
+    assert tn.primes(40) == rns.largest_primes_below(1 << 31, 40)
+    with pytest.raises(tn.TNError):
+        tn.primes(tn.MAX_PRIMES + 1)
+
+
+def test_crt_matches_oracle():
+    r = random.Random(3)
+    for k in (1, 2, 3, 5, 8, 11, 20):
+        ps = rns.largest_primes_below(1 << 31, k)
+        M = 1
+        for p in ps:
+            M *= p
+        for _ in range(30):
+            x = r.randrange(M)
+            assert tn.crt([x % p for p in ps]) == x == rns.crt([x % p for p in ps], ps)
+
+
+def test_crt_rejects_unreduced_residue():
+    with pytest.raises(tn.TNError):
+        tn.crt([2 ** 31 - 1])
+
+
+def test_workspace_query_scales_with_prime_group():
+    f = I.cvc(120, 0)
+    net = tn.Network(f)
+    plan = net.order("community")
+    one = tn.workspace_bytes(net, plan, "rns", 5, 1)
+    five = tn.workspace_bytes(net, plan, "rns", 5, 5)
+    assert five > one
+    assert one >= plan.stats["peak_elems"] * 4 * 0.5
