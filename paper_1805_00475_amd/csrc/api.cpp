@@ -6,6 +6,56 @@
 
 #include "internal.hpp"
 
+namespace tn {
+
+tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out) {
+    try {
+        auto plan_of = [&](int32_t k, Plan& p) -> tn_status {
+            switch (k) {
+                case TN_ORDER_GREEDY: return make_plan(N, order_greedy(N), k, p);
+                case TN_ORDER_PARTITION: return make_plan(N, order_partition(N, seed), k, p);
+                case TN_ORDER_COMMUNITY: return make_plan(N, order_community(N), k, p);
+                default: return TN_EINVAL;
+            }
+        };
+        if (kind == TN_ORDER_GREEDY || kind == TN_ORDER_PARTITION || kind == TN_ORDER_COMMUNITY)
+            return plan_of(kind, out);
+        if (kind != TN_ORDER_BEST && kind != TN_ORDER_LEARNED) return TN_EINVAL;
+        // the judge: the cheapest plan under the cost model (Sec. 4, lazy
+        // evaluation); plans whose ranks exceed the cap are excluded
+        bool have = false;
+        tn_status last = TN_ERANK;
+        for (int32_t k : {TN_ORDER_GREEDY, TN_ORDER_PARTITION, TN_ORDER_COMMUNITY}) {
+            Plan p;
+            tn_status s2 = plan_of(k, p);
+            if (s2 != TN_OK) {
+                last = s2;
+                continue;
+            }
+            if (!have || plan_cost(p) < plan_cost(out)) {
+                out = std::move(p);
+                have = true;
+            }
+        }
+        if (kind == TN_ORDER_LEARNED) {
+            bool ok = false;
+            auto lm = order_learned(N, model, &ok);
+            Plan p;
+            if (ok && make_plan(N, lm, TN_ORDER_LEARNED, p) == TN_OK && (!have || plan_cost(p) <= plan_cost(out))) {
+                out = std::move(p);
+                have = true;
+            } else if (have) {
+                out.stats.fallback = 1;
+            }
+        }
+        return have ? TN_OK : last;
+    } catch (const std::bad_alloc&) {
+        return TN_ENOMEM;
+    }
+}
+
+}  // namespace tn
+
 using namespace tn;
 
 extern "C" {
@@ -39,55 +89,7 @@ tn_status tn_order(const tn_network* net, tn_order_kind kind, uint64_t seed, con
     *out = nullptr;
     tn_plan* h = new (std::nothrow) tn_plan;
     if (!h) return TN_ENOMEM;
-    tn_status st = TN_OK;
-    try {
-        const Network& N = net->net;
-        auto plan_of = [&](int32_t k, Plan& p) -> tn_status {
-            switch (k) {
-                case TN_ORDER_GREEDY: return make_plan(N, order_greedy(N), k, p);
-                case TN_ORDER_PARTITION: return make_plan(N, order_partition(N, seed), k, p);
-                case TN_ORDER_COMMUNITY: return make_plan(N, order_community(N), k, p);
-                default: return TN_EINVAL;
-            }
-        };
-        if (kind == TN_ORDER_GREEDY || kind == TN_ORDER_PARTITION || kind == TN_ORDER_COMMUNITY) {
-            st = plan_of(kind, h->plan);
-        } else if (kind == TN_ORDER_BEST || kind == TN_ORDER_LEARNED) {
-            // the judge: the cheapest plan under the cost model (Sec. 4,
-            // lazy evaluation), plans whose ranks exceed the cap excluded
-            bool have = false;
-            tn_status last = TN_ERANK;
-            for (int32_t k : {TN_ORDER_GREEDY, TN_ORDER_PARTITION, TN_ORDER_COMMUNITY}) {
-                Plan p;
-                tn_status s2 = plan_of(k, p);
-                if (s2 != TN_OK) {
-                    last = s2;
-                    continue;
-                }
-                if (!have || plan_cost(p) < plan_cost(h->plan)) {
-                    h->plan = std::move(p);
-                    have = true;
-                }
-            }
-            if (kind == TN_ORDER_LEARNED) {
-                bool ok = false;
-                auto lm = order_learned(N, model, &ok);
-                Plan p;
-                if (ok && make_plan(N, lm, TN_ORDER_LEARNED, p) == TN_OK &&
-                    (!have || plan_cost(p) <= plan_cost(h->plan))) {
-                    h->plan = std::move(p);
-                    have = true;
-                } else if (have) {
-                    h->plan.stats.fallback = 1;
-                }
-            }
-            st = have ? TN_OK : last;
-        } else {
-            st = TN_EINVAL;
-        }
-    } catch (const std::bad_alloc&) {
-        st = TN_ENOMEM;
-    }
+    tn_status st = make_order(net->net, kind, seed, model, h->plan);
     if (st != TN_OK) {
         delete h;
         return st;

@@ -274,11 +274,7 @@ uint64_t init_entry(const InitTensor& t, const std::vector<int32_t>& pos, uint64
     return ntrue == 1 ? 1 : 0;
 }
 
-struct Resolved {
-    bool u64 = false;
-    int32_t k = 0;  // primes
-    std::vector<uint32_t> primes;
-};
+}  // namespace
 
 tn_status resolve(const Plan& plan, const tn_contract_opts* o, Resolved& r) {
     int32_t arith = o ? o->arith : TN_ARITH_AUTO;
@@ -297,6 +293,8 @@ tn_status resolve(const Plan& plan, const tn_contract_opts* o, Resolved& r) {
     r.primes.assign(P.begin(), P.begin() + r.k);
     return TN_OK;
 }
+
+namespace {
 
 int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 

@@ -89,6 +89,19 @@ tn_status make_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>>
                     int32_t chosen, Plan& plan);
 double plan_cost(const Plan& plan);
 
+// api.cpp: order of any kind (with the judge for BEST / LEARNED) + plan
+tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out);
+
+// contract.hip
+struct Resolved {
+    bool u64 = false;
+    int32_t k = 0;  // primes
+    std::vector<uint32_t> primes;
+};
+tn_status resolve(const Plan& plan, const tn_contract_opts* o, Resolved& r);
+tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts* o, const Resolved& R,
+                   std::vector<uint32_t>& residues, uint64_t* u64v);
+
 // crt.cpp
 const std::vector<uint32_t>& prime_table(int32_t k);
 void crt_limbs(const uint32_t* residues, int32_t k, std::vector<uint32_t>& limbs);
