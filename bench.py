@@ -93,19 +93,24 @@ def main():
     formulas = [I.cvc(args.n, s) for s in range(args.batch)]
     k_primes = (args.n + 30) // 31 + 1
     ws = tn.default_workspace()
-    ws.get(8 << 30)
+    ws.get(64 << 30)
 
     def one_pass(flags=0):
         if args.single:
             return [tn.count(f, args.order, seed=i, flags=flags, workspace=ws) for i, f in enumerate(formulas)]
         return tn.count_batch(formulas, args.order, seed=0, flags=flags, workspace=ws, with_stats=False)
 
+    def log(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
     for _ in range(args.warmup):
         ref = one_pass()
+        log("warmup pass done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         got = one_pass()
+        log(f"timed step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     if args.warmup and got != ref:
@@ -116,6 +121,7 @@ def main():
     # roofline: one more identical pass with per-launch hipEvents
     one_pass(tn.FLAG_TIMING)
     prof = tn.profile()
+    log("timing pass done")
     dom = max(prof, key=lambda k: prof[k]["ms"])
     d = prof[dom]
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
@@ -147,6 +153,7 @@ def main():
     if not args.no_cpu_baseline:
         p0 = plans[0]
         out["cpu_baseline"] = cpu_baseline(formulas[0], p0.steps(), k_primes, args.cpu_seconds)
+        log("cpu baseline done")
     print(json.dumps(out))
 
 

@@ -8,6 +8,9 @@
 
 namespace tn {
 
+// randomized bisection trials tried by the judge
+constexpr int kPartitionTrials = 16;
+
 tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out) {
     try {
         auto plan_of = [&](int32_t k, Plan& p) -> tn_status {
@@ -25,17 +28,28 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         // evaluation); plans whose ranks exceed the cap are excluded
         bool have = false;
         tn_status last = TN_ERANK;
-        for (int32_t k : {TN_ORDER_GREEDY, TN_ORDER_PARTITION, TN_ORDER_COMMUNITY}) {
-            Plan p;
-            tn_status s2 = plan_of(k, p);
+        // candidates: greedy, community, and kPartitionTrials randomized
+        // recursive bisections (each itself best-of-2 per level)
+        auto consider = [&](tn_status s2, Plan& p) {
             if (s2 != TN_OK) {
                 last = s2;
-                continue;
+                return;
             }
             if (!have || plan_cost(p) < plan_cost(out)) {
                 out = std::move(p);
                 have = true;
             }
+        };
+        for (int32_t k : {TN_ORDER_GREEDY, TN_ORDER_COMMUNITY}) {
+            Plan p;
+            tn_status s2 = plan_of(k, p);
+            consider(s2, p);
+        }
+        for (int t = 0; t < kPartitionTrials; ++t) {
+            Plan p;
+            tn_status s2 = make_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t)),
+                                     TN_ORDER_PARTITION, p);
+            consider(s2, p);
         }
         if (kind == TN_ORDER_LEARNED) {
             bool ok = false;

@@ -277,7 +277,7 @@ def count(formula, order: str = "greedy", seed: int = 0, arith="auto", n_primes=
 
 
 def count_batch(formulas: Sequence, order: str = "greedy", seed: int = 0, arith="auto", n_primes=0, flags=0,
-                workspace_bytes_: int = 8 << 30, workspace: Workspace = None, with_stats: bool = False):
+                workspace_bytes_: int = 64 << 30, workspace: Workspace = None, with_stats: bool = False):
     """Batched counting (tn_count_batch) of many formulas."""
     lib = load()
     n = len(formulas)
