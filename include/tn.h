@@ -182,6 +182,20 @@ typedef struct {
 } tn_kernel_profile;
 tn_status tn_profile_get(tn_kernel_profile* out /* TN_KERNEL_CLASSES entries */);
 
+/* One contraction step from host buffers (test and measurement hook):
+ *     C[c] = sum over z < 2^s of A[z + 2^s xA] * B[z + 2^s xB]
+ * where xA gathers the bits of c selected by maskA and xB the remaining bits
+ * of c below 2^(rA + rB - 2s) (the shared bonds are the low s bits of both
+ * operands, Sec. 2.1 / Eq. 5 form). Entries are uint32 residues modulo
+ * ``prime`` (arith TN_ARITH_RNS; prime in (2^30, 2^31) with 2^32 mod prime
+ * below 2^12) or uint64 wrapping (TN_ARITH_U64). ``kernel`` forces a
+ * tn_kernel_class (-1 = the library's choice); TN_EUNSUPPORTED if that kernel
+ * cannot run this shape. The workspace (device) must hold the three tensors,
+ * each rounded up to 256 bytes; A and B may be overwritten on the device. */
+tn_status tn_step(const void* A, int32_t rA, const void* B, int32_t rB, int32_t s, uint64_t maskA,
+                  int32_t arith, uint32_t prime, int32_t kernel, void* C, void* workspace,
+                  size_t workspace_bytes, void* stream);
+
 /* -------------------------------------------------------------- utilities */
 /* The k largest primes below 2^31, descending, as used by the RNS path. */
 tn_status tn_primes(int32_t k, uint32_t* out);

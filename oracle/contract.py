@@ -168,3 +168,33 @@ def max_rank_of_order(label_sets, order) -> int:
         mr = max(mr, len(live[nid]))
         nid += 1
     return mr
+
+
+def step_entries(A, B, s: int, maskA: int, rC: int, cs, p: Optional[int] = None) -> List[int]:
+    """Entries of one contraction step written out from its definition.
+
+    Flat storage: entry index x of a tensor holds bit k of x for its k-th
+    bond. A and B hold their s shared bonds as their low s bits, in the same
+    order; output bit j of C comes from A's free bits when bit j of maskA is
+    set and from B's free bits otherwise, each in increasing order. Then
+        C[c] = sum over z < 2^s of A[z + 2^s xA] * B[z + 2^s xB]
+    (Eq. 5 form, all shared bonds summed at once), in exact integers, reduced
+    mod p when p is given, else mod 2^64 (the wrapping 64-bit mode).
+    """
+    out = []
+    for c in cs:
+        xa = xb = 0
+        ka = kb = 0
+        for j in range(rC):
+            bit = (c >> j) & 1
+            if (maskA >> j) & 1:
+                xa |= bit << ka
+                ka += 1
+            else:
+                xb |= bit << kb
+                kb += 1
+        acc = 0
+        for z in range(1 << s):
+            acc += int(A[z + (xa << s)]) * int(B[z + (xb << s)])
+        out.append(acc % p if p is not None else acc % (1 << 64))
+    return out

@@ -16,6 +16,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "mfma.hpp"
 #include "profile.hpp"
 
 namespace tn {
@@ -199,7 +200,7 @@ inline uint32_t cap32(uint64_t x, uint32_t hi) { return uint32_t(std::min<uint64
 
 // Choose and launch the kernel of one step for a group of G primes.
 hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* primes, int G, char* init_base,
-                       char* arena_base, int64_t arena_elems, hipStream_t stream, KernelClass* kc) {
+                       char* arena_base, int64_t arena_elems, hipStream_t stream, KernelClass* kc, int force = -1) {
     const size_t es = u64 ? 8 : 4;
     Step st = st0;
     StepArgs a{};
@@ -229,7 +230,16 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
     }
     const bool generic_only = flags & TN_FLAG_GENERIC_ONLY;
     const uint64_t total = uint64_t(1) << a.rC;
-    if (!generic_only && a.s <= 5 && a.fA >= 8) {
+    const bool can_mfma = !u64 && !st.initA && !st.initB && mfma_eligible(a);
+    const bool can_stream = a.s <= 5 && a.fA >= 8;
+    if (force == KC_MFMA && !can_mfma) return hipErrorInvalidValue;
+    if (force == KC_STREAM && !can_stream) return hipErrorInvalidValue;
+    if (force == KC_ROWDOT && a.rC > 40) return hipErrorInvalidValue;
+    if ((force == KC_MFMA) || (force < 0 && !generic_only && can_mfma && !(flags & TN_FLAG_NO_MFMA))) {
+        *kc = KC_MFMA;
+        return launch_mfma(a, G, stream);
+    }
+    if (force == KC_STREAM || (force < 0 && !generic_only && can_stream)) {
         const int nb = std::min(a.fB, 4);
         const uint64_t n_iter = (uint64_t(1) << a.fA) >> 8;
         const uint64_t n_chunk = (uint64_t(1) << a.fB) >> nb;
@@ -238,7 +248,7 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
         return u64 ? launch_stream<true>(a.s, 1 << nb, grid, stream, a)
                    : launch_stream<false>(a.s, 1 << nb, grid, stream, a);
     }
-    if (!generic_only && a.s >= 6) {
+    if (force == KC_ROWDOT || (force < 0 && !generic_only && a.s >= 6)) {
         dim3 grid(cap32((total + 3) / 4, 1u << 20), 1, G);
         *kc = KC_ROWDOT;
         if (u64)
@@ -458,6 +468,56 @@ tn_status tn_count(const tn_network* net, const tn_plan* plan, const tn_contract
 }
 
 }  // extern "C"
+
+extern "C" tn_status tn_step(const void* A, int32_t rA, const void* B, int32_t rB, int32_t s, uint64_t maskA,
+                             int32_t arith, uint32_t prime, int32_t kernel, void* C, void* workspace,
+                             size_t workspace_bytes, void* stream_) {
+    if (!A || !B || !C || !workspace) return TN_EINVAL;
+    if (rA < 0 || rB < 0 || s < 0 || s > rA || s > rB) return TN_EINVAL;
+    const int32_t rC = rA + rB - 2 * s;
+    if (rA > TN_MAX_RANK || rB > TN_MAX_RANK || rC > TN_MAX_RANK) return TN_ERANK;
+    const uint64_t cmask = (uint64_t(1) << rC) - 1;
+    if ((maskA & ~cmask) || __builtin_popcountll(maskA) != rA - s) return TN_EINVAL;
+    const bool u64 = arith == TN_ARITH_U64;
+    if (!u64 && (arith != TN_ARITH_RNS || prime < (1u << 30) || prime >= (1u << 31) ||
+                 ((uint64_t(1) << 32) % prime) >= (1u << 12)))
+        return TN_EINVAL;
+    if (kernel < -1 || kernel > KC_MFMA) return TN_EINVAL;
+    const int64_t es = u64 ? 8 : 4;
+    const int64_t nA = align256((int64_t(1) << rA) * es), nB = align256((int64_t(1) << rB) * es),
+                  nC = align256((int64_t(1) << rC) * es);
+    if (nA + nB + nC > int64_t(workspace_bytes)) return TN_ETOOBIG;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    char* base = static_cast<char*>(workspace);
+    Step st;
+    st.rA = rA;
+    st.rB = rB;
+    st.s = s;
+    st.rC = rC;
+    st.maskA = maskA;
+    st.initA = st.initB = false;
+    st.offA = 0;
+    st.offB = nA / es;
+    st.offC = (nA + nB) / es;
+    if (hipMemcpyAsync(base, A, size_t((int64_t(1) << rA) * es), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(base + nA, B, size_t((int64_t(1) << rB) * es), hipMemcpyHostToDevice, stream) != hipSuccess) {
+        (void)hipStreamSynchronize(stream);
+        return TN_EHIP;
+    }
+    KernelClass kc = KC_GENERIC;
+    hipError_t e = launch_step(st, u64, 0, u64 ? nullptr : &prime, 1, base, base, 0, stream, &kc, kernel);
+    if (e == hipErrorInvalidValue) {
+        (void)hipStreamSynchronize(stream);
+        return TN_EUNSUPPORTED;
+    }
+    if (e != hipSuccess ||
+        hipMemcpyAsync(C, base + nA + nB, size_t((int64_t(1) << rC) * es), hipMemcpyDeviceToHost, stream) !=
+            hipSuccess) {
+        (void)hipStreamSynchronize(stream);
+        return TN_EHIP;
+    }
+    return hipStreamSynchronize(stream) == hipSuccess ? TN_OK : TN_EHIP;
+}
 
 namespace tn {
 Profiler& profiler() {

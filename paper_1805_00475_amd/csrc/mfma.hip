@@ -1,0 +1,227 @@
+// Dense contraction steps on the matrix cores, exactly.
+//
+// A step whose shared dimension K = 2^s is wide and whose two free sides are
+// large is a plain matrix product C = A B^T over residues modulo p < 2^31
+// (rows of A and B are contiguous along the shared bonds in the plan's
+// layout). Each residue r is centred to r' in (-p/2, p/2] and written as four
+// signed base-256 digits r' = d0 + d1 2^8 + d2 2^16 + d3 2^24 with d0..d2 in
+// [-128, 127] and |d3| <= 64. Then
+//     C = sum over t = 0..6 of 2^(8t) T_t,   T_t = sum_{i+j=t} A_i B_j^T,
+// where A_i, B_j are int8 digit matrices; every T_t is accumulated by the
+// int8 MFMA into int32 registers. Each product of digits is at most 2^14 in
+// magnitude, at most four digit pairs share a shift, so K <= 2^14 keeps every
+// T_t below 2^30 -- exact. The epilogue forms
+//     X = (T0 + T1 2^8 + T2 2^16 + T3 2^24) + (T4 + T5 2^8 + T6 2^16) (2^32 mod p)
+// in 64-bit integers (|X| < 2^59), adds a multiple of p above 2^59, and
+// reduces with the folding reduction of the other kernels.
+//
+// Two kernels per step: k_digits rewrites A and B in place (they die at this
+// step) so that every 64-entry chunk of a row holds its four digit planes of
+// 64 bytes each; k_mfma then copies digit tiles into LDS and runs
+// v_mfma_i32_16x16x64_i8. Output tiles are staged in LDS and written in
+// C-address order so stores stay coalesced for any bit interleaving.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+#include "mfma.hpp"
+
+namespace tn {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------- digit pass
+// In place: the 16 lanes owning one 64-entry chunk read it (4 entries each)
+// before any of them writes, since they are consecutive lanes of one wave
+// and every store depends on all four loads of that lane.
+__global__ __launch_bounds__(256) void k_digits(uint32_t* X, int64_t stride, uint64_t n_vec4,
+                                                StepArgs a) {
+    const uint32_t p = a.p[blockIdx.z];
+    uint32_t* base = X + blockIdx.z * stride;
+    const uint32_t half = p >> 1;
+    for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n_vec4;
+         v += uint64_t(gridDim.x) * blockDim.x) {
+        uint4 r = reinterpret_cast<const uint4*>(base)[v];
+        uint32_t rv[4] = {r.x, r.y, r.z, r.w};
+        uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int32_t c = rv[e] > half ? int32_t(rv[e] - p) : int32_t(rv[e]);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                int32_t dig = d < 3 ? int32_t(int8_t(c & 0xff)) : c;
+                w[d] |= (uint32_t(dig) & 0xffu) << (8 * e);
+                c = (c - dig) >> 8;
+            }
+        }
+        // chunk = 16 vec4 of 64 entries; plane d of the chunk at byte 64 d
+        const uint64_t chunk = v >> 4;
+        const uint32_t lane16 = uint32_t(v & 15);
+        uint32_t* cbase = base + chunk * 64;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) cbase[d * 16 + lane16] = w[d];
+    }
+}
+
+// --------------------------------------------------------------- GEMM
+constexpr int kBM = 128, kBN = 64, kRowB = 256 + 16;  // LDS row stride (bytes)
+
+__device__ __forceinline__ uint32_t combine_digits(const int32_t T[7], uint32_t p, uint32_t r, uint64_t off) {
+    const int64_t lo = int64_t(T[0]) + (int64_t(T[1]) << 8) + (int64_t(T[2]) << 16) + (int64_t(T[3]) << 24);
+    const int64_t hi = int64_t(T[4]) + (int64_t(T[5]) << 8) + (int64_t(T[6]) << 16);
+    const uint64_t y = uint64_t(lo + hi * int64_t(r)) + off;
+    const ModP m{p, r};
+    return m.finish(y);
+}
+
+__global__ __launch_bounds__(256, 1) void k_mfma(StepArgs a, MfmaExtra ex) {
+    __shared__ __align__(16) uint8_t lds[kBM * kRowB + kBN * kRowB];
+    __shared__ uint64_t hiOff[32];
+    __shared__ uint32_t hiIJ[32][2];
+    uint8_t* sA = lds;
+    uint8_t* sB = lds + kBM * kRowB;
+    uint32_t* sOut = reinterpret_cast<uint32_t*>(lds);  // kBM x kBN after the K loop
+
+    const int g = blockIdx.z;
+    const uint8_t* A = reinterpret_cast<const uint8_t*>(static_cast<const uint32_t*>(a.A) + g * a.strideA);
+    const uint8_t* B = reinterpret_cast<const uint8_t*>(static_cast<const uint32_t*>(a.B) + g * a.strideB);
+    uint32_t* C = static_cast<uint32_t*>(a.C) + g * a.strideC;
+    const uint32_t p = a.p[g], r2 = a.r2[g];
+    const uint64_t off = ex.off[g];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = (w & 1) * 64, wc = (w >> 1) * 32;
+    const uint64_t rowBytes = uint64_t(4) << a.s;  // K entries of 4 bytes (4 digit planes)
+    const int nk = 1 << (a.s - 6);
+    const uint64_t tilesA = uint64_t(1) << (a.fA - 7), tilesB = uint64_t(1) << (a.fB - 6);
+    const uint64_t T = tilesA * tilesB;
+
+    // output mapping inside a tile: tile-local t = tid | q << 8 (q < 32),
+    // position pdep(t, TM), TM = the 7 lowest A bits and 6 lowest B bits of C
+    const uint64_t TM = pdep64(127, a.maskA) | pdep64(63, a.maskB);
+    const uint64_t offLow = pdep64(uint64_t(tid), TM);
+    const uint32_t iLow = uint32_t(pext64(offLow, a.maskA)), jLow = uint32_t(pext64(offLow, a.maskB));
+    if (tid < 32) {
+        const uint64_t oh = pdep64(uint64_t(tid) << 8, TM);
+        hiOff[tid] = oh;
+        hiIJ[tid][0] = uint32_t(pext64(oh, a.maskA));
+        hiIJ[tid][1] = uint32_t(pext64(oh, a.maskB));
+    }
+    __syncthreads();
+
+    for (uint64_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
+        // XCD-aware order: blocks on one XCD (blockIdx % 8) walk a contiguous
+        // band of tiles that share the same B tile
+        uint64_t tt = tile;
+        if ((T & 7) == 0) tt = (tile & 7) * (T >> 3) + (tile >> 3);
+        const uint64_t ta = tt % tilesA, tb = tt / tilesA;
+        const uint64_t xA0 = ta * kBM, xB0 = tb * kBN;
+        const uint8_t* gA = A + xA0 * rowBytes;
+        const uint8_t* gB = B + xB0 * rowBytes;
+
+        v4i acc[7][4][2];
+#pragma unroll
+        for (int t = 0; t < 7; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[t][i][j] = v4i{0, 0, 0, 0};
+
+        for (int kc = 0; kc < nk; ++kc) {
+            __syncthreads();
+            // raw copy of the digit chunks: A 128 rows x 256 B, B 64 rows x 256 B
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int idx = tid + 256 * q;
+                const int row = idx >> 4, c16 = idx & 15;
+                const uint4 v = *reinterpret_cast<const uint4*>(gA + uint64_t(row) * rowBytes + uint64_t(kc) * 256 +
+                                                                c16 * 16);
+                *reinterpret_cast<uint4*>(sA + row * kRowB + c16 * 16) = v;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int idx = tid + 256 * q;
+                const int row = idx >> 4, c16 = idx & 15;
+                const uint4 v = *reinterpret_cast<const uint4*>(gB + uint64_t(row) * rowBytes + uint64_t(kc) * 256 +
+                                                                c16 * 16);
+                *reinterpret_cast<uint4*>(sB + row * kRowB + c16 * 16) = v;
+            }
+            __syncthreads();
+            v4i fa[4][4], fb[4][2];
+            const int kg = (lane >> 4) * 16;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+                    fa[d][rb] = *reinterpret_cast<const v4i*>(sA + (wr + rb * 16 + (lane & 15)) * kRowB + d * 64 + kg);
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    fb[d][cb] = *reinterpret_cast<const v4i*>(sB + (wc + cb * 16 + (lane & 15)) * kRowB + d * 64 + kg);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb)
+                            acc[i + j][rb][cb] =
+                                __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i][rb], fb[j][cb], acc[i + j][rb][cb], 0, 0, 0);
+        }
+        __syncthreads();
+        // epilogue: lane holds rows 4 (lane / 16) + v, column lane % 16 of each 16x16 block
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int32_t Tt[7];
+#pragma unroll
+                    for (int t = 0; t < 7; ++t) Tt[t] = acc[t][rb][cb][v];
+                    const int i = wr + rb * 16 + 4 * (lane >> 4) + v;
+                    const int j = wc + cb * 16 + (lane & 15);
+                    sOut[i * kBN + j] = combine_digits(Tt, p, r2, off);
+                }
+        __syncthreads();
+        const uint64_t baseC = pdep64(xA0, a.maskA) | pdep64(xB0, a.maskB);
+        for (int q = 0; q < 32; ++q) {
+            const uint64_t o = offLow | hiOff[q];
+            const uint32_t i = iLow | hiIJ[q][0];
+            const uint32_t j = jLow | hiIJ[q][1];
+            C[baseC | o] = sOut[i * kBN + j];
+        }
+    }
+}
+
+hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream) {
+    MfmaExtra ex{};
+    for (int g = 0; g < G; ++g) {
+        const uint64_t p = a.p[g];
+        ex.off[g] = p * ((uint64_t(1) << 59) / p + 1);
+    }
+    const uint64_t nA = (uint64_t(1) << (a.fA + a.s)) / 4, nB = (uint64_t(1) << (a.fB + a.s)) / 4;
+    auto blocks = [](uint64_t n) { return dim3(uint32_t(std::min<uint64_t>((n + 255) / 256, 1u << 16)), 1, 1); };
+    dim3 gA = blocks(nA), gB = blocks(nB);
+    gA.z = gB.z = G;
+    hipLaunchKernelGGL(k_digits, gA, dim3(256), 0, stream, static_cast<uint32_t*>(const_cast<void*>(a.A)),
+                       a.strideA, nA, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_digits, gB, dim3(256), 0, stream, static_cast<uint32_t*>(const_cast<void*>(a.B)),
+                       a.strideB, nB, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint64_t T = (uint64_t(1) << (a.fA - 7)) * (uint64_t(1) << (a.fB - 6));
+    dim3 grid(uint32_t(std::min<uint64_t>(T, 2048)), 1, G);
+    hipLaunchKernelGGL(k_mfma, grid, dim3(256), 0, stream, a, ex);
+    return hipGetLastError();
+}
+
+bool mfma_eligible(const StepArgs& a) {
+    return a.s >= 6 && a.s <= 14 && a.fA >= 7 && a.fB >= 6;
+}
+
+}  // namespace tn

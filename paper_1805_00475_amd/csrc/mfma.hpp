@@ -1,0 +1,21 @@
+// Dense contraction steps on the int8 matrix cores (see mfma.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace tn {
+
+struct MfmaExtra {
+    uint64_t off[kMaxGroup];  // a multiple of p at least 2^59, per prime
+};
+
+// A step qualifies when K = 2^s is in [64, 2^14] and the free sides give at
+// least one 128 x 64 output tile. The caller must also ensure that neither
+// operand is a shared initial tensor: both are rewritten in place into digit
+// planes.
+bool mfma_eligible(const StepArgs& a);
+hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream);
+
+}  // namespace tn

@@ -82,6 +82,9 @@ _SIGS = {
     "tn_crt": ([_P(ctypes.c_uint32), ctypes.c_int32, _P(ctypes.c_uint32), ctypes.c_size_t, _P(ctypes.c_size_t)],
                ctypes.c_int),
     "tn_profile_get": ([_P(KernelProfile_c)], ctypes.c_int),
+    "tn_step": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                 ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                 ctypes.c_void_p], ctypes.c_int),
     "tn_status_str": ([ctypes.c_int], ctypes.c_char_p),
     "tn_version": ([], ctypes.c_char_p),
 }
@@ -296,6 +299,28 @@ def count_batch(formulas: Sequence, order: str = "greedy", seed: int = 0, arith=
     if with_stats:
         return out, [_stats_dict(stats[i]) for i in range(n)]
     return out
+
+
+def step(A, rA: int, B, rB: int, s: int, maskA: int, prime: int = None, kernel: str = "auto",
+         workspace: Workspace = None):
+    """One contraction step on the GPU (tn_step). A, B: numpy uint32 (RNS,
+    with ``prime``) or uint64 arrays of 2^rA / 2^rB entries. Returns C."""
+    import numpy as np
+    u64 = prime is None
+    dt = np.uint64 if u64 else np.uint32
+    A = np.ascontiguousarray(A, dtype=dt)
+    B = np.ascontiguousarray(B, dtype=dt)
+    assert A.size == 1 << rA and B.size == 1 << rB
+    rC = rA + rB - 2 * s
+    C = np.empty(1 << rC, dtype=dt)
+    es = 8 if u64 else 4
+    need = sum(((x * es + 255) // 256) * 256 for x in (1 << rA, 1 << rB, 1 << rC))
+    ws = workspace or default_workspace()
+    ptr, nb = ws.get(need)
+    kc = -1 if kernel == "auto" else KERNEL_CLASSES.index(kernel)
+    _check(load().tn_step(A.ctypes.data, rA, B.ctypes.data, rB, s, maskA, ARITH["u64" if u64 else "rns"],
+                          0 if u64 else prime, kc, C.ctypes.data, ptr, nb, current_stream_handle()), "tn_step")
+    return C
 
 
 def primes(k: int) -> List[int]:

@@ -110,7 +110,8 @@ def test_hierarchical_orders_beat_greedy_on_cubic_graphs():
 def test_best_is_cheapest():
     net = tn.Network(I.cvc(120, 1))
     costs = {k: net.order(k, seed=0).stats["log2_cost"] for k in ("greedy", "partition", "community")}
-    assert net.order("best", seed=0).stats["log2_cost"] == pytest.approx(min(costs.values()))
+    # the judge also tries randomized bisections, so it can only do better
+    assert net.order("best", seed=0).stats["log2_cost"] <= min(costs.values()) + 1e-12
 
 
 def test_rank_cap_reported():

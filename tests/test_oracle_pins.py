@@ -335,3 +335,29 @@ def test_rng_bounded_draws_are_uniform_enough():
     for _ in range(60000):
         counts[rng.below(6)] += 1
     assert max(counts) - min(counts) < 600
+
+
+def test_step_definition_matches_pairwise_contraction():
+    # the entry-by-entry step definition agrees with labelled tensordot
+    rng = np.random.default_rng(1)
+    p = 2147483647
+    for rA, rB, s, maskA in ((5, 4, 2, 0b10110), (6, 6, 3, 0b100101), (4, 2, 0, 0b011110), (3, 3, 3, 0)):
+        rC = rA + rB - 2 * s
+        A = rng.integers(0, p, 1 << rA)
+        B = rng.integers(0, p, 1 << rB)
+        la = tuple(("z", k) if k < s else ("a", k - s) for k in reversed(range(rA)))
+        lb = tuple(("z", k) if k < s else ("b", k - s) for k in reversed(range(rB)))
+        Ct, lc = contract.contract_pair((A.reshape((2,) * rA).astype(np.int64), la),
+                                        (B.reshape((2,) * rB).astype(np.int64), lb), p)
+        ka = kb = 0
+        cl = []
+        for j in range(rC):
+            if (maskA >> j) & 1:
+                cl.append(("a", ka))
+                ka += 1
+            else:
+                cl.append(("b", kb))
+                kb += 1
+        Cf = np.transpose(Ct, [lc.index(l) for l in reversed(cl)]).reshape(-1) if rC else Ct.reshape(-1)
+        want = contract.step_entries(A, B, s, maskA, rC, range(1 << rC), p)
+        assert [int(x) for x in Cf] == want
