@@ -172,8 +172,10 @@ tn_status tn_count_batch(const tn_formula* fs, int32_t n, tn_order_kind kind, ui
  * (hipEvents around every launch, on the caller's stream). bytes and macs
  * are the algorithmic totals of those launches: 2^rA + 2^rB + 2^rC entries
  * of 4 or 8 bytes and 2^(rA + rB - s) multiply-adds per step and prime. */
-typedef enum { TN_KC_GENERIC = 0, TN_KC_STREAM = 1, TN_KC_ROWDOT = 2, TN_KC_MFMA = 3, TN_KC_BATCH = 4 } tn_kernel_class;
-#define TN_KERNEL_CLASSES 5
+typedef enum {
+    TN_KC_GENERIC = 0, TN_KC_STREAM = 1, TN_KC_ROWDOT = 2, TN_KC_MFMA = 3, TN_KC_BATCH = 4, TN_KC_DOT = 5
+} tn_kernel_class;
+#define TN_KERNEL_CLASSES 6
 typedef struct {
     int64_t launches;
     double ms;
@@ -191,7 +193,8 @@ tn_status tn_profile_get(tn_kernel_profile* out /* TN_KERNEL_CLASSES entries */)
  * below 2^12) or uint64 wrapping (TN_ARITH_U64). ``kernel`` forces a
  * tn_kernel_class (-1 = the library's choice); TN_EUNSUPPORTED if that kernel
  * cannot run this shape. The workspace (device) must hold the three tensors,
- * each rounded up to 256 bytes; A and B may be overwritten on the device. */
+ * each rounded up to 256 bytes, plus 512 KiB of scratch; A and B may be
+ * overwritten on the device. */
 tn_status tn_step(const void* A, int32_t rA, const void* B, int32_t rB, int32_t s, uint64_t maskA,
                   int32_t arith, uint32_t prime, int32_t kernel, void* C, void* workspace,
                   size_t workspace_bytes, void* stream);

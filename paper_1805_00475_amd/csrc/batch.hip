@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "profile.hpp"
 
 namespace tn {
 
@@ -48,6 +49,7 @@ extern "C" tn_status tn_count_batch(const tn_formula* fs, int32_t n, tn_order_ki
     } catch (const std::bad_alloc&) {
         return TN_ENOMEM;
     }
+    profiler().start(opts->flags & TN_FLAG_TIMING);
     std::mutex mu;
     std::condition_variable cv;
     std::atomic<int32_t> next{0};

@@ -168,6 +168,85 @@ __global__ __launch_bounds__(256) void k_rowdot(StepArgs a) {
     }
 }
 
+// Few outputs (2^rC <= 64), very wide K: the shared dimension is split over
+// the grid. Block b sums its K slice for every output and writes one partial
+// per output; a second kernel adds the partials of each output.
+constexpr int kDotBlocks = 1024;
+constexpr int64_t kScratchPerPrime = int64_t(kDotBlocks) * 64 * 8;
+
+template <bool U64>
+__global__ __launch_bounds__(256) void k_dot_partial(StepArgs a, uint64_t* scratch, int nblk) {
+    using T = typename std::conditional<U64, uint64_t, uint32_t>::type;
+    const void *pA, *pB;
+    void* pC;
+    load_planes<U64>(a, pA, pB, pC);
+    const T* A = static_cast<const T*>(pA);
+    const T* B = static_cast<const T*>(pB);
+    const ModP m{a.p[blockIdx.z], a.r2[blockIdx.z]};
+    __shared__ uint64_t red[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t K = uint64_t(1) << a.s;
+    const uint64_t slice = K / uint64_t(nblk);
+    const uint64_t z0 = slice * blockIdx.x;
+    const uint64_t nOut = uint64_t(1) << a.rC;
+    uint64_t* out = scratch + (uint64_t(blockIdx.z) * nblk + blockIdx.x) * 64;
+    for (uint64_t c = 0; c < nOut; ++c) {
+        const T* ra = A + (pext64(c, a.maskA) << a.s) + z0;
+        const T* rb = B + (pext64(c, a.maskB) << a.s) + z0;
+        uint64_t v;
+        if constexpr (U64) {
+            uint64_t acc = 0;
+            for (uint64_t z = threadIdx.x; z < slice; z += blockDim.x) acc += ra[z] * rb[z];
+            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+            v = acc;
+        } else {
+            uint64_t acc = 0;
+            uint32_t n3 = 0;
+            for (uint64_t z = threadIdx.x; z < slice; z += blockDim.x) {
+                acc += uint64_t(ra[z]) * rb[z];
+                if (++n3 == 3) {
+                    acc = m.fold(acc);
+                    n3 = 0;
+                }
+            }
+            uint32_t r = m.finish(acc);
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint32_t t = r + __shfl_xor(r, o);
+                r = t >= m.p ? t - m.p : t;
+            }
+            v = r;
+        }
+        if (lane == 0) red[wave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if constexpr (U64) {
+                out[c] = red[0] + red[1] + red[2] + red[3];
+            } else {
+                out[c] = (red[0] + red[1] + red[2] + red[3]) % m.p;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <bool U64>
+__global__ __launch_bounds__(64) void k_dot_final(StepArgs a, const uint64_t* scratch, int nblk) {
+    using T = typename std::conditional<U64, uint64_t, uint32_t>::type;
+    T* C = static_cast<T*>(a.C) + blockIdx.z * a.strideC;
+    const uint32_t p = a.p[blockIdx.z];
+    const uint64_t c = blockIdx.x;
+    const uint64_t* part = scratch + uint64_t(blockIdx.z) * nblk * 64;
+    uint64_t acc = 0;
+    for (int b = threadIdx.x; b < nblk; b += 64) acc += part[uint64_t(b) * 64 + c];  // < 1024 * 2^31
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (threadIdx.x == 0) {
+        if constexpr (U64)
+            C[c] = acc;
+        else
+            C[c] = T(acc % p);
+    }
+}
+
 // ----------------------------------------------------------------- launches
 
 namespace {
@@ -200,7 +279,8 @@ inline uint32_t cap32(uint64_t x, uint32_t hi) { return uint32_t(std::min<uint64
 
 // Choose and launch the kernel of one step for a group of G primes.
 hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* primes, int G, char* init_base,
-                       char* arena_base, int64_t arena_elems, hipStream_t stream, KernelClass* kc, int force = -1) {
+                       char* arena_base, int64_t arena_elems, char* scratch, hipStream_t stream, KernelClass* kc,
+                       int force = -1) {
     const size_t es = u64 ? 8 : 4;
     Step st = st0;
     StepArgs a{};
@@ -235,6 +315,22 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
     if (force == KC_MFMA && !can_mfma) return hipErrorInvalidValue;
     if (force == KC_STREAM && !can_stream) return hipErrorInvalidValue;
     if (force == KC_ROWDOT && a.rC > 40) return hipErrorInvalidValue;
+    const bool can_dot = a.rC <= 6 && a.s >= 10;
+    if (force == KC_DOT && !can_dot) return hipErrorInvalidValue;
+    if (force == KC_DOT || (force < 0 && !generic_only && can_dot)) {
+        const int nblk = int(std::min<uint64_t>(kDotBlocks, (uint64_t(1) << a.s) >> 8));
+        *kc = KC_DOT;
+        dim3 g1(nblk, 1, G), g2(uint32_t(total), 1, G);
+        uint64_t* scr = reinterpret_cast<uint64_t*>(scratch);
+        if (u64) {
+            hipLaunchKernelGGL(k_dot_partial<true>, g1, dim3(256), 0, stream, a, scr, nblk);
+            hipLaunchKernelGGL(k_dot_final<true>, g2, dim3(64), 0, stream, a, scr, nblk);
+        } else {
+            hipLaunchKernelGGL(k_dot_partial<false>, g1, dim3(256), 0, stream, a, scr, nblk);
+            hipLaunchKernelGGL(k_dot_final<false>, g2, dim3(64), 0, stream, a, scr, nblk);
+        }
+        return hipGetLastError();
+    }
     if ((force == KC_MFMA) || (force < 0 && !generic_only && can_mfma && !(flags & TN_FLAG_NO_MFMA))) {
         *kc = KC_MFMA;
         return launch_mfma(a, G, stream);
@@ -333,8 +429,8 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
     const int64_t arena_bytes = align256(plan.arena_elems * int64_t(es));
     const int64_t arena_elems = arena_bytes / int64_t(es);
     const int64_t ws = int64_t(o->workspace_bytes);
-    if (init_bytes + arena_bytes > ws) return TN_ETOOBIG;
-    int G = int((ws - init_bytes) / std::max<int64_t>(arena_bytes, 256));
+    if (init_bytes + arena_bytes + kScratchPerPrime > ws) return TN_ETOOBIG;
+    int G = int((ws - init_bytes) / (arena_bytes + kScratchPerPrime));
     G = std::min({G, R.k, kMaxGroup});
     if (o->prime_group > 0) G = std::min(G, int(o->prime_group));
     G = std::max(G, 1);
@@ -342,6 +438,7 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
     char* base = static_cast<char*>(o->workspace);
     char* init_base = base;
     char* arena_base = base + init_bytes;
+    char* scratch = arena_base + int64_t(G) * arena_bytes;
     // initial tensors in plan layout, identical for every prime (0/1/2 entries)
     std::vector<uint8_t> host(size_t(plan.init_elems) * es, 0);
     for (int32_t i = 0; i < plan.n_init; ++i) {
@@ -360,12 +457,11 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
         }
     }
     Profiler& prof = profiler();
-    prof.begin(o->flags & TN_FLAG_TIMING, stream);
     hipError_t err = hipMemcpyAsync(init_base, host.data(), host.size(), hipMemcpyHostToDevice, stream);
     // on any failure, drain the stream before the host staging buffer goes away
     auto fail = [&]() {
         (void)hipStreamSynchronize(stream);
-        prof.end();
+        prof.collect();
         return TN_EHIP;
     };
     if (err != hipSuccess) return fail();
@@ -377,7 +473,7 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
             KernelClass kc = KC_GENERIC;
             prof.before(stream);
             err = launch_step(st, R.u64, o->flags, R.u64 ? nullptr : R.primes.data() + g0, gn, init_base, arena_base,
-                              arena_elems, stream, &kc);
+                              arena_elems, scratch, stream, &kc);
             if (err != hipSuccess) return fail();
             prof.after(stream, kc, st, gn, es);
         }
@@ -389,7 +485,7 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
     }
     err = hipStreamSynchronize(stream);
     if (err != hipSuccess) return TN_EHIP;
-    prof.end();
+    prof.collect();
     if (R.u64) {
         *u64v = out[0];
     } else {
@@ -412,7 +508,8 @@ tn_status tn_workspace_bytes(const tn_network* net, const tn_plan* plan, const t
     if (st != TN_OK) return st;
     const int64_t es = R.u64 ? 8 : 4;
     int G = (opts && opts->prime_group > 0) ? std::min<int>(opts->prime_group, std::min(R.k, kMaxGroup)) : 1;
-    *bytes = size_t(align256(plan->plan.init_elems * es) + int64_t(G) * align256(plan->plan.arena_elems * es));
+    *bytes = size_t(align256(plan->plan.init_elems * es) +
+                    int64_t(G) * (align256(plan->plan.arena_elems * es) + kScratchPerPrime));
     return TN_OK;
 }
 
@@ -426,6 +523,7 @@ tn_status tn_contract(const tn_network* net, const tn_plan* plan, const tn_contr
     if (!R.u64 && residues && residues_cap < R.k) return TN_EBUFSIZE;
     std::vector<uint32_t> res;
     uint64_t v = 0;
+    profiler().start(opts && (opts->flags & TN_FLAG_TIMING));
     try {
         st = run_plan(net->net, plan->plan, opts, R, res, &v);
     } catch (const std::bad_alloc&) {
@@ -449,6 +547,7 @@ tn_status tn_count(const tn_network* net, const tn_plan* plan, const tn_contract
     if (st != TN_OK) return st;
     std::vector<uint32_t> res, L;
     uint64_t v = 0;
+    profiler().start(opts && (opts->flags & TN_FLAG_TIMING));
     try {
         st = run_plan(net->net, plan->plan, opts, R, res, &v);
         if (st != TN_OK) return st;
@@ -482,11 +581,11 @@ extern "C" tn_status tn_step(const void* A, int32_t rA, const void* B, int32_t r
     if (!u64 && (arith != TN_ARITH_RNS || prime < (1u << 30) || prime >= (1u << 31) ||
                  ((uint64_t(1) << 32) % prime) >= (1u << 12)))
         return TN_EINVAL;
-    if (kernel < -1 || kernel > KC_MFMA) return TN_EINVAL;
+    if (kernel < -1 || kernel > KC_DOT || kernel == KC_BATCH) return TN_EINVAL;
     const int64_t es = u64 ? 8 : 4;
     const int64_t nA = align256((int64_t(1) << rA) * es), nB = align256((int64_t(1) << rB) * es),
                   nC = align256((int64_t(1) << rC) * es);
-    if (nA + nB + nC > int64_t(workspace_bytes)) return TN_ETOOBIG;
+    if (nA + nB + nC + kScratchPerPrime > int64_t(workspace_bytes)) return TN_ETOOBIG;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     char* base = static_cast<char*>(workspace);
     Step st;
@@ -505,7 +604,8 @@ extern "C" tn_status tn_step(const void* A, int32_t rA, const void* B, int32_t r
         return TN_EHIP;
     }
     KernelClass kc = KC_GENERIC;
-    hipError_t e = launch_step(st, u64, 0, u64 ? nullptr : &prime, 1, base, base, 0, stream, &kc, kernel);
+    hipError_t e = launch_step(st, u64, 0, u64 ? nullptr : &prime, 1, base, base, 0, base + nA + nB + nC, stream, &kc,
+                               kernel);
     if (e == hipErrorInvalidValue) {
         (void)hipStreamSynchronize(stream);
         return TN_EUNSUPPORTED;

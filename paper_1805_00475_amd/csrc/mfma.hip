@@ -10,7 +10,8 @@
 // where A_i, B_j are int8 digit matrices; every T_t is accumulated by the
 // int8 MFMA into int32 registers. Each product of digits is at most 2^14 in
 // magnitude, at most four digit pairs share a shift, so K <= 2^14 keeps every
-// T_t below 2^30 -- exact. The epilogue forms
+// T_t below 2^30 -- exact; wider K is summed in chunks of 2^14 whose results
+// are reduced to residues and added modulo p. The epilogue forms
 //     X = (T0 + T1 2^8 + T2 2^16 + T3 2^24) + (T4 + T5 2^8 + T6 2^16) (2^32 mod p)
 // in 64-bit integers (|X| < 2^59), adds a multiple of p above 2^59, and
 // reduces with the folding reduction of the other kernels.
@@ -75,6 +76,30 @@ __device__ __forceinline__ uint32_t combine_digits(const int32_t T[7], uint32_t 
     return m.finish(y);
 }
 
+constexpr int kFlushChunks = (1 << 14) / 64;  // K chunks of 64 per exact int32 accumulation
+
+__device__ __forceinline__ void flush(v4i (&acc)[7][4][2], uint32_t (&racc)[4][2][4], uint32_t p, uint32_t r2,
+                                      uint64_t off) {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int32_t Tt[7];
+#pragma unroll
+                for (int t = 0; t < 7; ++t) Tt[t] = acc[t][rb][cb][v];
+                const uint32_t x = combine_digits(Tt, p, r2, off) + racc[rb][cb][v];
+                racc[rb][cb][v] = x >= p ? x - p : x;
+            }
+#pragma unroll
+    for (int t = 0; t < 7; ++t)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) acc[t][rb][cb] = v4i{0, 0, 0, 0};
+}
+
 __global__ __launch_bounds__(256, 1) void k_mfma(StepArgs a, MfmaExtra ex) {
     __shared__ __align__(16) uint8_t lds[kBM * kRowB + kBN * kRowB];
     __shared__ uint64_t hiOff[32];
@@ -121,12 +146,19 @@ __global__ __launch_bounds__(256, 1) void k_mfma(StepArgs a, MfmaExtra ex) {
         const uint8_t* gB = B + xB0 * rowBytes;
 
         v4i acc[7][4][2];
+        uint32_t racc[4][2][4];  // residues of the K chunks already flushed
 #pragma unroll
         for (int t = 0; t < 7; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) acc[t][i][j] = v4i{0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) racc[i][j][v] = 0;
 
         for (int kc = 0; kc < nk; ++kc) {
             __syncthreads();
@@ -169,6 +201,9 @@ __global__ __launch_bounds__(256, 1) void k_mfma(StepArgs a, MfmaExtra ex) {
                         for (int cb = 0; cb < 2; ++cb)
                             acc[i + j][rb][cb] =
                                 __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i][rb], fb[j][cb], acc[i + j][rb][cb], 0, 0, 0);
+            // every 2^14 entries of K, fold the exact int32 sums into residues
+            // so they never exceed 2^30
+            if (((kc + 1) & (kFlushChunks - 1)) == 0 && kc + 1 < nk) flush(acc, racc, p, r2, off);
         }
         __syncthreads();
         // epilogue: lane holds rows 4 (lane / 16) + v, column lane % 16 of each 16x16 block
@@ -183,7 +218,8 @@ __global__ __launch_bounds__(256, 1) void k_mfma(StepArgs a, MfmaExtra ex) {
                     for (int t = 0; t < 7; ++t) Tt[t] = acc[t][rb][cb][v];
                     const int i = wr + rb * 16 + 4 * (lane >> 4) + v;
                     const int j = wc + cb * 16 + (lane & 15);
-                    sOut[i * kBN + j] = combine_digits(Tt, p, r2, off);
+                    const uint32_t x = combine_digits(Tt, p, r2, off) + racc[rb][cb][v];  // < 2p < 2^32
+                    sOut[i * kBN + j] = x >= p ? x - p : x;
                 }
         __syncthreads();
         const uint64_t baseC = pdep64(xA0, a.maskA) | pdep64(xB0, a.maskB);
@@ -221,7 +257,7 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream) {
 }
 
 bool mfma_eligible(const StepArgs& a) {
-    return a.s >= 6 && a.s <= 14 && a.fA >= 7 && a.fB >= 6;
+    return a.s >= 6 && a.fA >= 7 && a.fB >= 6;
 }
 
 }  // namespace tn

@@ -11,7 +11,7 @@ struct MfmaExtra {
     uint64_t off[kMaxGroup];  // a multiple of p at least 2^59, per prime
 };
 
-// A step qualifies when K = 2^s is in [64, 2^14] and the free sides give at
+// A step qualifies when K = 2^s is at least 64 and the free sides give at
 // least one 128 x 64 output tile. The caller must also ensure that neither
 // operand is a shared initial tensor: both are rewritten in place into digit
 // planes.

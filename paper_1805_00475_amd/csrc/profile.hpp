@@ -12,7 +12,7 @@
 
 namespace tn {
 
-enum KernelClass { KC_GENERIC = 0, KC_STREAM = 1, KC_ROWDOT = 2, KC_MFMA = 3, KC_BATCH = 4 };
+enum KernelClass { KC_GENERIC = 0, KC_STREAM = 1, KC_ROWDOT = 2, KC_MFMA = 3, KC_BATCH = 4, KC_DOT = 5 };
 
 struct Profiler {
     bool on = false;
@@ -29,7 +29,8 @@ struct Profiler {
         }
         return pool[used++];
     }
-    void begin(bool enable, hipStream_t) {
+    // top-level calls (tn_contract, tn_count, tn_count_batch) start a record
+    void start(bool enable) {
         on = enable;
         used = 0;
         cls.clear();
@@ -60,14 +61,16 @@ struct Profiler {
         cls.push_back(kc);
         account(kc, bytes, macs);
     }
-    // call after the stream is synchronized
-    void end() {
+    // after the stream is synchronized: add the recorded launch times and
+    // recycle the events (the record stays open for further launches)
+    void collect() {
         if (!on) return;
         for (size_t i = 0; i < cls.size() && 2 * i + 1 < used; ++i) {
             float ms = 0;
             if (hipEventElapsedTime(&ms, pool[2 * i], pool[2 * i + 1]) == hipSuccess) acc[cls[i]].ms += ms;
         }
-        on = false;
+        used = 0;
+        cls.clear();
     }
 };
 

@@ -71,7 +71,9 @@ SMALL = [
     ("stream", 14, 5, 3), ("stream", 12, 3, 1), ("stream", 13, 7, 5), ("stream", 10, 2, 0),
     ("rowdot", 12, 10, 8), ("rowdot", 9, 9, 9), ("rowdot", 14, 8, 7),
     ("mfma", 13, 12, 6), ("mfma", 18, 17, 8), ("mfma", 16, 15, 9), ("mfma", 21, 20, 14), ("mfma", 15, 14, 7),
-    ("auto", 16, 15, 9), ("auto", 12, 3, 1),
+    ("mfma", 22, 21, 15),
+    ("dot", 14, 14, 14), ("dot", 16, 15, 13), ("dot", 12, 12, 10),
+    ("auto", 16, 15, 9), ("auto", 12, 3, 1), ("auto", 18, 18, 16),
 ]
 
 
@@ -88,7 +90,8 @@ def test_kernel_extreme_residues(kernel, rA, rB, s, kind):
     _check(rA, rB, s, kernel, P[-1], seed=7, kind=kind, samples=2000)
 
 
-@pytest.mark.parametrize("kernel,rA,rB,s", [("generic", 9, 7, 3), ("stream", 14, 5, 3), ("rowdot", 12, 10, 8)])
+@pytest.mark.parametrize("kernel,rA,rB,s", [("generic", 9, 7, 3), ("stream", 14, 5, 3), ("rowdot", 12, 10, 8),
+                                            ("dot", 16, 15, 13)])
 def test_kernel_u64(kernel, rA, rB, s):
     _check(rA, rB, s, kernel, None, seed=5, samples=2000)
 
@@ -100,7 +103,8 @@ def test_mfma_refuses_small_or_u64():
         tn.step(A, 10, B, 10, 5, (1 << 5) - 1, prime=P[0], kernel="mfma")  # K = 32 < 64
 
 
-@pytest.mark.parametrize("kernel,rA,rB,s", [("mfma", 24, 23, 10), ("stream", 28, 3, 1), ("stream", 27, 5, 2)])
+@pytest.mark.parametrize("kernel,rA,rB,s", [("mfma", 24, 23, 10), ("stream", 28, 3, 1), ("stream", 27, 5, 2),
+                                            ("dot", 22, 22, 22), ("mfma", 22, 24, 15)])
 def test_kernel_full_size_sampled(kernel, rA, rB, s):
     # shapes of the largest steps of the n=200 cubic vertex-cover plans
     _check(rA, rB, s, kernel, P[3], seed=11, samples=400)
