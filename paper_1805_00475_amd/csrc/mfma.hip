@@ -66,7 +66,14 @@ __global__ __launch_bounds__(256) void k_digits(uint32_t* X, int64_t stride, uin
 }
 
 // --------------------------------------------------------------- GEMM
+// Work-group tile 128 (xA) x 64 (xB), 8 waves of 32 x 32 (two per SIMD), K
+// consumed in chunks of 64 entries (one 16x16x64 MFMA per digit pair and
+// 16x16 block). Digit tiles are double-buffered in LDS: the global loads of
+// chunk k+1 are issued before the MFMAs of chunk k and stored to the other
+// buffer after them, one barrier per chunk.
 constexpr int kBM = 128, kBN = 64, kRowB = 256 + 16;  // LDS row stride (bytes)
+constexpr int kBuf = (kBM + kBN) * kRowB;             // one LDS buffer
+constexpr int kThreads = 512;
 
 __device__ __forceinline__ uint32_t combine_digits(const int32_t T[7], uint32_t p, uint32_t r, uint64_t off) {
     const int64_t lo = int64_t(T[0]) + (int64_t(T[1]) << 8) + (int64_t(T[2]) << 16) + (int64_t(T[3]) << 24);
@@ -78,10 +85,10 @@ __device__ __forceinline__ uint32_t combine_digits(const int32_t T[7], uint32_t 
 
 constexpr int kFlushChunks = (1 << 14) / 64;  // K chunks of 64 per exact int32 accumulation
 
-__device__ __forceinline__ void flush(v4i (&acc)[7][4][2], uint32_t (&racc)[4][2][4], uint32_t p, uint32_t r2,
+__device__ __forceinline__ void flush(v4i (&acc)[7][2][2], uint32_t (&racc)[2][2][4], uint32_t p, uint32_t r2,
                                       uint64_t off) {
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -95,17 +102,15 @@ __device__ __forceinline__ void flush(v4i (&acc)[7][4][2], uint32_t (&racc)[4][2
 #pragma unroll
     for (int t = 0; t < 7; ++t)
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) acc[t][rb][cb] = v4i{0, 0, 0, 0};
 }
 
-__global__ __launch_bounds__(256, 1) void k_mfma(StepArgs a, MfmaExtra ex) {
-    __shared__ __align__(16) uint8_t lds[kBM * kRowB + kBN * kRowB];
-    __shared__ uint64_t hiOff[32];
-    __shared__ uint32_t hiIJ[32][2];
-    uint8_t* sA = lds;
-    uint8_t* sB = lds + kBM * kRowB;
+__global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex) {
+    __shared__ __align__(16) uint8_t lds[2 * kBuf];
+    __shared__ uint64_t hiOff[16];
+    __shared__ uint32_t hiIJ[16][2];
     uint32_t* sOut = reinterpret_cast<uint32_t*>(lds);  // kBM x kBN after the K loop
 
     const int g = blockIdx.z;
@@ -116,23 +121,28 @@ __global__ __launch_bounds__(256, 1) void k_mfma(StepArgs a, MfmaExtra ex) {
     const uint64_t off = ex.off[g];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wr = (w & 1) * 64, wc = (w >> 1) * 32;
+    const int wr = (w & 3) * 32, wc = (w >> 2) * 32;
     const uint64_t rowBytes = uint64_t(4) << a.s;  // K entries of 4 bytes (4 digit planes)
     const int nk = 1 << (a.s - 6);
     const uint64_t tilesA = uint64_t(1) << (a.fA - 7), tilesB = uint64_t(1) << (a.fB - 6);
     const uint64_t T = tilesA * tilesB;
 
-    // output mapping inside a tile: tile-local t = tid | q << 8 (q < 32),
+    // output mapping inside a tile: tile-local t = tid | q << 9 (q < 16),
     // position pdep(t, TM), TM = the 7 lowest A bits and 6 lowest B bits of C
     const uint64_t TM = pdep64(127, a.maskA) | pdep64(63, a.maskB);
     const uint64_t offLow = pdep64(uint64_t(tid), TM);
     const uint32_t iLow = uint32_t(pext64(offLow, a.maskA)), jLow = uint32_t(pext64(offLow, a.maskB));
-    if (tid < 32) {
-        const uint64_t oh = pdep64(uint64_t(tid) << 8, TM);
+    if (tid < 16) {
+        const uint64_t oh = pdep64(uint64_t(tid) << 9, TM);
         hiOff[tid] = oh;
         hiIJ[tid][0] = uint32_t(pext64(oh, a.maskA));
         hiIJ[tid][1] = uint32_t(pext64(oh, a.maskB));
     }
+    // raw digit copies: thread tid moves 16 B at row (tid / 16) + 32 q,
+    // byte (tid % 16) * 16 of the 256-byte chunk (A: q < 4, B: q < 2)
+    const int ldRow = tid >> 4, ldCol = (tid & 15) * 16;
+    const int kg = (lane >> 4) * 16;
+    const int fr = lane & 15;
     __syncthreads();
 
     for (uint64_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
@@ -145,58 +155,67 @@ __global__ __launch_bounds__(256, 1) void k_mfma(StepArgs a, MfmaExtra ex) {
         const uint8_t* gA = A + xA0 * rowBytes;
         const uint8_t* gB = B + xB0 * rowBytes;
 
-        v4i acc[7][4][2];
-        uint32_t racc[4][2][4];  // residues of the K chunks already flushed
+        v4i acc[7][2][2];
+        uint32_t racc[2][2][4];  // residues of the K chunks already flushed
 #pragma unroll
         for (int t = 0; t < 7; ++t)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) acc[t][i][j] = v4i{0, 0, 0, 0};
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) racc[i][j][v] = 0;
 
+        // prefetch registers (named, so they stay in VGPRs)
+        uint4 pa0, pa1, pa2, pa3, pb0, pb1;
+#define TN_FETCH(kc_)                                                                         \
+    do {                                                                                      \
+        const uint64_t kb_ = uint64_t(kc_) * 256 + ldCol;                                     \
+        pa0 = *reinterpret_cast<const uint4*>(gA + uint64_t(ldRow) * rowBytes + kb_);         \
+        pa1 = *reinterpret_cast<const uint4*>(gA + uint64_t(ldRow + 32) * rowBytes + kb_);    \
+        pa2 = *reinterpret_cast<const uint4*>(gA + uint64_t(ldRow + 64) * rowBytes + kb_);    \
+        pa3 = *reinterpret_cast<const uint4*>(gA + uint64_t(ldRow + 96) * rowBytes + kb_);    \
+        pb0 = *reinterpret_cast<const uint4*>(gB + uint64_t(ldRow) * rowBytes + kb_);         \
+        pb1 = *reinterpret_cast<const uint4*>(gB + uint64_t(ldRow + 32) * rowBytes + kb_);    \
+    } while (0)
+#define TN_STASH(buf_)                                                                        \
+    do {                                                                                      \
+        uint8_t* sA_ = lds + (buf_) * kBuf;                                                   \
+        uint8_t* sB_ = sA_ + kBM * kRowB;                                                     \
+        *reinterpret_cast<uint4*>(sA_ + ldRow * kRowB + ldCol) = pa0;                         \
+        *reinterpret_cast<uint4*>(sA_ + (ldRow + 32) * kRowB + ldCol) = pa1;                  \
+        *reinterpret_cast<uint4*>(sA_ + (ldRow + 64) * kRowB + ldCol) = pa2;                  \
+        *reinterpret_cast<uint4*>(sA_ + (ldRow + 96) * kRowB + ldCol) = pa3;                  \
+        *reinterpret_cast<uint4*>(sB_ + ldRow * kRowB + ldCol) = pb0;                         \
+        *reinterpret_cast<uint4*>(sB_ + (ldRow + 32) * kRowB + ldCol) = pb1;                  \
+    } while (0)
+        __syncthreads();  // the previous tile's output staging is done with the LDS
+        TN_FETCH(0);
+        TN_STASH(0);
+        __syncthreads();
         for (int kc = 0; kc < nk; ++kc) {
-            __syncthreads();
-            // raw copy of the digit chunks: A 128 rows x 256 B, B 64 rows x 256 B
+            const int buf = kc & 1;
+            if (kc + 1 < nk) TN_FETCH(kc + 1);
+            const uint8_t* sA = lds + buf * kBuf;
+            const uint8_t* sB = sA + kBM * kRowB;
+            v4i fa[4][2], fb[4][2];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int idx = tid + 256 * q;
-                const int row = idx >> 4, c16 = idx & 15;
-                const uint4 v = *reinterpret_cast<const uint4*>(gA + uint64_t(row) * rowBytes + uint64_t(kc) * 256 +
-                                                                c16 * 16);
-                *reinterpret_cast<uint4*>(sA + row * kRowB + c16 * 16) = v;
-            }
+            for (int d = 0; d < 4; ++d)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int idx = tid + 256 * q;
-                const int row = idx >> 4, c16 = idx & 15;
-                const uint4 v = *reinterpret_cast<const uint4*>(gB + uint64_t(row) * rowBytes + uint64_t(kc) * 256 +
-                                                                c16 * 16);
-                *reinterpret_cast<uint4*>(sB + row * kRowB + c16 * 16) = v;
-            }
-            __syncthreads();
-            v4i fa[4][4], fb[4][2];
-            const int kg = (lane >> 4) * 16;
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-#pragma unroll
-                for (int rb = 0; rb < 4; ++rb)
-                    fa[d][rb] = *reinterpret_cast<const v4i*>(sA + (wr + rb * 16 + (lane & 15)) * kRowB + d * 64 + kg);
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
-                    fb[d][cb] = *reinterpret_cast<const v4i*>(sB + (wc + cb * 16 + (lane & 15)) * kRowB + d * 64 + kg);
-            }
+                for (int b = 0; b < 2; ++b) {
+                    fa[d][b] = *reinterpret_cast<const v4i*>(sA + (wr + b * 16 + fr) * kRowB + d * 64 + kg);
+                    fb[d][b] = *reinterpret_cast<const v4i*>(sB + (wc + b * 16 + fr) * kRowB + d * 64 + kg);
+                }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
-                    for (int rb = 0; rb < 4; ++rb)
+                    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
                         for (int cb = 0; cb < 2; ++cb)
                             acc[i + j][rb][cb] =
@@ -204,11 +223,12 @@ __global__ __launch_bounds__(256, 1) void k_mfma(StepArgs a, MfmaExtra ex) {
             // every 2^14 entries of K, fold the exact int32 sums into residues
             // so they never exceed 2^30
             if (((kc + 1) & (kFlushChunks - 1)) == 0 && kc + 1 < nk) flush(acc, racc, p, r2, off);
+            if (kc + 1 < nk) TN_STASH(buf ^ 1);
+            __syncthreads();
         }
-        __syncthreads();
         // epilogue: lane holds rows 4 (lane / 16) + v, column lane % 16 of each 16x16 block
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -217,19 +237,22 @@ __global__ __launch_bounds__(256, 1) void k_mfma(StepArgs a, MfmaExtra ex) {
 #pragma unroll
                     for (int t = 0; t < 7; ++t) Tt[t] = acc[t][rb][cb][v];
                     const int i = wr + rb * 16 + 4 * (lane >> 4) + v;
-                    const int j = wc + cb * 16 + (lane & 15);
+                    const int j = wc + cb * 16 + fr;
                     const uint32_t x = combine_digits(Tt, p, r2, off) + racc[rb][cb][v];  // < 2p < 2^32
                     sOut[i * kBN + j] = x >= p ? x - p : x;
                 }
         __syncthreads();
         const uint64_t baseC = pdep64(xA0, a.maskA) | pdep64(xB0, a.maskB);
-        for (int q = 0; q < 32; ++q) {
+#pragma unroll 4
+        for (int q = 0; q < 16; ++q) {
             const uint64_t o = offLow | hiOff[q];
             const uint32_t i = iLow | hiIJ[q][0];
             const uint32_t j = jLow | hiIJ[q][1];
             C[baseC | o] = sOut[i * kBN + j];
         }
     }
+#undef TN_FETCH
+#undef TN_STASH
 }
 
 hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream) {
@@ -251,8 +274,8 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const uint64_t T = (uint64_t(1) << (a.fA - 7)) * (uint64_t(1) << (a.fB - 6));
-    dim3 grid(uint32_t(std::min<uint64_t>(T, 2048)), 1, G);
-    hipLaunchKernelGGL(k_mfma, grid, dim3(256), 0, stream, a, ex);
+    dim3 grid(uint32_t(std::min<uint64_t>(T, 1024)), 1, G);
+    hipLaunchKernelGGL(k_mfma, grid, dim3(kThreads), 0, stream, a, ex);
     return hipGetLastError();
 }
 
