@@ -173,9 +173,10 @@ tn_status tn_count_batch(const tn_formula* fs, int32_t n, tn_order_kind kind, ui
  * are the algorithmic totals of those launches: 2^rA + 2^rB + 2^rC entries
  * of 4 or 8 bytes and 2^(rA + rB - s) multiply-adds per step and prime. */
 typedef enum {
-    TN_KC_GENERIC = 0, TN_KC_STREAM = 1, TN_KC_ROWDOT = 2, TN_KC_MFMA = 3, TN_KC_BATCH = 4, TN_KC_DOT = 5
+    TN_KC_GENERIC = 0, TN_KC_STREAM = 1, TN_KC_ROWDOT = 2, TN_KC_MFMA = 3, TN_KC_BATCH = 4, TN_KC_DOT = 5,
+    TN_KC_DIGITS = 6   /* in-place digit pass before TN_KC_MFMA */
 } tn_kernel_class;
-#define TN_KERNEL_CLASSES 6
+#define TN_KERNEL_CLASSES 7
 typedef struct {
     int64_t launches;
     double ms;

@@ -282,6 +282,11 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
                        char* arena_base, int64_t arena_elems, char* scratch, hipStream_t stream, KernelClass* kc,
                        int force = -1) {
     const size_t es = u64 ? 8 : 4;
+    Profiler& prof = profiler();
+    // algorithmic work of the step: entries read and written, multiply-adds
+    const double step_bytes =
+        double(es) * G * (std::ldexp(1.0, st0.rA) + std::ldexp(1.0, st0.rB) + std::ldexp(1.0, st0.rC));
+    const double step_macs = double(G) * std::ldexp(1.0, st0.rA + st0.rB - st0.s);
     Step st = st0;
     StepArgs a{};
     a.B = st.initB ? init_base + st.offB * es : arena_base + st.offB * es;
@@ -322,18 +327,21 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
         *kc = KC_DOT;
         dim3 g1(nblk, 1, G), g2(uint32_t(total), 1, G);
         uint64_t* scr = reinterpret_cast<uint64_t*>(scratch);
-        if (u64) {
+        prof.before(stream);
+        if (u64)
             hipLaunchKernelGGL(k_dot_partial<true>, g1, dim3(256), 0, stream, a, scr, nblk);
-            hipLaunchKernelGGL(k_dot_final<true>, g2, dim3(64), 0, stream, a, scr, nblk);
-        } else {
+        else
             hipLaunchKernelGGL(k_dot_partial<false>, g1, dim3(256), 0, stream, a, scr, nblk);
+        prof.after_raw(stream, KC_DOT, step_bytes, step_macs);
+        if (u64)
+            hipLaunchKernelGGL(k_dot_final<true>, g2, dim3(64), 0, stream, a, scr, nblk);
+        else
             hipLaunchKernelGGL(k_dot_final<false>, g2, dim3(64), 0, stream, a, scr, nblk);
-        }
         return hipGetLastError();
     }
     if ((force == KC_MFMA) || (force < 0 && !generic_only && can_mfma && !(flags & TN_FLAG_NO_MFMA))) {
         *kc = KC_MFMA;
-        return launch_mfma(a, G, stream);
+        return launch_mfma(a, G, stream, &prof, step_bytes, step_macs);
     }
     if (force == KC_STREAM || (force < 0 && !generic_only && can_stream)) {
         const int nb = std::min(a.fB, 4);
@@ -341,24 +349,31 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
         const uint64_t n_chunk = (uint64_t(1) << a.fB) >> nb;
         dim3 grid(cap32(n_iter, 1u << 20), cap32(n_chunk, 65535), G);
         *kc = KC_STREAM;
-        return u64 ? launch_stream<true>(a.s, 1 << nb, grid, stream, a)
-                   : launch_stream<false>(a.s, 1 << nb, grid, stream, a);
+        prof.before(stream);
+        hipError_t e = u64 ? launch_stream<true>(a.s, 1 << nb, grid, stream, a)
+                           : launch_stream<false>(a.s, 1 << nb, grid, stream, a);
+        prof.after_raw(stream, KC_STREAM, step_bytes, step_macs);
+        return e;
     }
     if (force == KC_ROWDOT || (force < 0 && !generic_only && a.s >= 6)) {
         dim3 grid(cap32((total + 3) / 4, 1u << 20), 1, G);
         *kc = KC_ROWDOT;
+        prof.before(stream);
         if (u64)
             hipLaunchKernelGGL(k_rowdot<true>, grid, dim3(256), 0, stream, a);
         else
             hipLaunchKernelGGL(k_rowdot<false>, grid, dim3(256), 0, stream, a);
+        prof.after_raw(stream, KC_ROWDOT, step_bytes, step_macs);
         return hipGetLastError();
     }
     dim3 grid(cap32((total + 255) / 256, 1u << 20), 1, G);
     *kc = KC_GENERIC;
+    prof.before(stream);
     if (u64)
         hipLaunchKernelGGL(k_generic<true>, grid, dim3(256), 0, stream, a);
     else
         hipLaunchKernelGGL(k_generic<false>, grid, dim3(256), 0, stream, a);
+    prof.after_raw(stream, KC_GENERIC, step_bytes, step_macs);
     return hipGetLastError();
 }
 
@@ -471,11 +486,9 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
         const int gn = std::min(G, R.k - g0);
         for (const Step& st : plan.steps) {
             KernelClass kc = KC_GENERIC;
-            prof.before(stream);
             err = launch_step(st, R.u64, o->flags, R.u64 ? nullptr : R.primes.data() + g0, gn, init_base, arena_base,
                               arena_elems, scratch, stream, &kc);
             if (err != hipSuccess) return fail();
-            prof.after(stream, kc, st, gn, es);
         }
         for (int g = 0; g < gn; ++g) {
             err = hipMemcpyAsync(&out[g0 + g], arena_base + (g * arena_elems + last.offC) * int64_t(es), es,

@@ -27,6 +27,7 @@
 
 #include "kernels.hpp"
 #include "mfma.hpp"
+#include "profile.hpp"
 
 namespace tn {
 
@@ -255,7 +256,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex) 
 #undef TN_STASH
 }
 
-hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream) {
+hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
+                       double step_macs) {
     MfmaExtra ex{};
     for (int g = 0; g < G; ++g) {
         const uint64_t p = a.p[g];
@@ -265,6 +267,7 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream) {
     auto blocks = [](uint64_t n) { return dim3(uint32_t(std::min<uint64_t>((n + 255) / 256, 1u << 16)), 1, 1); };
     dim3 gA = blocks(nA), gB = blocks(nB);
     gA.z = gB.z = G;
+    prof->before(stream);
     hipLaunchKernelGGL(k_digits, gA, dim3(256), 0, stream, static_cast<uint32_t*>(const_cast<void*>(a.A)),
                        a.strideA, nA, a);
     hipError_t e = hipGetLastError();
@@ -273,9 +276,13 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream) {
                        a.strideB, nB, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // the digit pass reads and rewrites both operands in place
+    prof->after_raw(stream, KC_DIGITS, 2.0 * 16.0 * double(nA + nB) * G, 0.0);
     const uint64_t T = (uint64_t(1) << (a.fA - 7)) * (uint64_t(1) << (a.fB - 6));
     dim3 grid(uint32_t(std::min<uint64_t>(T, 1024)), 1, G);
+    prof->before(stream);
     hipLaunchKernelGGL(k_mfma, grid, dim3(kThreads), 0, stream, a, ex);
+    prof->after_raw(stream, KC_MFMA, step_bytes, step_macs);
     return hipGetLastError();
 }
 

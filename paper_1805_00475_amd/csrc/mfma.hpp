@@ -16,6 +16,10 @@ struct MfmaExtra {
 // operand is a shared initial tensor: both are rewritten in place into digit
 // planes.
 bool mfma_eligible(const StepArgs& a);
-hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream);
+struct Profiler;
+// Digit pass on both operands, then the GEMM; each launch is bracketed by
+// the profiler (no-op unless timing is on) with its algorithmic work.
+hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
+                       double step_macs);
 
 }  // namespace tn

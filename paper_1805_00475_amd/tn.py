@@ -24,7 +24,7 @@ FLAG_GENERIC_ONLY = 1
 FLAG_NO_MFMA = 2
 FLAG_TIMING = 4
 FLAG_NO_GRAPH = 8
-KERNEL_CLASSES = ["generic", "stream", "rowdot", "mfma", "batch", "dot"]
+KERNEL_CLASSES = ["generic", "stream", "rowdot", "mfma", "batch", "dot", "digits"]
 MAX_RANK = 34
 MAX_PRIMES = 64
 
