@@ -18,6 +18,7 @@
 #include "kernels.hpp"
 #include "mfma.hpp"
 #include "profile.hpp"
+#include "launch.hpp"
 
 namespace tn {
 
@@ -171,8 +172,6 @@ __global__ __launch_bounds__(256) void k_rowdot(StepArgs a) {
 // Few outputs (2^rC <= 64), very wide K: the shared dimension is split over
 // the grid. Block b sums its K slice for every output and writes one partial
 // per output; a second kernel adds the partials of each output.
-constexpr int kDotBlocks = 1024;
-constexpr int64_t kScratchPerPrime = int64_t(kDotBlocks) * 64 * 8;
 
 template <bool U64>
 __global__ __launch_bounds__(256) void k_dot_partial(StepArgs a, uint64_t* scratch, int nblk) {
@@ -249,8 +248,6 @@ __global__ __launch_bounds__(64) void k_dot_final(StepArgs a, const uint64_t* sc
 
 // ----------------------------------------------------------------- launches
 
-namespace {
-
 template <bool U64, int LOGK>
 hipError_t launch_stream_nb(int nb, dim3 grid, hipStream_t st, const StepArgs& a) {
     switch (nb) {
@@ -280,7 +277,7 @@ inline uint32_t cap32(uint64_t x, uint32_t hi) { return uint32_t(std::min<uint64
 // Choose and launch the kernel of one step for a group of G primes.
 hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* primes, int G, char* init_base,
                        char* arena_base, int64_t arena_elems, char* scratch, hipStream_t stream, KernelClass* kc,
-                       int force = -1) {
+                       int force) {
     const size_t es = u64 ? 8 : 4;
     Profiler& prof = profiler();
     // algorithmic work of the step: entries read and written, multiply-adds
@@ -395,7 +392,23 @@ uint64_t init_entry(const InitTensor& t, const std::vector<int32_t>& pos, uint64
     return ntrue == 1 ? 1 : 0;
 }
 
-}  // namespace
+void fill_init(const Network& net, const Plan& plan, bool u64, uint8_t* host) {
+    for (int32_t i = 0; i < plan.n_init; ++i) {
+        const InitTensor& t = net.t[i];
+        const auto& L = plan.layout[i];
+        std::vector<int32_t> pos(t.bonds.size());
+        for (size_t k = 0; k < t.bonds.size(); ++k)
+            pos[k] = int32_t(std::find(L.begin(), L.end(), t.bonds[k]) - L.begin());
+        const uint64_t n = uint64_t(1) << t.bonds.size();
+        for (uint64_t x = 0; x < n; ++x) {
+            const uint64_t v = init_entry(t, pos, x);
+            if (u64)
+                reinterpret_cast<uint64_t*>(host)[plan.init_off[i] + x] = v;
+            else
+                reinterpret_cast<uint32_t*>(host)[plan.init_off[i] + x] = uint32_t(v);
+        }
+    }
+}
 
 tn_status resolve(const Plan& plan, const tn_contract_opts* o, Resolved& r) {
     int32_t arith = o ? o->arith : TN_ARITH_AUTO;
@@ -415,11 +428,7 @@ tn_status resolve(const Plan& plan, const tn_contract_opts* o, Resolved& r) {
     return TN_OK;
 }
 
-namespace {
-
 int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
-
-}  // namespace
 
 // Runs the plan; fills residues (RNS) or *u64v (U64).
 tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts* o, const Resolved& R,
@@ -456,21 +465,7 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
     char* scratch = arena_base + int64_t(G) * arena_bytes;
     // initial tensors in plan layout, identical for every prime (0/1/2 entries)
     std::vector<uint8_t> host(size_t(plan.init_elems) * es, 0);
-    for (int32_t i = 0; i < plan.n_init; ++i) {
-        const InitTensor& t = net.t[i];
-        const auto& L = plan.layout[i];
-        std::vector<int32_t> pos(t.bonds.size());
-        for (size_t k = 0; k < t.bonds.size(); ++k)
-            pos[k] = int32_t(std::find(L.begin(), L.end(), t.bonds[k]) - L.begin());
-        const uint64_t n = uint64_t(1) << t.bonds.size();
-        for (uint64_t x = 0; x < n; ++x) {
-            uint64_t v = init_entry(t, pos, x);
-            if (R.u64)
-                reinterpret_cast<uint64_t*>(host.data())[plan.init_off[i] + x] = v;
-            else
-                reinterpret_cast<uint32_t*>(host.data())[plan.init_off[i] + x] = uint32_t(v);
-        }
-    }
+    fill_init(net, plan, R.u64, host.data());
     Profiler& prof = profiler();
     hipError_t err = hipMemcpyAsync(init_base, host.data(), host.size(), hipMemcpyHostToDevice, stream);
     // on any failure, drain the stream before the host staging buffer goes away

@@ -4,6 +4,7 @@
 
 small_1in3_counts.json    monotone 1-in-3, n=20, m=14, seeds 0..999 (O-A brute force)
 batch_small_counts.json   the first instances of the mixed batch with n <= 30 (O-A)
+batch_counts.json         mixed batch instances 0..47 (O-A for n <= 30, else O-D)
 cvc_counts.json           vertex cover of random cubic graphs, n=60 (O-A is out of
                           reach; bucket elimination O-D, cross-checked by the
                           pairwise contractor O-B) and n=120 (O-D); with --large
@@ -46,6 +47,17 @@ def main(large=False):
     dump("batch_small_counts.json", {
         "workload": "instances.batch_instance(i), master seed 0, the first 24 with n <= 32",
         "oracle": "oracle.brute.count_c (O-A)", "items": items})
+
+    bat = []
+    for i in range(48):
+        f = I.batch_instance(i)
+        t = time.time()
+        c = brute.count_c(f) if f.n_vars <= 30 else elim.count_rns(f)
+        bat.append({"index": i, "n_vars": f.n_vars, "count": str(c)})
+        print(f"  batch {i} n={f.n_vars}: {c} ({time.time() - t:.1f}s)")
+    dump("batch_counts.json", {
+        "workload": "instances.batch_instance(i), master seed 0, i < 48",
+        "oracle": "oracle.brute.count_c (O-A) for n <= 30, else oracle.elim.count_rns (O-D)", "items": bat})
 
     cvc = []
     for n, seeds in ((60, range(10)), (120, range(6))) + (((200, range(2)),) if large else ()):
