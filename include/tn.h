@@ -137,6 +137,10 @@ void tn_plan_free(tn_plan* plan);
 /* Copy the merges of a plan: pairs[2k], pairs[2k+1] are the tensor ids of
  * step k, which creates tensor id n_tensors + k. cap = pair capacity. */
 tn_status tn_plan_steps(const tn_plan* plan, int32_t* pairs, int32_t cap, int32_t* n_steps);
+/* Self-check of a plan's memory layouts: TN_OK when no two tensors that are
+ * alive at the same time overlap in the arena, both for one-step-at-a-time
+ * execution and for execution in waves of equal level; TN_EINVAL otherwise. */
+tn_status tn_plan_verify(const tn_plan* plan);
 
 /* --------------------------------------------------------------- contract
  * Device workspace needed for a plan under opts (arith, n_primes,

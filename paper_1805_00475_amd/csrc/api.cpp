@@ -128,6 +128,11 @@ tn_status tn_plan_steps(const tn_plan* plan, int32_t* pairs, int32_t cap, int32_
     return TN_OK;
 }
 
+tn_status tn_plan_verify(const tn_plan* plan) {
+    if (!plan) return TN_EINVAL;
+    return verify_plan(plan->plan);
+}
+
 tn_status tn_primes(int32_t k, uint32_t* out) {
     if (k < 0 || k > TN_MAX_PRIMES || (k > 0 && !out)) return TN_EINVAL;
     const auto& P = prime_table(k);

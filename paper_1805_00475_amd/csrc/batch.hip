@@ -94,7 +94,7 @@ struct Inst {
     Resolved R;
     int P = 0;                // residue planes (1 for 64-bit)
     int64_t es = 4;
-    int64_t init_bytes = 0, arena_bytes = 0;
+    int64_t init_bytes = 0, arena_bytes = 0;  // arena_bytes: the wave layout
     int64_t n_items = 0;
     int64_t init_off = 0, arena_off = 0;  // in the sub-batch layout
     std::vector<uint32_t> res;
@@ -181,9 +181,9 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
             for (int q = 0; q < I.P; ++q) {
                 char* ab = base + I.arena_off + q * I.arena_bytes;
                 BItem it{};
-                it.A = st.initA ? ib + st.offA * I.es : ab + st.offA * I.es;
-                it.B = st.initB ? ib + st.offB * I.es : ab + st.offB * I.es;
-                it.C = ab + st.offC * I.es;
+                it.A = st.initA ? ib + st.woffA * I.es : ab + st.woffA * I.es;
+                it.B = st.initB ? ib + st.woffB * I.es : ab + st.woffB * I.es;
+                it.C = ab + st.woffC * I.es;
                 it.maskA = st.maskA;
                 it.maskB = cmask & ~st.maskA;
                 it.s = st.s;
@@ -201,7 +201,7 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
         }
         const Step& last = I.plan.steps.back();
         for (int q = 0; q < I.P; ++q) {
-            gathers.push_back({base + I.arena_off + q * I.arena_bytes + last.offC * I.es, I.R.u64 ? 1 : 0});
+            gathers.push_back({base + I.arena_off + q * I.arena_bytes + last.woffC * I.es, I.R.u64 ? 1 : 0});
             gather_of.push_back({i, q});
         }
     }
@@ -254,7 +254,10 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
         }
         for (const auto& bk : wave_big[L]) {
             Inst& I = ins[bk.first];
-            const Step& st = I.plan.steps[bk.second];
+            Step st = I.plan.steps[bk.second];
+            st.offA = st.woffA;
+            st.offB = st.woffB;
+            st.offC = st.woffC;
             for (int g0 = 0; g0 < I.P && err == hipSuccess; g0 += kMaxGroup) {
                 const int gn = std::min(kMaxGroup, I.P - g0);
                 KernelClass kc = KC_GENERIC;
@@ -377,7 +380,7 @@ extern "C" tn_status tn_count_batch(const tn_formula* fs, int32_t n, tn_order_ki
             continue;
         }
         I.init_bytes = align256(I.plan.init_elems * I.es);
-        I.arena_bytes = align256(I.plan.arena_elems * I.es);
+        I.arena_bytes = align256(I.plan.warena_elems * I.es);
         I.n_items = items_of(I.plan, I.P);
         const int64_t need = I.init_bytes + I.P * I.arena_bytes + I.n_items * int64_t(sizeof(BItem)) +
                              I.P * int64_t(sizeof(GItem) + 8) + 4096;

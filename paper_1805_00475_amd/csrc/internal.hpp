@@ -41,7 +41,8 @@ struct Step {
     int32_t rA = 0, rB = 0, s = 0, rC = 0;
     uint64_t maskA = 0;
     bool initA = false, initB = false;   // operand lives in the shared init region
-    int64_t offA = 0, offB = 0, offC = 0;  // element offsets (init region or arena)
+    int64_t offA = 0, offB = 0, offC = 0;  // element offsets (init region or arena), plan order
+    int64_t woffA = 0, woffB = 0, woffC = 0;  // the same for execution in waves (by level)
     int32_t level = 0;                   // longest chain of steps feeding this one
 };
 
@@ -54,7 +55,8 @@ struct Plan {
     std::vector<std::vector<int32_t>> layout;  // per tensor id: bond on each bit
     std::vector<int64_t> init_off;             // per initial tensor, element offset
     int64_t init_elems = 0;                    // size of the init region (elements)
-    int64_t arena_elems = 0;                   // arena size for one prime (elements)
+    int64_t arena_elems = 0;                   // arena size for one prime (elements), plan order
+    int64_t warena_elems = 0;                  // arena size when steps run in waves by level
     int32_t root = -1;                         // id of the final scalar
     tn_plan_stats stats{};
 };
@@ -88,6 +90,7 @@ Reduced absorb_small(const Network& net);
 tn_status make_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>> merges,
                     int32_t chosen, Plan& plan);
 double plan_cost(const Plan& plan);
+tn_status verify_plan(const Plan& plan);
 
 // api.cpp: order of any kind (with the judge for BEST / LEARNED) + plan
 tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out);

@@ -213,6 +213,34 @@ tn_status make_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>>
             plan.steps.push_back(st);
         }
         plan.arena_elems = arena.high;
+        // wave layout: steps of one level run concurrently, so every output
+        // of a wave is allocated before any input consumed in it is released
+        {
+            int32_t maxl = 0;
+            for (const Step& st : plan.steps) maxl = std::max(maxl, st.level);
+            std::vector<std::vector<int32_t>> by_level(size_t(maxl) + 1);
+            for (int32_t k = 0; k < int32_t(plan.steps.size()); ++k) by_level[plan.steps[k].level].push_back(k);
+            std::vector<int64_t> woff(n_ids, -1);
+            Arena wa;
+            for (int32_t L = 1; L <= maxl; ++L) {
+                for (int32_t k : by_level[L]) {
+                    Step& st = plan.steps[k];
+                    st.woffC = wa.alloc(align_up(int64_t(1) << st.rC));
+                    woff[st.out] = st.woffC;
+                }
+                for (int32_t k : by_level[L]) {
+                    Step& st = plan.steps[k];
+                    st.woffA = st.initA ? plan.init_off[st.a] : woff[st.a];
+                    st.woffB = st.initB ? plan.init_off[st.b] : woff[st.b];
+                }
+                for (int32_t k : by_level[L]) {
+                    const Step& st = plan.steps[k];
+                    if (!st.initA) wa.release(woff[st.a], align_up(int64_t(1) << st.rA));
+                    if (!st.initB) wa.release(woff[st.b], align_up(int64_t(1) << st.rB));
+                }
+            }
+            plan.warena_elems = wa.high;
+        }
         plan.stats.n_steps = int32_t(plan.steps.size());
         plan.stats.max_rank = maxr;
         plan.stats.entries = entries;
@@ -225,6 +253,49 @@ tn_status make_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>>
     } catch (const std::bad_alloc&) {
         return TN_ENOMEM;
     }
+    return TN_OK;
+}
+
+}  // namespace tn
+
+namespace tn {
+
+// Checks both arena layouts against the liveness of the plan's tensors: no
+// tensor may overlap another one that is alive at the same time, in plan
+// order (one step at a time) and in waves (all steps of a level at once).
+tn_status verify_plan(const Plan& plan) {
+    const int32_t n_init = plan.n_init;
+    const int32_t n_ids = n_init + int32_t(plan.steps.size());
+    std::vector<int32_t> born(n_ids, -1), died(n_ids, -1), lborn(n_ids, 0), ldied(n_ids, 0);
+    std::vector<int64_t> off(n_ids, -1), woff(n_ids, -1), size(n_ids, 0);
+    for (int32_t k = 0; k < int32_t(plan.steps.size()); ++k) {
+        const Step& st = plan.steps[k];
+        born[st.out] = k;
+        lborn[st.out] = st.level;
+        died[st.a] = died[st.b] = k;
+        ldied[st.a] = ldied[st.b] = st.level;
+        off[st.out] = st.offC;
+        woff[st.out] = st.woffC;
+        size[st.out] = int64_t(1) << st.rC;
+        if (st.offC < 0 || st.offC + size[st.out] > plan.arena_elems) return TN_EINVAL;
+        if (st.woffC < 0 || st.woffC + size[st.out] > plan.warena_elems) return TN_EINVAL;
+        if (!st.initA && (st.offA != off[st.a] || st.woffA != woff[st.a])) return TN_EINVAL;
+        if (!st.initB && (st.offB != off[st.b] || st.woffB != woff[st.b])) return TN_EINVAL;
+    }
+    const int32_t root = plan.root;
+    if (root >= n_init) {
+        died[root] = int32_t(plan.steps.size());
+        ldied[root] = 1 << 30;
+    }
+    for (int32_t x = n_init; x < n_ids; ++x)
+        for (int32_t y = x + 1; y < n_ids; ++y) {
+            // plan order: live on [born, died] (inputs stay live through the step)
+            const bool seq_overlap = born[x] <= died[y] && born[y] <= died[x];
+            const bool wave_overlap = lborn[x] <= ldied[y] && lborn[y] <= ldied[x];
+            const bool mem = off[x] < off[y] + size[y] && off[y] < off[x] + size[x];
+            const bool wmem = woff[x] < woff[y] + size[y] && woff[y] < woff[x] + size[x];
+            if ((seq_overlap && mem) || (wave_overlap && wmem)) return TN_EINVAL;
+        }
     return TN_OK;
 }
 

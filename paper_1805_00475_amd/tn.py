@@ -69,6 +69,7 @@ _SIGS = {
     "tn_order": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, _P(ctypes.c_void_p),
                   _P(PlanStats_c)], ctypes.c_int),
     "tn_plan_free": ([ctypes.c_void_p], None),
+    "tn_plan_verify": ([ctypes.c_void_p], ctypes.c_int),
     "tn_plan_steps": ([ctypes.c_void_p, _P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_int32)], ctypes.c_int),
     "tn_workspace_bytes": ([ctypes.c_void_p, ctypes.c_void_p, _P(ContractOpts_c), _P(ctypes.c_size_t)],
                            ctypes.c_int),
@@ -176,6 +177,9 @@ class Plan:
         buf = (ctypes.c_int32 * max(2, 2 * n.value))()
         _check(load().tn_plan_steps(self.h, buf, n.value, ctypes.byref(n)), "tn_plan_steps")
         return [(buf[2 * k], buf[2 * k + 1]) for k in range(n.value)]
+
+    def verify(self) -> bool:
+        return load().tn_plan_verify(self.h) == TN_OK
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -60,6 +60,7 @@ def _check_plan(f, plan):
     assert rep["macs"] == pytest.approx(st["macs"], rel=1e-12)
     if n0:
         assert rep["remaining"] == [[]]
+    assert plan.verify()  # arena layouts respect liveness (plan order and waves)
     return rep
 
 
