@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["cvc", "batch"], default="cvc",
+                    help="cvc: vertex cover of random cubic graphs (n vertices); batch: the mixed batch "
+                         "of 1-in-3 and cubic vertex cover with n in [30, 120]")
     ap.add_argument("--n", type=int, default=200)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--order", default="best")
@@ -116,8 +119,17 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
-    formulas = [I.cvc(args.n, s) for s in range(args.batch)]
-    k_primes = (args.n + 30) // 31 + 1
+    if args.workload == "cvc":
+        formulas = [I.cvc(args.n, s) for s in range(args.batch)]
+        k_primes = (args.n + 30) // 31 + 1
+        workload = (f"#Cubic-Vertex-Cover, uniform random cubic graphs n={args.n} (configuration model), "
+                    f"batch of {args.batch} seeds, {args.order} order, {k_primes} primes + CRT")
+    else:
+        formulas = [I.batch_instance(i) for i in range(args.batch)]
+        k_primes = None
+        workload = (f"mixed batch of {args.batch}: even index monotone 1-in-3 n~U[30,120] m=round(0.66n), "
+                    f"odd index cubic vertex cover n~U[30,120] (even); {args.order} order; u64 for n<=63 else "
+                    f"residues mod ceil(n/31)+1 primes")
     ws = tn.default_workspace()
     ws.get(64 << 30)
 
@@ -163,10 +175,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32 residues mod 31-bit primes (exact)",
         "data": "synthetic",
-        "config": {"workload": f"#Cubic-Vertex-Cover, uniform random cubic graphs n={args.n} "
-                               f"(configuration model), batch of {args.batch} seeds, {args.order} order, "
-                               f"{k_primes} primes + CRT",
-                   "batch": args.batch, "n": args.n, "order": args.order, "primes": k_primes},
+        "config": {"workload": workload, "batch": args.batch, "n": args.n if args.workload == "cvc" else None,
+                   "order": args.order, "primes": k_primes},
         "roofline": roofline,
         "hbm_roofline_stream": roofline_of("stream", prof["stream"]) if prof["stream"]["launches"] else None,
         "kernel_classes": per_class,
@@ -175,7 +185,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         p0 = plans[0]
-        out["cpu_baseline"] = cpu_baseline(formulas[0], p0.steps(), k_primes, args.cpu_seconds)
+        kp = k_primes if k_primes else (formulas[0].n_vars + 30) // 31 + 1
+        out["cpu_baseline"] = cpu_baseline(formulas[0], p0.steps(), kp, args.cpu_seconds)
         log("cpu baseline done")
     print(json.dumps(out))
 
