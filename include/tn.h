@@ -82,7 +82,9 @@ typedef enum {
     TN_ORDER_PARTITION = 1,  /* Sec. 3.1.1 tensor-METIS: recursive best-of-2 bisection */
     TN_ORDER_COMMUNITY = 2,  /* Sec. 3.1.1 tensor-GN: Girvan-Newman split tree */
     TN_ORDER_LEARNED = 3,    /* MLP pair scorer, judged against greedy and partition */
-    TN_ORDER_BEST = 4        /* cheapest of greedy, community and 16 randomized partitions */
+    TN_ORDER_BEST = 4        /* cheapest of greedy, community and up to 16 randomized partitions,
+                                searched while the host time spent stays below the best
+                                plan's predicted device time */
 } tn_order_kind;
 
 /* Predicted cost of a plan, known before any tensor entry is touched (the

@@ -1,6 +1,7 @@
 // Host-side entry points of the C ABI: build, order, plan queries, primes,
 // CRT and status strings. The GPU entry points live in contract.hip.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <new>
 
@@ -8,8 +9,10 @@
 
 namespace tn {
 
-// randomized bisection trials tried by the judge
+// randomized bisection trials the judge may try
 constexpr int kPartitionTrials = 16;
+// host microseconds of order search allowed per predicted device microsecond
+constexpr double kSearchRatio = 4.0;
 
 tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out) {
     try {
@@ -40,17 +43,38 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 have = true;
             }
         };
-        for (int32_t k : {TN_ORDER_GREEDY, TN_ORDER_COMMUNITY}) {
-            Plan p;
-            tn_status s2 = plan_of(k, p);
-            consider(s2, p);
-        }
-        for (int t = 0; t < kPartitionTrials; ++t) {
+        // Candidates in increasing host cost: greedy, four randomized
+        // bisections, Girvan-Newman, then more bisections. After the first
+        // three, stop once the host time spent on this search exceeds
+        // kSearchRatio times the predicted device time of the best plan so
+        // far (all residue planes); orders are searched on up to 16 host
+        // threads while the GPU contracts, so a few host microseconds per
+        // device microsecond still pay for themselves.
+        const auto t0 = std::chrono::steady_clock::now();
+        const double planes = N.n_vars <= 63 ? 1.0 : double((N.n_vars + 30) / 31 + 1);
+        auto over_budget = [&]() {
+            const double spent_us =
+                std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+            return have && spent_us > kSearchRatio * planes * plan_cost(out);
+        };
+        auto partition_trial = [&](int t) {
             Plan p;
             tn_status s2 = make_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t)),
                                      TN_ORDER_PARTITION, p);
             consider(s2, p);
+        };
+        {
+            Plan p;
+            consider(plan_of(TN_ORDER_GREEDY, p), p);
         }
+        partition_trial(0);
+        partition_trial(1);
+        for (int t = 2; t < 4 && !over_budget(); ++t) partition_trial(t);
+        if (!over_budget()) {
+            Plan p;
+            consider(plan_of(TN_ORDER_COMMUNITY, p), p);
+        }
+        for (int t = 4; t < kPartitionTrials && !over_budget(); ++t) partition_trial(t);
         if (kind == TN_ORDER_LEARNED) {
             bool ok = false;
             auto lm = order_learned(N, model, &ok);

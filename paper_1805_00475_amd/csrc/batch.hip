@@ -42,13 +42,16 @@ struct BItem {
 };
 
 // Persistent wave kernel: a fixed grid walks the wave's work list; each
-// block computes one tile, one thread per output entry (bit gathers).
+// wavefront takes one tile at a time, one lane per output entry (bit
+// gathers), so a block serves four small tiles at once.
 __global__ __launch_bounds__(256) void k_batch(const BItem* items, int64_t n) {
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = int64_t(gridDim.x) * (blockDim.x >> 6);
+    for (int64_t i = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); i < n; i += nw) {
         const BItem it = items[i];
         const uint64_t nOut = uint64_t(1) << it.tlog;
         const uint64_t K = uint64_t(1) << it.s;
-        for (uint64_t t = threadIdx.x; t < nOut; t += blockDim.x) {
+        for (uint64_t t = lane; t < nOut; t += 64) {
             const uint64_t c = it.c0 + t;
             const uint64_t xa = pext64(c, it.maskA) << it.s, xb = pext64(c, it.maskB) << it.s;
             if (it.u64) {
@@ -109,10 +112,12 @@ int worker_count(int n) {
     return std::max(1, std::min(w, n));
 }
 
-constexpr int kTileLog = 10;  // outputs per wave tile (2^10)
+constexpr int kTileLog = 8;  // outputs per wave tile (2^8, four per lane)
 
+// Steps small enough for the wave kernel; larger or wider ones get the
+// shape-specific kernels of the single-instance path.
 bool small_step(const Step& st) {
-    return st.rC <= 16 && st.rA <= 18 && st.rB <= 18 && st.rA + st.rB - st.s <= 24;
+    return st.rC <= 14 && st.s <= 6 && st.rA <= 16 && st.rB <= 16;
 }
 
 int64_t items_of(const Plan& plan, int P) {
@@ -247,7 +252,7 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
                     macs += std::ldexp(1.0, it.tlog + it.s);
                 }
             prof.before(stream);
-            const uint32_t grid = uint32_t(std::min<int64_t>(n, 4096));
+            const uint32_t grid = uint32_t(std::min<int64_t>((n + 3) / 4, 4096));
             hipLaunchKernelGGL(k_batch, dim3(grid), dim3(256), 0, stream, d_items + wave_off[L], n);
             err = hipGetLastError();
             prof.after_raw(stream, KC_BATCH, bytes, macs);
