@@ -82,9 +82,10 @@ typedef enum {
     TN_ORDER_PARTITION = 1,  /* Sec. 3.1.1 tensor-METIS: recursive best-of-2 bisection */
     TN_ORDER_COMMUNITY = 2,  /* Sec. 3.1.1 tensor-GN: Girvan-Newman split tree */
     TN_ORDER_LEARNED = 3,    /* MLP pair scorer, judged against greedy and partition */
-    TN_ORDER_BEST = 4        /* cheapest of greedy, community and up to 16 randomized partitions,
+    TN_ORDER_BEST = 4,       /* cheapest of greedy, community and up to 16 randomized partitions,
                                 searched while the host time spent stays below the best
                                 plan's predicted device time */
+    TN_ORDER_LEARNED_RAW = 5 /* the learned order alone, not judged (evaluation) */
 } tn_order_kind;
 
 /* Predicted cost of a plan, known before any tensor entry is touched (the
@@ -205,6 +206,45 @@ tn_status tn_profile_get(tn_kernel_profile* out /* TN_KERNEL_CLASSES entries */)
 tn_status tn_step(const void* A, int32_t rA, const void* B, int32_t rB, int32_t s, uint64_t maskA,
                   int32_t arith, uint32_t prime, int32_t kernel, void* C, void* workspace,
                   size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------- learned order
+ * A 3-layer perceptron scores candidate pairs of live tensors from 10
+ * features (ranks, shared bonds, result rank, neighbour counts; see
+ * order_learned.cpp): h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2),
+ * y = w3 . h2 + b3 with hidden width 128, fp32. The learned order contracts
+ * the best-scoring pair at every step; tn_order(TN_ORDER_LEARNED) then lets
+ * the judge keep it only when its predicted cost beats greedy, partition and
+ * community (the fallback, Sec. 4: portfolio and lazy evaluation).
+ * Parameters are packed as W1 [128 x 10], b1 [128], W2 [128 x 128], b2 [128],
+ * w3 [128], b3 (tn_model_param_count() floats). */
+int32_t tn_model_param_count(void);
+/* Host-side model for ordering; params (host, nullable = zeros) are copied. */
+tn_status tn_model_create(const float* params, tn_model** out);
+void tn_model_free(tn_model* model);
+tn_status tn_model_get(const tn_model* model, float* params);
+/* Host forward pass over n rows of 10 features (row-major) -> n scores. */
+tn_status tn_model_score(const tn_model* model, const float* x, int32_t n, float* y);
+/* Imitation data along a teacher plan's merge sequence: before each merge,
+ * one row of features per connected pair of live tensors (plus the teacher's
+ * pair if it shares no bond), label 1 for pairs the teacher merges while both
+ * are alive. groups[g] .. groups[g+1]-1 are the rows of state g. Host
+ * buffers; TN_EBUFSIZE with the needed sizes when a capacity is too small. */
+tn_status tn_trace(const tn_network* net, const tn_plan* teacher, float* feats, uint8_t* labels, int32_t* groups,
+                   int64_t cap_rows, int32_t cap_groups, int64_t* n_rows, int32_t* n_groups);
+/* GPU training kernels (all pointers device memory owned by the caller,
+ * queued on ``stream``). Forward: H1, H2 [n x 128], y [n]. Backward: the
+ * listwise loss L_g = log sum_{rows of g} exp(y) - log sum_{label 1} exp(y),
+ * averaged over the n_groups groups (device offsets, n_groups + 1 entries),
+ * into *loss; parameter gradients into grad (overwritten); dZ2, dZ1
+ * [n x 128] and dy [n] are scratch. Adam: one step (step >= 1) on the packed
+ * parameters with moment buffers m, v. */
+tn_status tn_mlp_forward(const float* params, const float* x, int64_t n, float* h1, float* h2, float* y,
+                         void* stream);
+tn_status tn_mlp_backward(const float* params, const float* x, const float* h1, const float* h2, const float* y,
+                          const uint8_t* labels, const int32_t* groups, int32_t n_groups, int64_t n, float* grad,
+                          float* dz2, float* dz1, float* dy, float* loss, void* stream);
+tn_status tn_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
+                      float beta2, float eps, void* stream);
 
 /* -------------------------------------------------------------- utilities */
 /* The k largest primes below 2^31, descending, as used by the RNS path. */

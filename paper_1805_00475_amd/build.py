@@ -39,7 +39,9 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, *COMMON, *HIP_FLAGS, "-c", src, "-o", obj]
     else:
-        cmd = ["g++", *COMMON, "-I" + os.path.join(ROCM, "include"), "-D__HIP_PLATFORM_AMD__", "-c", src, "-o", obj]
+        # AVX2 + FMA: present on every EPYC host and on Xeons since Haswell
+        cmd = ["g++", *COMMON, "-mavx2", "-mfma", "-I" + os.path.join(ROCM, "include"), "-D__HIP_PLATFORM_AMD__",
+               "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

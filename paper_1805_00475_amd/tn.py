@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libtn.so")
 TN_OK = 0
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ETOOBIG", -5: "ERANK", -6: "EBUFSIZE",
           -7: "EUNSUPPORTED"}
-ORDERS = {"greedy": 0, "partition": 1, "community": 2, "learned": 3, "best": 4}
+ORDERS = {"greedy": 0, "partition": 1, "community": 2, "learned": 3, "best": 4, "learned_raw": 5}
 ORDER_NAMES = {v: k for k, v in ORDERS.items()}
 ARITH = {"auto": 0, "u64": 1, "rns": 2}
 FLAG_GENERIC_ONLY = 1
@@ -83,6 +83,19 @@ _SIGS = {
     "tn_crt": ([_P(ctypes.c_uint32), ctypes.c_int32, _P(ctypes.c_uint32), ctypes.c_size_t, _P(ctypes.c_size_t)],
                ctypes.c_int),
     "tn_profile_get": ([_P(KernelProfile_c)], ctypes.c_int),
+    "tn_model_param_count": ([], ctypes.c_int32),
+    "tn_model_create": ([_P(ctypes.c_float), _P(ctypes.c_void_p)], ctypes.c_int),
+    "tn_model_free": ([ctypes.c_void_p], None),
+    "tn_model_get": ([ctypes.c_void_p, _P(ctypes.c_float)], ctypes.c_int),
+    "tn_model_score": ([ctypes.c_void_p, _P(ctypes.c_float), ctypes.c_int32, _P(ctypes.c_float)], ctypes.c_int),
+    "tn_trace": ([ctypes.c_void_p, ctypes.c_void_p, _P(ctypes.c_float), _P(ctypes.c_uint8), _P(ctypes.c_int32),
+                  ctypes.c_int64, ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_int32)], ctypes.c_int),
+    "tn_mlp_forward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                        ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "tn_mlp_backward": ([ctypes.c_void_p] * 7 + [ctypes.c_int32, ctypes.c_int64] + [ctypes.c_void_p] * 6,
+                        ctypes.c_int),
+    "tn_mlp_adam": ([ctypes.c_void_p] * 4 + [ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                             ctypes.c_float, ctypes.c_void_p], ctypes.c_int),
     "tn_step": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                  ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                  ctypes.c_void_p], ctypes.c_int),
@@ -325,6 +338,88 @@ def step(A, rA: int, B, rB: int, s: int, maskA: int, prime: int = None, kernel: 
     _check(load().tn_step(A.ctypes.data, rA, B.ctypes.data, rB, s, maskA, ARITH["u64" if u64 else "rns"],
                           0 if u64 else prime, kc, C.ctypes.data, ptr, nb, current_stream_handle()), "tn_step")
     return C
+
+
+# ------------------------------------------------------------ learned order
+N_FEATURES = 10
+HIDDEN = 128
+
+
+class Model:
+    """Host handle of the order-scoring perceptron (tn_model_*)."""
+
+    def __init__(self, params=None):
+        import numpy as np
+        lib = load()
+        self.n_params = int(lib.tn_model_param_count())
+        h = ctypes.c_void_p()
+        if params is None:
+            _check(lib.tn_model_create(None, ctypes.byref(h)), "tn_model_create")
+        else:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            assert p.size == self.n_params
+            _check(lib.tn_model_create(p.ctypes.data_as(_P(ctypes.c_float)), ctypes.byref(h)), "tn_model_create")
+        self.h = h
+
+    @classmethod
+    def load_file(cls, path):
+        import numpy as np
+        return cls(np.load(path))
+
+    def params(self):
+        import numpy as np
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(load().tn_model_get(self.h, out.ctypes.data_as(_P(ctypes.c_float))), "tn_model_get")
+        return out
+
+    def score(self, x):
+        import numpy as np
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, N_FEATURES)
+        y = np.empty(x.shape[0], dtype=np.float32)
+        _check(load().tn_model_score(self.h, x.ctypes.data_as(_P(ctypes.c_float)), x.shape[0],
+                                     y.ctypes.data_as(_P(ctypes.c_float))), "tn_model_score")
+        return y
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.tn_model_free(self.h)
+            self.h = None
+
+
+def trace(net: Network, teacher: Plan):
+    """(features [rows x 10] float32, labels [rows] uint8, groups [states+1] int32)."""
+    import numpy as np
+    lib = load()
+    nr, ng = ctypes.c_int64(), ctypes.c_int32()
+    st = lib.tn_trace(net.h, teacher.h, None, None, None, 0, 0, ctypes.byref(nr), ctypes.byref(ng))
+    if st not in (TN_OK, -6):
+        _check(st, "tn_trace")
+    f = np.empty((max(1, nr.value), N_FEATURES), dtype=np.float32)
+    l = np.empty(max(1, nr.value), dtype=np.uint8)
+    g = np.empty(ng.value + 1, dtype=np.int32)
+    _check(lib.tn_trace(net.h, teacher.h, f.ctypes.data_as(_P(ctypes.c_float)), l.ctypes.data_as(_P(ctypes.c_uint8)),
+                        g.ctypes.data_as(_P(ctypes.c_int32)), nr.value, ng.value + 1, ctypes.byref(nr),
+                        ctypes.byref(ng)), "tn_trace")
+    return f[:nr.value], l[:nr.value], g
+
+
+def mlp_forward(params, x, h1, h2, y):
+    """GPU forward (torch tensors on the device; argument marshalling only)."""
+    _check(load().tn_mlp_forward(params.data_ptr(), x.data_ptr(), x.shape[0], h1.data_ptr(), h2.data_ptr(),
+                                 y.data_ptr(), current_stream_handle()), "tn_mlp_forward")
+
+
+def mlp_backward(params, x, h1, h2, y, labels, groups, grad, dz2, dz1, dy, loss):
+    n_groups = groups.numel() - 1
+    _check(load().tn_mlp_backward(params.data_ptr(), x.data_ptr(), h1.data_ptr(), h2.data_ptr(), y.data_ptr(),
+                                  labels.data_ptr(), groups.data_ptr(), n_groups, x.shape[0], grad.data_ptr(),
+                                  dz2.data_ptr(), dz1.data_ptr(), dy.data_ptr(), loss.data_ptr(),
+                                  current_stream_handle()), "tn_mlp_backward")
+
+
+def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(load().tn_mlp_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), step, lr, beta1, beta2,
+                              eps, current_stream_handle()), "tn_mlp_adam")
 
 
 def primes(k: int) -> List[int]:
