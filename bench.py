@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--order", default="best")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned vs greedy comparison")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--single", action="store_true", help="count one formula at a time instead of the batch API")
     return ap.parse_args()
@@ -105,6 +106,48 @@ def cpu_baseline(formula, plan_steps, n_primes, budget_s):
                        f"({time.process_time() - t0:.1f}s CPU); instance time extrapolated linearly in "
                        f"multiply-adds and primes"),
             "extrapolated_instance_s": inst_s}
+
+
+LEARNED_HELDOUT = [1, 4, 6, 9, 12, 15, 16, 18, 22, 23]
+
+
+def learned_vs_greedy(tn, I, ws, log):
+    """Order + contraction wall time of greedy, the learned scorer alone and
+    the judged learned order on held-out 1-in-3 instances (n in [100, 180],
+    alpha = 0.66) where greedy stays within the rank cap."""
+    import torch
+    model_path = os.path.join(ROOT, "paper_1805_00475_amd", "models", "order_mlp.npy")
+    if not os.path.exists(model_path):
+        return None
+    model = tn.Model.load_file(model_path)
+    res = {}
+    counts = {}
+    for kind in ("greedy", "learned_raw", "learned"):
+        order_s = contract_s = 0.0
+        cs = []
+        for i in LEARNED_HELDOUT:
+            f = I.learned_instance(i, "heldout")
+            net = tn.Network(f)
+            t0 = time.perf_counter()
+            plan = net.order(kind, seed=i, model=model if "learned" in kind else None)
+            t1 = time.perf_counter()
+            tn.count_plan(net, plan, workspace=ws)  # warm
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            cs.append(tn.count_plan(net, plan, workspace=ws))
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            order_s += t1 - t0
+            contract_s += t3 - t2
+        counts[kind] = cs
+        res[kind] = {"order_ms": round(1000 * order_s, 3), "contract_ms": round(1000 * contract_s, 3),
+                     "total_ms": round(1000 * (order_s + contract_s), 3)}
+    if not (counts["greedy"] == counts["learned_raw"] == counts["learned"]):
+        raise SystemExit("learned and greedy orders disagree on a count")
+    res["instances"] = f"held-out learned_instance {LEARNED_HELDOUT}"
+    res["learned_over_greedy_speedup"] = round(res["greedy"]["total_ms"] / res["learned_raw"]["total_ms"], 3)
+    log("learned vs greedy done")
+    return res
 
 
 def main():
@@ -168,6 +211,7 @@ def main():
                      "avg_launch_us": round(1000.0 * v["ms"] / v["launches"], 3)}
                  for k, v in prof.items() if v["launches"]}
 
+    lvg = learned_vs_greedy(tn, I, ws, log) if not args.no_learned else None
     plans = [tn.Network(f).order(args.order, seed=i) for i, f in enumerate(formulas[:4])]
     out = {
         "metric": "exact counts/sec + contraction HBM GB/s; learned vs greedy order wall-time",
@@ -180,6 +224,7 @@ def main():
         "roofline": roofline,
         "hbm_roofline_stream": roofline_of("stream", prof["stream"]) if prof["stream"]["launches"] else None,
         "kernel_classes": per_class,
+        "learned_vs_greedy": lvg,
         "plan_max_rank": [p.stats["max_rank"] for p in plans],
         "plan_chosen": [p.stats["chosen"] for p in plans],
     }
