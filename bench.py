@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--order", default="best")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned vs greedy comparison")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device (a plain copy kernel of known size, used to scale "
+                         "hardware byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--single", action="store_true", help="count one formula at a time instead of the batch API")
     return ap.parse_args()
@@ -175,6 +178,12 @@ def main():
                     f"residues mod ceil(n/31)+1 primes")
     ws = tn.default_workspace()
     ws.get(64 << 30)
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def one_pass(flags=0):
         if args.single:
