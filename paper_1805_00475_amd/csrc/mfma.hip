@@ -86,6 +86,36 @@ __device__ __forceinline__ uint32_t combine_digits(const int32_t T[7], uint32_t 
 
 constexpr int kFlushChunks = (1 << 14) / 64;  // K chunks of 64 per exact int32 accumulation
 
+// Tile traversal. Work-groups are dealt to the 8 XCDs round-robin, so tile
+// t runs on XCD t % 8. Each XCD owns a band of A tiles (or of B tiles when
+// there are fewer than 8 A tiles) and walks it in groups of up to 8 tiles of
+// that side: the group stays in the XCD's L2 while the other operand's tiles
+// stream past it once per group.
+__device__ __forceinline__ void tile_coords(uint64_t tile, uint64_t tilesA, uint64_t tilesB, uint64_t& ta,
+                                            uint64_t& tb) {
+    if (tilesA < 8 && tilesB < 8) {
+        ta = tile % tilesA;
+        tb = tile / tilesA;
+        return;
+    }
+    const uint64_t x = tile & 7, j = tile >> 3;
+    if (tilesA >= 8) {
+        const uint64_t per = tilesA >> 3;
+        const uint64_t gm = per < 8 ? per : 8;
+        const uint64_t span = gm * tilesB;
+        const uint64_t group = j / span, r = j % span;
+        ta = x * per + group * gm + r % gm;
+        tb = r / gm;
+    } else {
+        const uint64_t per = tilesB >> 3;
+        const uint64_t gn = per < 8 ? per : 8;
+        const uint64_t span = gn * tilesA;
+        const uint64_t group = j / span, r = j % span;
+        tb = x * per + group * gn + r % gn;
+        ta = r / gn;
+    }
+}
+
 __device__ __forceinline__ void flush(v4i (&acc)[7][2][2], uint32_t (&racc)[2][2][4], uint32_t p, uint32_t r2,
                                       uint64_t off) {
 #pragma unroll
@@ -147,11 +177,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex) 
     __syncthreads();
 
     for (uint64_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
-        // XCD-aware order: blocks on one XCD (blockIdx % 8) walk a contiguous
-        // band of tiles that share the same B tile
-        uint64_t tt = tile;
-        if ((T & 7) == 0) tt = (tile & 7) * (T >> 3) + (tile >> 3);
-        const uint64_t ta = tt % tilesA, tb = tt / tilesA;
+        uint64_t ta, tb;
+        tile_coords(tile, tilesA, tilesB, ta, tb);
         const uint64_t xA0 = ta * kBM, xB0 = tb * kBN;
         const uint8_t* gA = A + xA0 * rowBytes;
         const uint8_t* gB = B + xB0 * rowBytes;
