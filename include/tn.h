@@ -99,6 +99,7 @@ typedef struct {
     uint64_t peak_elems;           /* arena high-water mark in entries, one prime */
     int32_t chosen;                /* tn_order_kind that produced the plan */
     int32_t fallback;              /* 1 when the learned order lost to the judge */
+    int32_t refined;               /* 1 when local tree reconfiguration improved the plan */
 } tn_plan_stats;
 
 typedef enum { TN_ARITH_AUTO = 0, TN_ARITH_U64 = 1, TN_ARITH_RNS = 2 } tn_arith;

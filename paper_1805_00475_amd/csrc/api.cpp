@@ -13,6 +13,8 @@ namespace tn {
 constexpr int kPartitionTrials = 16;
 // host microseconds of order search allowed per predicted device microsecond
 constexpr double kSearchRatio = 4.0;
+// most host time spent reconfiguring one plan
+constexpr double kRefineCapUs = 400000.0;
 
 tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out) {
     try {
@@ -81,6 +83,17 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             consider(plan_of(TN_ORDER_COMMUNITY, p), p);
         }
         for (int t = 4; t < kPartitionTrials && !over_budget(); ++t) partition_trial(t);
+        // local reconfiguration of the winner's contraction tree
+        if (have && out.merges.size() > 2) {
+            const double budget = std::min(kRefineCapUs, kSearchRatio * planes * plan_cost(out));
+            Plan p;
+            const int32_t chosen = out.stats.chosen;
+            if (make_plan(N, refine_order(N, out.merges, budget), chosen, p) == TN_OK &&
+                plan_cost(p) < plan_cost(out)) {
+                p.stats.refined = 1;
+                out = std::move(p);
+            }
+        }
         if (kind == TN_ORDER_LEARNED) {
             bool ok = false;
             auto lm = order_learned(N, model, &ok);

@@ -90,6 +90,12 @@ Reduced absorb_small(const Network& net);
 tn_status make_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>> merges,
                     int32_t chosen, Plan& plan);
 double plan_cost(const Plan& plan);
+double step_cost_model(int rA, int rB, int s, int rC);  // microseconds, one prime
+// order_refine.cpp: exact re-optimization of subtrees with up to 8 frontier
+// nodes, sweeping the largest tensors first, within budget_us
+std::vector<std::pair<int32_t, int32_t>> refine_order(const Network& net,
+                                                      const std::vector<std::pair<int32_t, int32_t>>& merges,
+                                                      double budget_us);
 tn_status verify_plan(const Plan& plan);
 
 // api.cpp: order of any kind (with the judge for BEST / LEARNED) + plan

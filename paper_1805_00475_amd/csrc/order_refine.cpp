@@ -1,0 +1,236 @@
+// Local refinement of a contraction tree.
+//
+// A plan's merges form a binary tree whose leaves are the original
+// tensors. Any subtree, cut at some frontier of k nodes (leaves or deeper
+// subtrees kept as they are), produces the same tensor whatever binary tree
+// joins its k frontier nodes: the result's bonds are those of the frontier
+// that leave the subtree. So the subtree's internal order can be replaced
+// by the cheapest one, found exactly by dynamic programming over the 2^k
+// subsets of the frontier (k <= 8), without changing the rest of the plan or
+// the count. The cost of a merge is the plan's cost model; the frontier is
+// grown from the subtree's root by opening the highest-rank internal node
+// first. Sweeps over all internal nodes repeat while they improve the
+// plan, within a time budget.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace tn {
+
+double step_cost_model(int rA, int rB, int s, int rC);
+
+namespace {
+
+struct Tree {
+    int32_t n_leaves = 0, words = 0;
+    std::vector<int32_t> left, right, parent;  // per node id; leaves have -1 children
+    std::vector<uint64_t> bonds;              // words per node
+    int32_t root = -1;
+    uint64_t* b(int32_t v) { return bonds.data() + size_t(v) * words; }
+    int rank(int32_t v) const {
+        int c = 0;
+        for (int i = 0; i < words; ++i) c += __builtin_popcountll(bonds[size_t(v) * words + i]);
+        return c;
+    }
+};
+
+constexpr int kMaxFrontier = 8;
+
+// set per refinement (per thread: orders are searched on worker threads):
+// no intermediate may exceed the plan's largest rank
+thread_local int g_rank_cap = 64;
+
+double merge_cost(int ra, int rb, int rc) {
+    const double c = step_cost_model(ra, rb, (ra + rb - rc) / 2, rc);
+    return rc > g_rank_cap ? c + 1e15 : c;
+}
+
+double subtree_cost(Tree& t, int32_t v, const std::vector<char>& is_frontier) {
+    if (is_frontier[v] || t.left[v] < 0) return 0.0;
+    const int32_t a = t.left[v], c = t.right[v];
+    return subtree_cost(t, a, is_frontier) + subtree_cost(t, c, is_frontier) +
+           merge_cost(t.rank(a), t.rank(c), t.rank(v));
+}
+
+void collect_internal(Tree& t, int32_t v, const std::vector<char>& is_frontier, std::vector<int32_t>& out) {
+    if (is_frontier[v] || t.left[v] < 0) return;
+    out.push_back(v);
+    collect_internal(t, t.left[v], is_frontier, out);
+    collect_internal(t, t.right[v], is_frontier, out);
+}
+
+// Try to improve the subtree rooted at v; returns true when it changed.
+bool reconfigure(Tree& t, int32_t v, std::vector<char>& is_frontier) {
+    if (t.left[v] < 0) return false;
+    // grow the frontier from v's children, opening the highest-rank
+    // internal node first
+    std::vector<int32_t> fr = {t.left[v], t.right[v]};
+    while (int(fr.size()) < kMaxFrontier) {
+        int best = -1, br = -1;
+        for (int i = 0; i < int(fr.size()); ++i)
+            if (t.left[fr[i]] >= 0 && t.rank(fr[i]) > br) {
+                br = t.rank(fr[i]);
+                best = i;
+            }
+        if (best < 0) break;
+        const int32_t x = fr[size_t(best)];
+        fr[size_t(best)] = t.left[x];
+        fr.push_back(t.right[x]);
+    }
+    const int k = int(fr.size());
+    if (k <= 2) return false;
+    for (int32_t x : fr) is_frontier[x] = 1;
+    const double old_cost = subtree_cost(t, v, is_frontier);
+    std::vector<int32_t> old_internal;
+    collect_internal(t, v, is_frontier, old_internal);
+    // DP over subsets of the frontier
+    const int S = 1 << k;
+    const int W = t.words;
+    std::vector<uint64_t> sb(size_t(S) * W, 0);
+    std::vector<int> sr(S, 0);
+    std::vector<double> cost(S, 0.0);
+    std::vector<int> split(S, 0);
+    for (int m = 1; m < S; ++m) {
+        const int low = __builtin_ctz(m);
+        const int rest = m & (m - 1);
+        const uint64_t* lb = t.b(fr[size_t(low)]);
+        for (int i = 0; i < W; ++i) sb[size_t(m) * W + i] = sb[size_t(rest) * W + i] ^ lb[i];
+        int c = 0;
+        for (int i = 0; i < W; ++i) c += __builtin_popcountll(sb[size_t(m) * W + i]);
+        sr[m] = c;
+        if (rest == 0) continue;  // a single frontier node
+        double best = 1e300;
+        int bs = 0;
+        // splits m = a | (m ^ a) with a containing the lowest element
+        for (int a = (m - 1) & m; a > 0; a = (a - 1) & m) {
+            if (!(a & (1 << low))) continue;
+            const int bb = m ^ a;
+            const double cst = cost[a] + cost[bb] + merge_cost(sr[a], sr[bb], c);
+            if (cst < best) {
+                best = cst;
+                bs = a;
+            }
+        }
+        cost[m] = best;
+        split[m] = bs;
+    }
+    const int full = S - 1;
+    bool changed = false;
+    if (cost[full] < old_cost * (1.0 - 1e-9)) {
+        // rebuild: reuse the k-1 internal node ids (v stays the root)
+        std::vector<int32_t> pool;
+        for (int32_t x : old_internal)
+            if (x != v) pool.push_back(x);
+        // recursive assembly
+        struct Builder {
+            Tree& t;
+            const std::vector<int32_t>& fr;
+            const std::vector<int>& split;
+            const std::vector<uint64_t>& sb;
+            std::vector<int32_t>& pool;
+            int32_t make(int m, int32_t id) {
+                if ((m & (m - 1)) == 0) return fr[size_t(__builtin_ctz(m))];
+                const int a = split[m], bb = m ^ a;
+                const int32_t na = (a & (a - 1)) == 0 ? fr[size_t(__builtin_ctz(a))] : take();
+                const int32_t nb = (bb & (bb - 1)) == 0 ? fr[size_t(__builtin_ctz(bb))] : take();
+                if (na >= t.n_leaves && (a & (a - 1)) != 0) make(a, na);
+                if (nb >= t.n_leaves && (bb & (bb - 1)) != 0) make(bb, nb);
+                t.left[id] = na;
+                t.right[id] = nb;
+                t.parent[na] = id;
+                t.parent[nb] = id;
+                std::memcpy(t.b(id), sb.data() + size_t(m) * t.words, sizeof(uint64_t) * t.words);
+                return id;
+            }
+            int32_t take() {
+                int32_t x = pool.back();
+                pool.pop_back();
+                return x;
+            }
+        } bld{t, fr, split, sb, pool};
+        bld.make(full, v);
+        changed = true;
+    }
+    for (int32_t x : fr) is_frontier[x] = 0;
+    return changed;
+}
+
+}  // namespace
+
+std::vector<std::pair<int32_t, int32_t>> refine_order(const Network& net,
+                                                      const std::vector<std::pair<int32_t, int32_t>>& merges,
+                                                      double budget_us) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int32_t n0 = int32_t(net.t.size());
+    const int32_t n = n0 + int32_t(merges.size());
+    if (merges.size() < 2) return merges;
+    Tree t;
+    t.n_leaves = n0;
+    t.words = int32_t((net.bond_end.size() + 63) / 64) + 1;
+    t.left.assign(n, -1);
+    t.right.assign(n, -1);
+    t.parent.assign(n, -1);
+    t.bonds.assign(size_t(n) * t.words, 0);
+    for (int32_t i = 0; i < n0; ++i)
+        for (int32_t bnd : net.t[i].bonds) t.b(i)[bnd >> 6] ^= uint64_t(1) << (bnd & 63);
+    for (int32_t k = 0; k < int32_t(merges.size()); ++k) {
+        const int32_t v = n0 + k, a = merges[k].first, c = merges[k].second;
+        t.left[v] = a;
+        t.right[v] = c;
+        t.parent[a] = t.parent[c] = v;
+        for (int i = 0; i < t.words; ++i) t.b(v)[i] = t.b(a)[i] ^ t.b(c)[i];
+    }
+    t.root = n - 1;
+    int maxr = 0;
+    for (int32_t v = 0; v < n; ++v) maxr = std::max(maxr, t.rank(v));
+    g_rank_cap = maxr;  // keep peak memory: never raise the largest rank
+    std::vector<char> is_frontier(n, 0);
+    for (int sweep = 0; sweep < 4; ++sweep) {
+        bool any = false;
+        // largest tensors first: their subtrees dominate the cost
+        std::vector<int32_t> nodes;
+        for (int32_t v = n0; v < n; ++v) nodes.push_back(v);
+        std::sort(nodes.begin(), nodes.end(), [&](int32_t x, int32_t y) { return t.rank(x) > t.rank(y); });
+        for (int32_t v : nodes) {
+            any |= reconfigure(t, v, is_frontier);
+            const double spent =
+                std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+            if (spent > budget_us) {
+                any = false;
+                break;
+            }
+        }
+        if (!any) break;
+    }
+    // post-order from the root; new merge ids are assigned in that order
+    std::vector<std::pair<int32_t, int32_t>> out;
+    out.reserve(merges.size());
+    std::vector<int32_t> newid(n, -1);
+    for (int32_t i = 0; i < n0; ++i) newid[i] = i;
+    int32_t next = n0;
+    std::vector<std::pair<int32_t, int>> st = {{t.root, 0}};
+    while (!st.empty()) {
+        auto& top = st.back();
+        const int32_t v = top.first;
+        if (v < n0) {
+            st.pop_back();
+            continue;
+        }
+        if (top.second == 0) {
+            top.second = 1;
+            st.push_back({t.right[v], 0});
+            st.push_back({t.left[v], 0});
+            continue;
+        }
+        st.pop_back();
+        const int32_t a = newid[t.left[v]], c = newid[t.right[v]];
+        out.push_back({std::min(a, c), std::max(a, c)});
+        newid[v] = next++;
+    }
+    return out;
+}
+
+}  // namespace tn

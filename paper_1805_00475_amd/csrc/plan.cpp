@@ -76,22 +76,29 @@ struct Arena {
 
 }  // namespace
 
-// Predicted device time in microseconds under a simple model: a step moves
-// 4 (2^rA + 2^rB + 2^rC) bytes at ~5 TB/s, does 2^(rA+rB-s) modular
-// multiply-adds at ~4e12/s on vector units, or ~1e14/s when it is wide
-// enough for the int8-limb matrix path, and pays ~2 us of launch overhead.
-static double step_cost_us(int rA, int rB, int s, int rC) {
-    double bytes = 4.0 * (std::ldexp(1.0, rA) + std::ldexp(1.0, rB) + std::ldexp(1.0, rC));
-    double macs = std::ldexp(1.0, rA + rB - s);
-    bool dense = s >= 6 && (rA - s) >= 4 && (rB - s) >= 4;
-    double t_mem = bytes / 5e12;
-    double t_mac = macs / (dense ? 1e14 : 4e12);
-    return 1e6 * std::max(t_mem, t_mac) + 2.0;
+// Predicted device time in microseconds of one step for one prime, from
+// the kernels' measured rates on MI355X: dense steps (the int8-limb MFMA
+// path: s >= 6, larger free side >= 7 bits, smaller >= 6) run at ~8e13
+// modular multiply-adds/s plus a digit pass over both operands; other wide
+// steps (s >= 6) at ~1e12 on vector units; streaming steps move
+// 4 (2^rA + 2^rB + 2^rC) bytes at ~2.5e12 B/s; every launch costs ~3 us.
+double step_cost_model(int rA, int rB, int s, int rC) {
+    const double bytes = 4.0 * (std::ldexp(1.0, rA) + std::ldexp(1.0, rB) + std::ldexp(1.0, rC));
+    const double macs = std::ldexp(1.0, rA + rB - s);
+    const int fa = std::max(rA, rB) - s, fb = std::min(rA, rB) - s;
+    double t;
+    if (s >= 6 && fa >= 7 && fb >= 6)
+        t = macs / 8e13 + 2.0 * 4.0 * (std::ldexp(1.0, rA) + std::ldexp(1.0, rB)) / 4e12 + 4.0 * std::ldexp(1.0, rC) / 2.5e12;
+    else if (s >= 6)
+        t = std::max(macs / 1e12, bytes / 2.5e12);
+    else
+        t = std::max(bytes / 2.5e12, macs / 4e12);
+    return 1e6 * t + 3.0;
 }
 
 double plan_cost(const Plan& plan) {
     double t = 0;
-    for (const Step& st : plan.steps) t += step_cost_us(st.rA, st.rB, st.s, st.rC);
+    for (const Step& st : plan.steps) t += step_cost_model(st.rA, st.rB, st.s, st.rC);
     return t;
 }
 

@@ -44,7 +44,7 @@ class Formula_c(ctypes.Structure):
 class PlanStats_c(ctypes.Structure):
     _fields_ = [("n_steps", ctypes.c_int32), ("max_rank", ctypes.c_int32), ("entries", ctypes.c_double),
                 ("macs", ctypes.c_double), ("log2_cost", ctypes.c_double), ("peak_elems", ctypes.c_uint64),
-                ("chosen", ctypes.c_int32), ("fallback", ctypes.c_int32)]
+                ("chosen", ctypes.c_int32), ("fallback", ctypes.c_int32), ("refined", ctypes.c_int32)]
 
 
 class ContractOpts_c(ctypes.Structure):
@@ -143,7 +143,7 @@ class _FormulaArrays:
 def _stats_dict(s: PlanStats_c) -> dict:
     return {"n_steps": s.n_steps, "max_rank": s.max_rank, "entries": s.entries, "macs": s.macs,
             "log2_cost": s.log2_cost, "peak_elems": int(s.peak_elems), "chosen": ORDER_NAMES.get(s.chosen, s.chosen),
-            "fallback": bool(s.fallback)}
+            "fallback": bool(s.fallback), "refined": bool(s.refined)}
 
 
 class Network:
