@@ -192,6 +192,15 @@ typedef struct {
     double macs;
 } tn_kernel_profile;
 tn_status tn_profile_get(tn_kernel_profile* out /* TN_KERNEL_CLASSES entries */);
+/* The individual launches of that record (at most 2^20), in launch order:
+ * kernel class, step shape and device time. *n receives the count. */
+typedef struct {
+    int32_t kernel_class;
+    int32_t rA, rB, s, rC;
+    int32_t planes;
+    double ms;
+} tn_launch_record;
+tn_status tn_profile_launches(tn_launch_record* out, int64_t cap, int64_t* n);
 
 /* One contraction step from host buffers (test and measurement hook):
  *     C[c] = sum over z < 2^s of A[z + 2^s xA] * B[z + 2^s xB]

@@ -251,6 +251,8 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
                     bytes += es * std::ldexp(1.0, it.tlog) * 1.0;  // outputs written
                     macs += std::ldexp(1.0, it.tlog + it.s);
                 }
+            prof.cur_rA = prof.cur_rB = prof.cur_s = prof.cur_rC = 0;
+            prof.cur_G = int32_t(n);  // tiles in the wave
             prof.before(stream);
             const uint32_t grid = uint32_t(std::min<int64_t>((n + 3) / 4, 4096));
             hipLaunchKernelGGL(k_batch, dim3(grid), dim3(256), 0, stream, d_items + wave_off[L], n);

@@ -284,6 +284,11 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
     const double step_bytes =
         double(es) * G * (std::ldexp(1.0, st0.rA) + std::ldexp(1.0, st0.rB) + std::ldexp(1.0, st0.rC));
     const double step_macs = double(G) * std::ldexp(1.0, st0.rA + st0.rB - st0.s);
+    prof.cur_rA = st0.rA;
+    prof.cur_rB = st0.rB;
+    prof.cur_s = st0.s;
+    prof.cur_rC = st0.rC;
+    prof.cur_G = G;
     Step st = st0;
     StepArgs a{};
     a.B = st.initB ? init_base + st.offB * es : arena_base + st.offB * es;
@@ -633,6 +638,16 @@ Profiler& profiler() {
     return p;
 }
 }  // namespace tn
+
+extern "C" tn_status tn_profile_launches(tn_launch_record* out, int64_t cap, int64_t* n) {
+    if (!n) return TN_EINVAL;
+    const auto& r = tn::profiler().recs;
+    *n = int64_t(r.size());
+    if (!out) return TN_OK;
+    if (cap < int64_t(r.size())) return TN_EBUFSIZE;
+    std::copy(r.begin(), r.end(), out);
+    return TN_OK;
+}
 
 extern "C" tn_status tn_profile_get(tn_kernel_profile* out) {
     if (!out) return TN_EINVAL;

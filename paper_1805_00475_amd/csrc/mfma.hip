@@ -76,12 +76,23 @@ constexpr int kBM = 128, kBN = 64, kRowB = 256 + 16;  // LDS row stride (bytes)
 constexpr int kBuf = (kBM + kBN) * kRowB;             // one LDS buffer
 constexpr int kThreads = 512;
 
+// V = sum_t 2^(8t) T_t is congruent to sum_t T_t w_t with w_t = 2^(8t) mod p:
+// w_0..w_3 = 1, 2^8, 2^16, 2^24 and w_4..w_6 = r, r 2^8, r 2^16 with
+// r = 2^32 mod p < 2^12. Every |T_t| < 2^30 (|T_6| < 2^26), so every term is
+// below 2^55 in magnitude and seven signed 32x32->64 multiply-adds are
+// exact; adding off (a multiple of p of at least 2^59) makes the sum
+// positive for the folding reduction.
 __device__ __forceinline__ uint32_t combine_digits(const int32_t T[7], uint32_t p, uint32_t r, uint64_t off) {
-    const int64_t lo = int64_t(T[0]) + (int64_t(T[1]) << 8) + (int64_t(T[2]) << 16) + (int64_t(T[3]) << 24);
-    const int64_t hi = int64_t(T[4]) + (int64_t(T[5]) << 8) + (int64_t(T[6]) << 16);
-    const uint64_t y = uint64_t(lo + hi * int64_t(r)) + off;
+    const int32_t ri = int32_t(r);
+    int64_t x = int64_t(T[0]);
+    x += int64_t(T[1]) * 256;
+    x += int64_t(T[2]) * 65536;
+    x += int64_t(T[3]) * 16777216;
+    x += int64_t(T[4]) * int64_t(ri);
+    x += int64_t(T[5]) * int64_t(ri << 8);
+    x += int64_t(T[6]) * int64_t(ri << 16);
     const ModP m{p, r};
-    return m.finish(y);
+    return m.finish(uint64_t(x) + off);
 }
 
 constexpr int kFlushChunks = (1 << 14) / 64;  // K chunks of 64 per exact int32 accumulation

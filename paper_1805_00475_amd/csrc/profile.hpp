@@ -19,7 +19,11 @@ struct Profiler {
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     std::vector<int> cls;
+    std::vector<tn_launch_record> recs;     // every launch of the record, in order
+    std::vector<tn_launch_record> pending;  // shapes of launches not yet timed
     tn_kernel_profile acc[TN_KERNEL_CLASSES]{};
+    // shape of the step being launched (set by the launcher)
+    int32_t cur_rA = 0, cur_rB = 0, cur_s = 0, cur_rC = 0, cur_G = 0;
 
     hipEvent_t ev() {
         if (used == pool.size()) {
@@ -34,6 +38,8 @@ struct Profiler {
         on = enable;
         used = 0;
         cls.clear();
+        recs.clear();
+        pending.clear();
         for (auto& a : acc) a = tn_kernel_profile{};
     }
     void before(hipStream_t s) {
@@ -45,6 +51,14 @@ struct Profiler {
         acc[kc].launches += 1;
         acc[kc].bytes += bytes;
         acc[kc].macs += macs;
+        tn_launch_record r{};
+        r.kernel_class = kc;
+        r.rA = cur_rA;
+        r.rB = cur_rB;
+        r.s = cur_s;
+        r.rC = cur_rC;
+        r.planes = cur_G;
+        pending.push_back(r);
     }
     void after(hipStream_t s, int kc, const Step& st, int G, size_t es) {
         if (!on) return;
@@ -68,9 +82,14 @@ struct Profiler {
         for (size_t i = 0; i < cls.size() && 2 * i + 1 < used; ++i) {
             float ms = 0;
             if (hipEventElapsedTime(&ms, pool[2 * i], pool[2 * i + 1]) == hipSuccess) acc[cls[i]].ms += ms;
+            if (i < pending.size()) {
+                pending[i].ms = ms;
+                if (recs.size() < (size_t(1) << 20)) recs.push_back(pending[i]);
+            }
         }
         used = 0;
         cls.clear();
+        pending.clear();
     }
 };
 

@@ -53,6 +53,11 @@ class ContractOpts_c(ctypes.Structure):
                 ("prime_group", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
+class LaunchRecord_c(ctypes.Structure):
+    _fields_ = [("kernel_class", ctypes.c_int32), ("rA", ctypes.c_int32), ("rB", ctypes.c_int32),
+                ("s", ctypes.c_int32), ("rC", ctypes.c_int32), ("planes", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
 class KernelProfile_c(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double),
                 ("macs", ctypes.c_double)]
@@ -83,6 +88,7 @@ _SIGS = {
     "tn_crt": ([_P(ctypes.c_uint32), ctypes.c_int32, _P(ctypes.c_uint32), ctypes.c_size_t, _P(ctypes.c_size_t)],
                ctypes.c_int),
     "tn_profile_get": ([_P(KernelProfile_c)], ctypes.c_int),
+    "tn_profile_launches": ([_P(LaunchRecord_c), ctypes.c_int64, _P(ctypes.c_int64)], ctypes.c_int),
     "tn_model_param_count": ([], ctypes.c_int32),
     "tn_model_create": ([_P(ctypes.c_float), _P(ctypes.c_void_p)], ctypes.c_int),
     "tn_model_free": ([ctypes.c_void_p], None),
@@ -443,6 +449,15 @@ def profile() -> dict:
     _check(load().tn_profile_get(buf), "tn_profile_get")
     return {name: {"launches": buf[i].launches, "ms": buf[i].ms, "bytes": buf[i].bytes, "macs": buf[i].macs}
             for i, name in enumerate(KERNEL_CLASSES)}
+
+
+def launches() -> list:
+    """Per-launch records of the last timed call: (class, rA, rB, s, rC, planes, ms)."""
+    n = ctypes.c_int64()
+    _check(load().tn_profile_launches(None, 0, ctypes.byref(n)), "tn_profile_launches")
+    buf = (LaunchRecord_c * max(1, n.value))()
+    _check(load().tn_profile_launches(buf, n.value, ctypes.byref(n)), "tn_profile_launches")
+    return [(KERNEL_CLASSES[r.kernel_class], r.rA, r.rB, r.s, r.rC, r.planes, r.ms) for r in buf[:n.value]]
 
 
 def version() -> str:
