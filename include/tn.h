@@ -211,7 +211,7 @@ tn_status tn_profile_launches(tn_launch_record* out, int64_t cap, int64_t* n);
  * below 2^12) or uint64 wrapping (TN_ARITH_U64). ``kernel`` forces a
  * tn_kernel_class (-1 = the library's choice); TN_EUNSUPPORTED if that kernel
  * cannot run this shape. The workspace (device) must hold the three tensors,
- * each rounded up to 256 bytes, plus 512 KiB of scratch; A and B may be
+ * each rounded up to 256 bytes, plus 4 MiB of scratch; A and B may be
  * overwritten on the device. */
 tn_status tn_step(const void* A, int32_t rA, const void* B, int32_t rB, int32_t s, uint64_t maskA,
                   int32_t arith, uint32_t prime, int32_t kernel, void* C, void* workspace,

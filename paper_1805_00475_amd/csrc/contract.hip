@@ -343,7 +343,7 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
     }
     if ((force == KC_MFMA) || (force < 0 && !generic_only && can_mfma && !(flags & TN_FLAG_NO_MFMA))) {
         *kc = KC_MFMA;
-        return launch_mfma(a, G, stream, &prof, step_bytes, step_macs);
+        return launch_mfma(a, G, stream, &prof, step_bytes, step_macs, scratch, kScratchPerPrime);
     }
     if (force == KC_STREAM || (force < 0 && !generic_only && can_stream)) {
         const int nb = std::min(a.fB, 4);

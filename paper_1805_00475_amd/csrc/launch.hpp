@@ -11,9 +11,10 @@
 
 namespace tn {
 
-// split-K dot kernels: partial sums per block, in a scratch area per prime
+// scratch per prime: partial sums of the split-K dot kernels (1024 blocks x
+// 64 outputs x 8 B) and of split-K matrix-core steps (up to 2^20 residues)
 constexpr int kDotBlocks = 1024;
-constexpr int64_t kScratchPerPrime = int64_t(kDotBlocks) * 64 * 8;
+constexpr int64_t kScratchPerPrime = int64_t(1) << 22;
 
 int64_t align256(int64_t b);
 

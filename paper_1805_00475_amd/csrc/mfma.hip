@@ -149,7 +149,8 @@ __device__ __forceinline__ void flush(v4i (&acc)[7][2][2], uint32_t (&racc)[2][2
             for (int cb = 0; cb < 2; ++cb) acc[t][rb][cb] = v4i{0, 0, 0, 0};
 }
 
-__global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex) {
+__global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, int splits, uint32_t* part,
+                                                      int64_t part_stride) {
     __shared__ __align__(16) uint8_t lds[2 * kBuf];
     __shared__ uint64_t hiOff[16];
     __shared__ uint32_t hiIJ[16][2];
@@ -165,7 +166,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex) 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (w & 3) * 32, wc = (w >> 2) * 32;
     const uint64_t rowBytes = uint64_t(4) << a.s;  // K entries of 4 bytes (4 digit planes)
-    const int nk = 1 << (a.s - 6);
+    const int nk_all = 1 << (a.s - 6);
+    // split-K: block row blockIdx.y owns chunks [kc0, kc0 + nk)
+    const int nk = nk_all / splits;
+    const int kc0 = int(blockIdx.y) * nk;
     const uint64_t tilesA = uint64_t(1) << (a.fA - 7), tilesB = uint64_t(1) << (a.fB - 6);
     const uint64_t T = tilesA * tilesB;
 
@@ -233,12 +237,12 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex) 
         *reinterpret_cast<uint4*>(sB_ + (ldRow + 32) * kRowB + ldCol) = pb1;                  \
     } while (0)
         __syncthreads();  // the previous tile's output staging is done with the LDS
-        TN_FETCH(0);
+        TN_FETCH(kc0);
         TN_STASH(0);
         __syncthreads();
         for (int kc = 0; kc < nk; ++kc) {
             const int buf = kc & 1;
-            if (kc + 1 < nk) TN_FETCH(kc + 1);
+            if (kc + 1 < nk) TN_FETCH(kc0 + kc + 1);
             const uint8_t* sA = lds + buf * kBuf;
             const uint8_t* sB = sA + kBM * kRowB;
             v4i fa[4][2], fb[4][2];
@@ -266,6 +270,25 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex) 
             __syncthreads();
         }
         // epilogue: lane holds rows 4 (lane / 16) + v, column lane % 16 of each 16x16 block
+        if (splits > 1) {
+            // partial residue of this K range, tile-local order (i, j)
+            uint32_t* pt = part + blockIdx.z * part_stride + (uint64_t(blockIdx.y) * T + tile) * (kBM * kBN);
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        int32_t Tt[7];
+#pragma unroll
+                        for (int t = 0; t < 7; ++t) Tt[t] = acc[t][rb][cb][v];
+                        const int i = wr + rb * 16 + 4 * (lane >> 4) + v;
+                        const int j = wc + cb * 16 + fr;
+                        const uint32_t x = combine_digits(Tt, p, r2, off) + racc[rb][cb][v];
+                        pt[i * kBN + j] = x >= p ? x - p : x;
+                    }
+            continue;
+        }
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -294,8 +317,29 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex) 
 #undef TN_STASH
 }
 
+// split-K: add the partial residues of every K range and scatter into C
+__global__ __launch_bounds__(256) void k_mfma_reduce(StepArgs a, const uint32_t* part, int64_t part_stride,
+                                                     int splits) {
+    const int g = blockIdx.z;
+    const uint32_t p = a.p[g];
+    uint32_t* C = static_cast<uint32_t*>(a.C) + g * a.strideC;
+    const uint64_t tilesA = uint64_t(1) << (a.fA - 7), tilesB = uint64_t(1) << (a.fB - 6);
+    const uint64_t T = tilesA * tilesB;
+    const uint64_t n = T * (kBM * kBN);
+    const uint32_t* pg = part + g * part_stride;
+    for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t tile = e / (kBM * kBN), loc = e % (kBM * kBN);
+        uint64_t sum = 0;
+        for (int y = 0; y < splits; ++y) sum += pg[(uint64_t(y) * T + tile) * (kBM * kBN) + loc];
+        uint64_t ta, tb;
+        tile_coords(tile, tilesA, tilesB, ta, tb);
+        const uint64_t i = loc / kBN, j = loc % kBN;
+        C[pdep64(ta * kBM + i, a.maskA) | pdep64(tb * kBN + j, a.maskB)] = uint32_t(sum % p);
+    }
+}
+
 hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
-                       double step_macs) {
+                       double step_macs, char* scratch, int64_t scratch_per_plane) {
     MfmaExtra ex{};
     for (int g = 0; g < G; ++g) {
         const uint64_t p = a.p[g];
@@ -317,9 +361,23 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* p
     // the digit pass reads and rewrites both operands in place
     prof->after_raw(stream, KC_DIGITS, 2.0 * 16.0 * double(nA + nB) * G, 0.0);
     const uint64_t T = (uint64_t(1) << (a.fA - 7)) * (uint64_t(1) << (a.fB - 6));
-    dim3 grid(uint32_t(std::min<uint64_t>(T, 1024)), 1, G);
+    // too few output tiles to fill the GPU: split K over block rows (powers
+    // of two, at most 128 partial tiles per plane in the scratch area, at
+    // least one 64-entry chunk each)
+    int splits = 1;
+    const int nk = 1 << (a.s - 6);
+    const uint64_t cap_tiles = uint64_t(scratch_per_plane) / (4 * kBM * kBN);
+    while (T * G * splits * 2 <= 1024 && splits * 2 <= nk && T * splits * 2 <= cap_tiles) splits *= 2;
+    uint32_t* part = reinterpret_cast<uint32_t*>(scratch);
+    const int64_t part_stride = scratch_per_plane / 4;
+    dim3 grid(uint32_t(std::min<uint64_t>(T, 1024)), uint32_t(splits), G);
     prof->before(stream);
-    hipLaunchKernelGGL(k_mfma, grid, dim3(kThreads), 0, stream, a, ex);
+    hipLaunchKernelGGL(k_mfma, grid, dim3(kThreads), 0, stream, a, ex, splits, part, part_stride);
+    if (splits > 1) {
+        const uint64_t n = T * (kBM * kBN);
+        dim3 gr(uint32_t(std::min<uint64_t>((n + 255) / 256, 4096)), 1, G);
+        hipLaunchKernelGGL(k_mfma_reduce, gr, dim3(256), 0, stream, a, part, part_stride, splits);
+    }
     prof->after_raw(stream, KC_MFMA, step_bytes, step_macs);
     return hipGetLastError();
 }

@@ -19,7 +19,8 @@ bool mfma_eligible(const StepArgs& a);
 struct Profiler;
 // Digit pass on both operands, then the GEMM; each launch is bracketed by
 // the profiler (no-op unless timing is on) with its algorithmic work.
+// scratch: scratch_per_plane bytes for each of the G planes (split-K partials)
 hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
-                       double step_macs);
+                       double step_macs, char* scratch, int64_t scratch_per_plane);
 
 }  // namespace tn

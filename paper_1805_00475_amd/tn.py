@@ -337,7 +337,7 @@ def step(A, rA: int, B, rB: int, s: int, maskA: int, prime: int = None, kernel: 
     rC = rA + rB - 2 * s
     C = np.empty(1 << rC, dtype=dt)
     es = 8 if u64 else 4
-    need = sum(((x * es + 255) // 256) * 256 for x in (1 << rA, 1 << rB, 1 << rC)) + (512 << 10)
+    need = sum(((x * es + 255) // 256) * 256 for x in (1 << rA, 1 << rB, 1 << rC)) + (4 << 20)
     ws = workspace or default_workspace()
     ptr, nb = ws.get(need)
     kc = -1 if kernel == "auto" else KERNEL_CLASSES.index(kernel)
