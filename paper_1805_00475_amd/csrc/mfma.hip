@@ -69,11 +69,22 @@ __global__ __launch_bounds__(256) void k_digits(uint32_t* X, int64_t stride, uin
 // --------------------------------------------------------------- GEMM
 // Work-group tile 128 (xA) x 64 (xB), 8 waves of 32 x 32 (two per SIMD), K
 // consumed in chunks of 64 entries (one 16x16x64 MFMA per digit pair and
-// 16x16 block). Digit tiles are double-buffered in LDS: the global loads of
-// chunk k+1 are issued before the MFMAs of chunk k and stored to the other
-// buffer after them, one barrier per chunk.
-constexpr int kBM = 128, kBN = 64, kRowB = 256 + 16;  // LDS row stride (bytes)
-constexpr int kBuf = (kBM + kBN) * kRowB;             // one LDS buffer
+// 16x16 block). Digit tiles go from global memory straight into LDS
+// (global_load_lds_dwordx4: one wave instruction fills 1 KiB, four 256-byte
+// rows) through three buffers, so the loads of chunk k+2 are in flight while
+// chunk k is multiplied: every chunk is first read by one of the work-groups
+// sharing it, which waits for HBM or the last-level cache, and one chunk of
+// look-ahead does not cover that latency. One barrier per chunk; the next
+// tile's first two chunks are requested before the current tile's epilogue.
+//
+// LDS rows are 256 bytes (one chunk of one row, 16 slots of 16 bytes) with
+// slot c of row r stored at slot c ^ (r % 16). A fragment read has the 16
+// lanes of a quarter-wave on 16 consecutive rows at one logical slot, so the
+// XOR spreads them over all 16 slots (all 64 banks): conflict-free. Plain
+// rows would put them on one slot.
+constexpr int kBM = 128, kBN = 64, kRowB = 256;  // LDS row stride (bytes)
+constexpr int kBuf = (kBM + kBN) * kRowB;        // one LDS buffer (48 KiB)
+constexpr int kStages = 3;
 constexpr int kThreads = 512;
 
 // V = sum_t 2^(8t) T_t is congruent to sum_t T_t w_t with w_t = 2^(8t) mod p:
@@ -149,12 +160,92 @@ __device__ __forceinline__ void flush(v4i (&acc)[7][2][2], uint32_t (&racc)[2][2
             for (int cb = 0; cb < 2; ++cb) acc[t][rb][cb] = v4i{0, 0, 0, 0};
 }
 
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// s_waitcnt immediate: vector memory count <= vm (0..63), LDS count 0
+constexpr int wait_vm_lgkm0(int vm) { return (vm & 15) | ((vm >> 4) << 14) | (7 << 4); }
+
+// Chunk barrier: the waiting wave's loads into LDS, except the newest VM of
+// them, have landed and its LDS reads have returned; then all waves meet.
+// After it, every wave's data of the awaited chunk is in LDS and no wave
+// still reads a buffer that is about to be refilled. The empty asm
+// statements keep the compiler from moving memory accesses across it; the
+// fence of __syncthreads is not used because it would also wait for the
+// loads still in flight.
+template <int VM>
+__device__ __forceinline__ void chunk_barrier() {
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(VM));
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
+// One chunk of a tile into LDS buffer `dst` (wave's 1 KiB slice): A rows
+// 4 (w + 8 i) + lane / 16 for i < 4, B rows 4 (w + 8 i) + lane / 16 for i < 2.
+__device__ __forceinline__ void fetch_chunk(const uint8_t* gA, const uint8_t* gB, uint64_t rows32, uint8_t* dst) {
+    __builtin_amdgcn_global_load_lds(gA, (lds_ptr_t)dst, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(gA + rows32, (lds_ptr_t)(dst + 8 * 1024), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(gA + 2 * rows32, (lds_ptr_t)(dst + 16 * 1024), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(gA + 3 * rows32, (lds_ptr_t)(dst + 24 * 1024), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(gB, (lds_ptr_t)(dst + kBM * kRowB), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(gB + rows32, (lds_ptr_t)(dst + kBM * kRowB + 8 * 1024), 16, 0, 0);
+}
+constexpr int kLoadsPerChunk = 6;
+
+// One K chunk: request the chunk at byte kb of the rows into LDS buffer
+// `dst` (wave slice; skipped when fetch is false) and multiply the chunk held
+// in buffer `src` into the shift-group accumulators. The buffers are
+// distinct, and the restrict qualifiers tell the compiler so: its wait-count
+// insertion otherwise makes every LDS read wait for all loads into LDS in
+// flight, which would undo the look-ahead. Ordering between chunks is kept
+// by chunk_barrier.
+__device__ __forceinline__ void chunk_step(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, bool fetch,
+                                           const uint8_t* gA, const uint8_t* gB, uint64_t kb, uint64_t rows32,
+                                           int wr, int wc, int fr, const int (&sw)[4], v4i (&acc)[7][2][2]) {
+    // A fragments are double-buffered in registers: the reads of digit i+1
+    // are issued before the 16 MFMAs of digit i, so that no MFMA waits for
+    // LDS after the chunk's first reads; B fragments are read once.
+    const uint8_t* rA = src + (wr + fr) * kRowB;        // A rows of block 0 (block 1: 16 rows on)
+    const uint8_t* rB = src + (kBM + wc + fr) * kRowB;  // B rows of block 0
+    auto ld = [](const uint8_t* q) { return *reinterpret_cast<const v4i*>(q); };
+    v4i fb[4][2], fx[2], fy[2];
+    fx[0] = ld(rA + sw[0]);
+    fx[1] = ld(rA + 16 * kRowB + sw[0]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        fb[j][0] = ld(rB + sw[j]);
+        fb[j][1] = ld(rB + 16 * kRowB + sw[j]);
+    }
+    fy[0] = ld(rA + sw[1]);
+    fy[1] = ld(rA + 16 * kRowB + sw[1]);
+    auto block = [&](int i, const v4i(&f)[2]) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    acc[i + j][rb][cb] =
+                        __builtin_amdgcn_mfma_i32_16x16x64_i8(f[rb], fb[j][cb], acc[i + j][rb][cb], 0, 0, 0);
+    };
+    block(0, fx);
+    if (fetch) fetch_chunk(gA + kb, gB + kb, rows32, dst);
+    fx[0] = ld(rA + sw[2]);
+    fx[1] = ld(rA + 16 * kRowB + sw[2]);
+    block(1, fy);
+    fy[0] = ld(rA + sw[3]);
+    fy[1] = ld(rA + 16 * kRowB + sw[3]);
+    block(2, fx);
+    block(3, fy);
+}
+
 __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, int splits, uint32_t* part,
                                                       int64_t part_stride) {
-    __shared__ __align__(16) uint8_t lds[2 * kBuf];
-    __shared__ uint64_t hiOff[16];
-    __shared__ uint32_t hiIJ[16][2];
-    uint32_t* sOut = reinterpret_cast<uint32_t*>(lds);  // kBM x kBN after the K loop
+    __shared__ __align__(1024) uint8_t lds[kStages * kBuf];
+    // output staging (kBM x kBN words) lives in the third buffer, so the next
+    // tile's first two chunks can load into the other two meanwhile
+    uint32_t* sOut = reinterpret_cast<uint32_t*>(lds + 2 * kBuf);
 
     const int g = blockIdx.z;
     const uint8_t* A = reinterpret_cast<const uint8_t*>(static_cast<const uint32_t*>(a.A) + g * a.strideA);
@@ -163,7 +254,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
     const uint32_t p = a.p[g], r2 = a.r2[g];
     const uint64_t off = ex.off[g];
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: LDS slice bases stay scalar
     const int wr = (w & 3) * 32, wc = (w >> 2) * 32;
     const uint64_t rowBytes = uint64_t(4) << a.s;  // K entries of 4 bytes (4 digit planes)
     const int nk_all = 1 << (a.s - 6);
@@ -172,32 +264,36 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
     const int kc0 = int(blockIdx.y) * nk;
     const uint64_t tilesA = uint64_t(1) << (a.fA - 7), tilesB = uint64_t(1) << (a.fB - 6);
     const uint64_t T = tilesA * tilesB;
+    if (uint64_t(blockIdx.x) >= T) return;  // whole work-group
 
-    // output mapping inside a tile: tile-local t = tid | q << 9 (q < 16),
-    // position pdep(t, TM), TM = the 7 lowest A bits and 6 lowest B bits of C
+    // output mapping inside a tile: tile-local t = 4 tid + k + 2048 q (k, q < 4)
+    // at position pdep(t, TM), TM = the 7 lowest A bits and 6 lowest B bits
+    // of C. The 6 lowest bits of C are always tile bits (at most 6 of them
+    // come from either side), so k adds to the position: each thread writes
+    // four consecutive words, one 16-byte store per q.
     const uint64_t TM = pdep64(127, a.maskA) | pdep64(63, a.maskB);
-    const uint64_t offLow = pdep64(uint64_t(tid), TM);
+    const uint64_t offLow = pdep64(uint64_t(4 * tid), TM);
     const uint32_t iLow = uint32_t(pext64(offLow, a.maskA)), jLow = uint32_t(pext64(offLow, a.maskB));
-    if (tid < 16) {
-        const uint64_t oh = pdep64(uint64_t(tid) << 9, TM);
-        hiOff[tid] = oh;
-        hiIJ[tid][0] = uint32_t(pext64(oh, a.maskA));
-        hiIJ[tid][1] = uint32_t(pext64(oh, a.maskB));
-    }
-    // raw digit copies: thread tid moves 16 B at row (tid / 16) + 32 q,
-    // byte (tid % 16) * 16 of the 256-byte chunk (A: q < 4, B: q < 2)
-    const int ldRow = tid >> 4, ldCol = (tid & 15) * 16;
-    const int kg = (lane >> 4) * 16;
+    // loads: lane l of wave w brings row ldRow = 4 w + l / 16 (+ 32 i) into
+    // physical slot l % 16, i.e. logical slot (l % 16) ^ (ldRow % 16)
+    const int ldRow = 4 * w + (lane >> 4);
+    const uint64_t ldOff = uint64_t(ldRow) * rowBytes + uint64_t(((lane & 15) ^ (ldRow & 15)) * 16);
+    const uint64_t rows32 = 32 * rowBytes;
+    uint8_t* const ldsW = lds + w * 1024;
     const int fr = lane & 15;
+    // fragment of digit d: logical slot 4 d + lane / 16 of row (.. + fr)
+    const int q4 = (lane >> 4) ^ fr;
+    const int sw[4] = {q4 * 16, (q4 ^ 4) * 16, (q4 ^ 8) * 16, (q4 ^ 12) * 16};
     __syncthreads();
 
-    for (uint64_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
-        uint64_t ta, tb;
-        tile_coords(tile, tilesA, tilesB, ta, tb);
-        const uint64_t xA0 = ta * kBM, xB0 = tb * kBN;
-        const uint8_t* gA = A + xA0 * rowBytes;
-        const uint8_t* gB = B + xB0 * rowBytes;
+    uint64_t tile = blockIdx.x, ta, tb;
+    tile_coords(tile, tilesA, tilesB, ta, tb);
+    const uint8_t* gA = A + ta * kBM * rowBytes + ldOff;
+    const uint8_t* gB = B + tb * kBN * rowBytes + ldOff;
+    fetch_chunk(gA + uint64_t(kc0) * 256, gB + uint64_t(kc0) * 256, rows32, ldsW);
+    if (nk > 1) fetch_chunk(gA + uint64_t(kc0 + 1) * 256, gB + uint64_t(kc0 + 1) * 256, rows32, ldsW + kBuf);
 
+    for (;;) {
         v4i acc[7][2][2];
         uint32_t racc[2][2][4];  // residues of the K chunks already flushed
 #pragma unroll
@@ -213,61 +309,33 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) racc[i][j][v] = 0;
 
-        // prefetch registers (named, so they stay in VGPRs)
-        uint4 pa0, pa1, pa2, pa3, pb0, pb1;
-#define TN_FETCH(kc_)                                                                         \
-    do {                                                                                      \
-        const uint64_t kb_ = uint64_t(kc_) * 256 + ldCol;                                     \
-        pa0 = *reinterpret_cast<const uint4*>(gA + uint64_t(ldRow) * rowBytes + kb_);         \
-        pa1 = *reinterpret_cast<const uint4*>(gA + uint64_t(ldRow + 32) * rowBytes + kb_);    \
-        pa2 = *reinterpret_cast<const uint4*>(gA + uint64_t(ldRow + 64) * rowBytes + kb_);    \
-        pa3 = *reinterpret_cast<const uint4*>(gA + uint64_t(ldRow + 96) * rowBytes + kb_);    \
-        pb0 = *reinterpret_cast<const uint4*>(gB + uint64_t(ldRow) * rowBytes + kb_);         \
-        pb1 = *reinterpret_cast<const uint4*>(gB + uint64_t(ldRow + 32) * rowBytes + kb_);    \
-    } while (0)
-#define TN_STASH(buf_)                                                                        \
-    do {                                                                                      \
-        uint8_t* sA_ = lds + (buf_) * kBuf;                                                   \
-        uint8_t* sB_ = sA_ + kBM * kRowB;                                                     \
-        *reinterpret_cast<uint4*>(sA_ + ldRow * kRowB + ldCol) = pa0;                         \
-        *reinterpret_cast<uint4*>(sA_ + (ldRow + 32) * kRowB + ldCol) = pa1;                  \
-        *reinterpret_cast<uint4*>(sA_ + (ldRow + 64) * kRowB + ldCol) = pa2;                  \
-        *reinterpret_cast<uint4*>(sA_ + (ldRow + 96) * kRowB + ldCol) = pa3;                  \
-        *reinterpret_cast<uint4*>(sB_ + ldRow * kRowB + ldCol) = pb0;                         \
-        *reinterpret_cast<uint4*>(sB_ + (ldRow + 32) * kRowB + ldCol) = pb1;                  \
-    } while (0)
-        __syncthreads();  // the previous tile's output staging is done with the LDS
-        TN_FETCH(kc0);
-        TN_STASH(0);
-        __syncthreads();
+        int buf = 0;  // kc % 3
         for (int kc = 0; kc < nk; ++kc) {
-            const int buf = kc & 1;
-            if (kc + 1 < nk) TN_FETCH(kc0 + kc + 1);
-            const uint8_t* sA = lds + buf * kBuf;
-            const uint8_t* sB = sA + kBM * kRowB;
-            v4i fa[4][2], fb[4][2];
-#pragma unroll
-            for (int d = 0; d < 4; ++d)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    fa[d][b] = *reinterpret_cast<const v4i*>(sA + (wr + b * 16 + fr) * kRowB + d * 64 + kg);
-                    fb[d][b] = *reinterpret_cast<const v4i*>(sB + (wc + b * 16 + fr) * kRowB + d * 64 + kg);
-                }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                        for (int cb = 0; cb < 2; ++cb)
-                            acc[i + j][rb][cb] =
-                                __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i][rb], fb[j][cb], acc[i + j][rb][cb], 0, 0, 0);
+            if (kc + 1 < nk)
+                chunk_barrier<kLoadsPerChunk>();
+            else
+                chunk_barrier<0>();
+            const int nb = buf == 0 ? 2 : buf - 1;  // (kc + 2) % 3
+            chunk_step(lds + buf * kBuf, ldsW + nb * kBuf, kc + 2 < nk, gA, gB, uint64_t(kc0 + kc + 2) * 256,
+                       rows32, wr, wc, fr, sw, acc);
             // every 2^14 entries of K, fold the exact int32 sums into residues
             // so they never exceed 2^30
             if (((kc + 1) & (kFlushChunks - 1)) == 0 && kc + 1 < nk) flush(acc, racc, p, r2, off);
-            if (kc + 1 < nk) TN_STASH(buf ^ 1);
-            __syncthreads();
+            buf = buf == 2 ? 0 : buf + 1;
+        }
+        // no wave reads this tile's chunks any more: buffers 0 and 1 may be
+        // refilled and buffer 2 may hold the output staging
+        chunk_barrier<0>();
+        const uint64_t next = tile + gridDim.x;
+        const bool more = next < T;
+        uint64_t nta = 0, ntb = 0;
+        const uint8_t *nA = gA, *nB = gB;
+        if (more) {
+            tile_coords(next, tilesA, tilesB, nta, ntb);
+            nA = A + nta * kBM * rowBytes + ldOff;
+            nB = B + ntb * kBN * rowBytes + ldOff;
+            fetch_chunk(nA + uint64_t(kc0) * 256, nB + uint64_t(kc0) * 256, rows32, ldsW);
+            if (nk > 1) fetch_chunk(nA + uint64_t(kc0 + 1) * 256, nB + uint64_t(kc0 + 1) * 256, rows32, ldsW + kBuf);
         }
         // epilogue: lane holds rows 4 (lane / 16) + v, column lane % 16 of each 16x16 block
         if (splits > 1) {
@@ -287,34 +355,44 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
                         const uint32_t x = combine_digits(Tt, p, r2, off) + racc[rb][cb][v];
                         pt[i * kBN + j] = x >= p ? x - p : x;
                     }
-            continue;
+        } else {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        int32_t Tt[7];
+#pragma unroll
+                        for (int t = 0; t < 7; ++t) Tt[t] = acc[t][rb][cb][v];
+                        const int i = wr + rb * 16 + 4 * (lane >> 4) + v;
+                        const int j = wc + cb * 16 + fr;
+                        const uint32_t x = combine_digits(Tt, p, r2, off) + racc[rb][cb][v];  // < 2p < 2^32
+                        sOut[i * kBN + j] = x >= p ? x - p : x;
+                    }
+            // staging complete (the next tile's loads may stay in flight)
+            chunk_barrier<63>();
+            const uint64_t baseC = pdep64(ta * kBM, a.maskA) | pdep64(tb * kBN, a.maskB);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t o = offLow | ex.hiOff[q];
+                const uint32_t i = iLow | ex.hiI[q];
+                const uint32_t j = jLow | ex.hiJ[q];
+                uint4 v;
+                v.x = sOut[i * kBN + j];
+                v.y = sOut[(i | ex.dI[1]) * kBN + (j | ex.dJ[1])];
+                v.z = sOut[(i | ex.dI[2]) * kBN + (j | ex.dJ[2])];
+                v.w = sOut[(i | ex.dI[3]) * kBN + (j | ex.dJ[3])];
+                *reinterpret_cast<uint4*>(C + (baseC | o)) = v;
+            }
         }
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    int32_t Tt[7];
-#pragma unroll
-                    for (int t = 0; t < 7; ++t) Tt[t] = acc[t][rb][cb][v];
-                    const int i = wr + rb * 16 + 4 * (lane >> 4) + v;
-                    const int j = wc + cb * 16 + fr;
-                    const uint32_t x = combine_digits(Tt, p, r2, off) + racc[rb][cb][v];  // < 2p < 2^32
-                    sOut[i * kBN + j] = x >= p ? x - p : x;
-                }
-        __syncthreads();
-        const uint64_t baseC = pdep64(xA0, a.maskA) | pdep64(xB0, a.maskB);
-#pragma unroll 4
-        for (int q = 0; q < 16; ++q) {
-            const uint64_t o = offLow | hiOff[q];
-            const uint32_t i = iLow | hiIJ[q][0];
-            const uint32_t j = jLow | hiIJ[q][1];
-            C[baseC | o] = sOut[i * kBN + j];
-        }
+        if (!more) break;
+        tile = next;
+        ta = nta;
+        tb = ntb;
+        gA = nA;
+        gB = nB;
     }
-#undef TN_FETCH
-#undef TN_STASH
 }
 
 // split-K: add the partial residues of every K range and scatter into C
@@ -344,6 +422,26 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* p
     for (int g = 0; g < G; ++g) {
         const uint64_t p = a.p[g];
         ex.off[g] = p * ((uint64_t(1) << 59) / p + 1);
+    }
+    auto pdep = [](uint64_t x, uint64_t m) {
+        uint64_t r = 0;
+        for (; m; m &= m - 1, x >>= 1)
+            if (x & 1) r |= m & (~m + 1);
+        return r;
+    };
+    auto pext = [](uint64_t x, uint64_t m) {
+        uint64_t r = 0, bit = 1;
+        for (; m; m &= m - 1, bit <<= 1)
+            if (x & m & (~m + 1)) r |= bit;
+        return r;
+    };
+    const uint64_t TM = pdep(127, a.maskA) | pdep(63, a.maskB);
+    for (int q = 0; q < 4; ++q) {
+        ex.hiOff[q] = pdep(uint64_t(q) << 11, TM);
+        ex.hiI[q] = uint32_t(pext(ex.hiOff[q], a.maskA));
+        ex.hiJ[q] = uint32_t(pext(ex.hiOff[q], a.maskB));
+        ex.dI[q] = uint32_t(pext(uint64_t(q), a.maskA));
+        ex.dJ[q] = uint32_t(pext(uint64_t(q), a.maskB));
     }
     const uint64_t nA = (uint64_t(1) << (a.fA + a.s)) / 4, nB = (uint64_t(1) << (a.fB + a.s)) / 4;
     auto blocks = [](uint64_t n) { return dim3(uint32_t(std::min<uint64_t>((n + 255) / 256, 1u << 16)), 1, 1); };

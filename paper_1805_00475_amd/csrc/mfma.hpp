@@ -9,6 +9,11 @@ namespace tn {
 
 struct MfmaExtra {
     uint64_t off[kMaxGroup];  // a multiple of p at least 2^59, per prime
+    // output tile positions 2048 q (q < 4) beyond a thread's first: C offset
+    // bits and the A-side and B-side tile-local indices; dI, dJ: the indices
+    // of the word k (< 4) after a position whose two lowest bits are 0
+    uint64_t hiOff[4];
+    uint32_t hiI[4], hiJ[4], dI[4], dJ[4];
 };
 
 // A step qualifies when K = 2^s is at least 64 and the free sides give at
