@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <mutex>
@@ -113,6 +114,9 @@ int worker_count(int n) {
 }
 
 constexpr int kTileLog = 8;  // outputs per wave tile (2^8, four per lane)
+// milliseconds without a newly ordered instance after which the pending
+// sub-batch is contracted
+constexpr int kIdleFlushMs = 2;
 
 // Steps small enough for the wave kernel; larger or wider ones get the
 // shape-specific kernels of the single-instance path.
@@ -331,6 +335,8 @@ extern "C" tn_status tn_count_batch(const tn_formula* fs, int32_t n, tn_order_ki
     std::mutex mu;
     std::condition_variable cv;
     std::atomic<int32_t> next{0};
+    std::vector<int32_t> done;  // instances in the order their plans were finished
+    done.reserve(size_t(n));
     auto work = [&]() {
         for (;;) {
             const int32_t i = next.fetch_add(1);
@@ -341,6 +347,7 @@ extern "C" tn_status tn_count_batch(const tn_formula* fs, int32_t n, tn_order_ki
             {
                 std::lock_guard<std::mutex> lk(mu);
                 s.ready = true;
+                done.push_back(i);
             }
             cv.notify_all();
         }
@@ -364,14 +371,24 @@ extern "C" tn_status tn_count_batch(const tn_formula* fs, int32_t n, tn_order_ki
         note(s);
         sb = SubBatch{};
     };
-    std::vector<int32_t> order_done;
-    for (int32_t i = 0; i < n; ++i) {
-        Inst& I = ins[size_t(i)];
+    // Instances are contracted in the order their plans become ready (order
+    // searches differ in length). When no new plan arrives for a while, the
+    // pending sub-batch goes to the device rather than leaving it idle.
+    size_t taken = 0;
+    for (int32_t got = 0; got < n; ++got) {
+        int32_t i;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv.wait(lk, [&] { return I.ready; });
+            auto more = [&] { return taken < done.size(); };
+            if (!sb.ids.empty() && !cv.wait_for(lk, std::chrono::milliseconds(kIdleFlushMs), more)) {
+                lk.unlock();
+                flush();
+                lk.lock();
+            }
+            cv.wait(lk, more);
+            i = done[taken++];
         }
-        order_done.push_back(i);
+        Inst& I = ins[size_t(i)];
         if (I.st != TN_OK) continue;
         I.st = resolve(I.plan, opts, I.R);
         if (I.st != TN_OK) continue;
