@@ -27,8 +27,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the matrix-core kernel from rocprofv3 byte counters
+# (FETCH_SIZE and WRITE_SIZE runs of this benchmark, scaled by a plain copy
+# of known size); used only while the kernel source is the one measured
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mfma_cvc200_batch16_traffic.txt")
 INT8_PEAK_TOPS = 5000.0   # dense int8 MFMA, MI355X
 INT8_OPS_PER_MODMAC = 32  # 16 digit-pair products, multiply + add each
+
+
+def measured_traffic():
+    """Counter-derived bytes per k_mfma launch, or None when the kernel
+    source changed since the counters were taken (or no record exists)."""
+    import hashlib
+    try:
+        rec = {}
+        for line in open(TRAFFIC_FILE):
+            if line.strip() and not line.startswith("#"):
+                key, _, val = line.partition(":")
+                rec[key.strip()] = val.strip()
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def roofline_of(name, d):
@@ -44,7 +66,7 @@ def roofline_of(name, d):
     if name == "mfma":
         tops = d["macs"] * INT8_OPS_PER_MODMAC / sec / 1e12 if sec > 0 else 0.0
         per.update({"bound": "mfma", "achieved": round(tops, 2), "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                    "frac": round(tops / INT8_PEAK_TOPS, 4), "traffic": None,
+                    "frac": round(tops / INT8_PEAK_TOPS, 4), "traffic": measured_traffic(),
                     "algorithmic_modmacs_per_launch": d["macs"] / max(1, d["launches"]),
                     "achieved_modmacs_per_s": d["macs"] / sec if sec > 0 else 0.0})
     else:
