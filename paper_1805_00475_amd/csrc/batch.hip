@@ -104,6 +104,7 @@ struct Inst {
     std::vector<uint32_t> res;
     uint64_t u64v = 0;
     bool host_only = false;   // the count is known without device work
+    std::vector<uint8_t> dig;  // per step: digit-plane bits of launch_step
 };
 
 int worker_count(int n) {
@@ -178,6 +179,12 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
     std::vector<std::pair<int32_t, int>> gather_of;  // (instance, plane)
     for (int32_t i : sb.ids) {
         Inst& I = ins[i];
+        // digit-plane hand-over between matrix-core steps (small steps run
+        // in the wave kernel)
+        std::vector<KernelClass> cls(I.plan.steps.size());
+        for (size_t k = 0; k < cls.size(); ++k)
+            cls[k] = small_step(I.plan.steps[k]) ? KC_BATCH : choose_class(I.plan.steps[k], I.R.u64, o->flags);
+        I.dig = digit_plan(I.plan, cls);
         char* ib = base + I.init_off;
         for (int32_t k = 0; k < int32_t(I.plan.steps.size()); ++k) {
             const Step& st = I.plan.steps[k];
@@ -274,7 +281,7 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
                 KernelClass kc = KC_GENERIC;
                 err = launch_step(st, I.R.u64, o->flags, I.R.u64 ? nullptr : I.R.primes.data() + g0, gn,
                                   base + I.init_off, base + I.arena_off + g0 * I.arena_bytes, I.arena_bytes / I.es,
-                                  base + scratch_off, stream, &kc);
+                                  base + scratch_off, stream, &kc, -1, I.dig[size_t(bk.second)]);
             }
         }
     }

@@ -274,10 +274,48 @@ hipError_t launch_stream(int logk, int nb, dim3 grid, hipStream_t st, const Step
 
 inline uint32_t cap32(uint64_t x, uint32_t hi) { return uint32_t(std::min<uint64_t>(std::max<uint64_t>(x, 1), hi)); }
 
+KernelClass choose_class(const Step& st, bool u64, int flags) {
+    StepArgs a{};
+    a.s = st.s;
+    a.rC = st.rC;
+    a.fA = std::max(st.rA, st.rB) - st.s;  // the larger free side plays A
+    a.fB = std::min(st.rA, st.rB) - st.s;
+    if (flags & TN_FLAG_GENERIC_ONLY) return KC_GENERIC;
+    if (a.rC <= 6 && a.s >= 10) return KC_DOT;
+    if (!u64 && !st.initA && !st.initB && mfma_eligible(a) && !(flags & TN_FLAG_NO_MFMA)) return KC_MFMA;
+    if (a.s <= 5 && a.fA >= 8) return KC_STREAM;
+    if (a.s >= 6) return KC_ROWDOT;
+    return KC_GENERIC;
+}
+
+std::vector<uint8_t> digit_plan(const Plan& plan, const std::vector<KernelClass>& cls) {
+    const size_t n = plan.steps.size();
+    const size_t ids = size_t(plan.n_init) + n;
+    std::vector<int32_t> prod(ids, -1), cons(ids, -1);
+    for (size_t k = 0; k < n; ++k) {
+        const Step& st = plan.steps[k];
+        prod[size_t(st.out)] = int32_t(k);
+        cons[size_t(st.a)] = int32_t(k);
+        cons[size_t(st.b)] = int32_t(k);
+    }
+    std::vector<uint8_t> out_dig(n, 0), dig(n, 0);
+    for (size_t k = 0; k < n; ++k) {
+        const int32_t c = cons[size_t(plan.steps[k].out)];
+        out_dig[k] = cls[k] == KC_MFMA && c >= 0 && cls[size_t(c)] == KC_MFMA;
+    }
+    for (size_t k = 0; k < n; ++k) {
+        const Step& st = plan.steps[k];
+        const int32_t pa = prod[size_t(st.a)], pb = prod[size_t(st.b)];
+        dig[k] = uint8_t((out_dig[k] ? 4 : 0) | (pa >= 0 && out_dig[size_t(pa)] ? 1 : 0) |
+                         (pb >= 0 && out_dig[size_t(pb)] ? 2 : 0));
+    }
+    return dig;
+}
+
 // Choose and launch the kernel of one step for a group of G primes.
 hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* primes, int G, char* init_base,
                        char* arena_base, int64_t arena_elems, char* scratch, hipStream_t stream, KernelClass* kc,
-                       int force) {
+                       int force, unsigned dig) {
     const size_t es = u64 ? 8 : 4;
     Profiler& prof = profiler();
     // algorithmic work of the step: entries read and written, multiply-adds
@@ -314,8 +352,8 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
         std::swap(a.strideA, a.strideB);
         std::swap(a.maskA, a.maskB);
         std::swap(a.fA, a.fB);
+        dig = (dig & 4u) | ((dig & 1u) << 1) | ((dig >> 1) & 1u);
     }
-    const bool generic_only = flags & TN_FLAG_GENERIC_ONLY;
     const uint64_t total = uint64_t(1) << a.rC;
     const bool can_mfma = !u64 && !st.initA && !st.initB && mfma_eligible(a);
     const bool can_stream = a.s <= 5 && a.fA >= 8;
@@ -324,7 +362,10 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
     if (force == KC_ROWDOT && a.rC > 40) return hipErrorInvalidValue;
     const bool can_dot = a.rC <= 6 && a.s >= 10;
     if (force == KC_DOT && !can_dot) return hipErrorInvalidValue;
-    if (force == KC_DOT || (force < 0 && !generic_only && can_dot)) {
+    // one decision rule for launches and for the digit-plane hand-over
+    const int pick = force >= 0 ? force : int(choose_class(st0, u64, flags));
+    if (pick != KC_MFMA && (dig & 3u)) return hipErrorInvalidValue;  // operands must be plain residues
+    if (pick == KC_DOT) {
         const int nblk = int(std::min<uint64_t>(kDotBlocks, (uint64_t(1) << a.s) >> 8));
         *kc = KC_DOT;
         dim3 g1(nblk, 1, G), g2(uint32_t(total), 1, G);
@@ -341,11 +382,11 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
             hipLaunchKernelGGL(k_dot_final<false>, g2, dim3(64), 0, stream, a, scr, nblk);
         return hipGetLastError();
     }
-    if ((force == KC_MFMA) || (force < 0 && !generic_only && can_mfma && !(flags & TN_FLAG_NO_MFMA))) {
+    if (pick == KC_MFMA) {
         *kc = KC_MFMA;
-        return launch_mfma(a, G, stream, &prof, step_bytes, step_macs, scratch, kScratchPerPrime);
+        return launch_mfma(a, G, stream, &prof, step_bytes, step_macs, scratch, kScratchPerPrime, dig);
     }
-    if (force == KC_STREAM || (force < 0 && !generic_only && can_stream)) {
+    if (pick == KC_STREAM) {
         const int nb = std::min(a.fB, 4);
         const uint64_t n_iter = (uint64_t(1) << a.fA) >> 8;
         const uint64_t n_chunk = (uint64_t(1) << a.fB) >> nb;
@@ -357,7 +398,7 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
         prof.after_raw(stream, KC_STREAM, step_bytes, step_macs);
         return e;
     }
-    if (force == KC_ROWDOT || (force < 0 && !generic_only && a.s >= 6)) {
+    if (pick == KC_ROWDOT) {
         dim3 grid(cap32((total + 3) / 4, 1u << 20), 1, G);
         *kc = KC_ROWDOT;
         prof.before(stream);
@@ -481,13 +522,16 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
     };
     if (err != hipSuccess) return fail();
     const Step& last = plan.steps.back();
+    std::vector<KernelClass> cls(plan.steps.size());
+    for (size_t k = 0; k < cls.size(); ++k) cls[k] = choose_class(plan.steps[k], R.u64, o->flags);
+    const std::vector<uint8_t> dig = digit_plan(plan, cls);
     std::vector<uint64_t> out(size_t(R.k), 0);
     for (int g0 = 0; g0 < R.k; g0 += G) {
         const int gn = std::min(G, R.k - g0);
-        for (const Step& st : plan.steps) {
+        for (size_t k = 0; k < plan.steps.size(); ++k) {
             KernelClass kc = KC_GENERIC;
-            err = launch_step(st, R.u64, o->flags, R.u64 ? nullptr : R.primes.data() + g0, gn, init_base, arena_base,
-                              arena_elems, scratch, stream, &kc);
+            err = launch_step(plan.steps[k], R.u64, o->flags, R.u64 ? nullptr : R.primes.data() + g0, gn, init_base,
+                              arena_base, arena_elems, scratch, stream, &kc, -1, dig[k]);
             if (err != hipSuccess) return fail();
         }
         for (int g = 0; g < gn; ++g) {

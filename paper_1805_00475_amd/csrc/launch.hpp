@@ -21,10 +21,23 @@ int64_t align256(int64_t b);
 // Chooses and launches the kernel(s) of one step for G residue planes (or
 // the single 64-bit plane). Operands that are initial tensors live in the
 // init region (shared by all planes); the others in the plane's arena.
-// force >= 0 selects a kernel class (test hook).
+// force >= 0 selects a kernel class (test hook). dig: bit 0 / bit 1 = operand
+// A / B of the plan's step is already held as digit planes (see mfma.hip),
+// bit 2 = write the output as digit planes (only the matrix-core kernel
+// does; the caller sets it only where choose_class says so for this step
+// and for the output's consumer).
 hipError_t launch_step(const Step& st, bool u64, int flags, const uint32_t* primes, int G, char* init_base,
                        char* arena_base, int64_t arena_elems, char* scratch, hipStream_t stream, KernelClass* kc,
-                       int force = -1);
+                       int force = -1, unsigned dig = 0);
+
+// The kernel class launch_step picks for a step (no launch, force < 0).
+KernelClass choose_class(const Step& st, bool u64, int flags);
+
+// Digit-plane hand-over between matrix-core steps: for every step, the dig
+// bits of launch_step, given the class each step runs with. A tensor is
+// written as digit planes when its producer and its consumer both run the
+// matrix-core kernel, which then skips the digit pass on it.
+std::vector<uint8_t> digit_plan(const Plan& plan, const std::vector<KernelClass>& cls);
 
 // Entry x of an initial tensor whose bonds sit at bit positions pos.
 uint64_t init_entry(const InitTensor& t, const std::vector<int32_t>& pos, uint64_t x);

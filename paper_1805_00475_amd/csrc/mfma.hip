@@ -34,6 +34,26 @@ namespace tn {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------- digit pass
+// Digit planes of four consecutive residues: word d holds digit d of each
+// (byte k = residue k). In a digit-plane tensor, entry e's digit d is byte
+// 256 (e / 64) + 64 d + e % 64, so the word of entries 4m..4m+3 (m = e / 4)
+// of plane d sits at word 64 (e / 64) + 16 d + (e % 64) / 4.
+__device__ __forceinline__ void digit_words(const uint32_t (&r)[4], uint32_t p, uint32_t (&w)[4]) {
+    const uint32_t half = p >> 1;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) w[d] = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        int32_t c = r[e] > half ? int32_t(r[e] - p) : int32_t(r[e]);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            int32_t dig = d < 3 ? int32_t(int8_t(c & 0xff)) : c;
+            w[d] |= (uint32_t(dig) & 0xffu) << (8 * e);
+            c = (c - dig) >> 8;
+        }
+    }
+}
+
 // In place: the 16 lanes owning one 64-entry chunk read it (4 entries each)
 // before any of them writes, since they are consecutive lanes of one wave
 // and every store depends on all four loads of that lane.
@@ -41,22 +61,12 @@ __global__ __launch_bounds__(256) void k_digits(uint32_t* X, int64_t stride, uin
                                                 StepArgs a) {
     const uint32_t p = a.p[blockIdx.z];
     uint32_t* base = X + blockIdx.z * stride;
-    const uint32_t half = p >> 1;
     for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n_vec4;
          v += uint64_t(gridDim.x) * blockDim.x) {
         uint4 r = reinterpret_cast<const uint4*>(base)[v];
-        uint32_t rv[4] = {r.x, r.y, r.z, r.w};
-        uint32_t w[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int32_t c = rv[e] > half ? int32_t(rv[e] - p) : int32_t(rv[e]);
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                int32_t dig = d < 3 ? int32_t(int8_t(c & 0xff)) : c;
-                w[d] |= (uint32_t(dig) & 0xffu) << (8 * e);
-                c = (c - dig) >> 8;
-            }
-        }
+        const uint32_t rv[4] = {r.x, r.y, r.z, r.w};
+        uint32_t w[4];
+        digit_words(rv, p, w);
         // chunk = 16 vec4 of 64 entries; plane d of the chunk at byte 64 d
         const uint64_t chunk = v >> 4;
         const uint32_t lane16 = uint32_t(v & 15);
@@ -378,12 +388,20 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
                 const uint64_t o = offLow | ex.hiOff[q];
                 const uint32_t i = iLow | ex.hiI[q];
                 const uint32_t j = jLow | ex.hiJ[q];
-                uint4 v;
-                v.x = sOut[i * kBN + j];
-                v.y = sOut[(i | ex.dI[1]) * kBN + (j | ex.dJ[1])];
-                v.z = sOut[(i | ex.dI[2]) * kBN + (j | ex.dJ[2])];
-                v.w = sOut[(i | ex.dI[3]) * kBN + (j | ex.dJ[3])];
-                *reinterpret_cast<uint4*>(C + (baseC | o)) = v;
+                const uint32_t v[4] = {sOut[i * kBN + j], sOut[(i | ex.dI[1]) * kBN + (j | ex.dJ[1])],
+                                       sOut[(i | ex.dI[2]) * kBN + (j | ex.dJ[2])],
+                                       sOut[(i | ex.dI[3]) * kBN + (j | ex.dJ[3])]};
+                const uint64_t e = baseC | o;
+                if (ex.digits_out) {
+                    // the consumer is a matrix-core step: hand over digit planes
+                    uint32_t w[4];
+                    digit_words(v, p, w);
+                    uint32_t* cw = C + (e >> 6) * 64 + ((e & 63) >> 2);
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) cw[16 * d] = w[d];
+                } else {
+                    *reinterpret_cast<uint4*>(C + e) = uint4{v[0], v[1], v[2], v[3]};
+                }
             }
         }
         if (!more) break;
@@ -397,7 +415,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
 
 // split-K: add the partial residues of every K range and scatter into C
 __global__ __launch_bounds__(256) void k_mfma_reduce(StepArgs a, const uint32_t* part, int64_t part_stride,
-                                                     int splits) {
+                                                     int splits, int digits_out) {
     const int g = blockIdx.z;
     const uint32_t p = a.p[g];
     uint32_t* C = static_cast<uint32_t*>(a.C) + g * a.strideC;
@@ -412,13 +430,28 @@ __global__ __launch_bounds__(256) void k_mfma_reduce(StepArgs a, const uint32_t*
         uint64_t ta, tb;
         tile_coords(tile, tilesA, tilesB, ta, tb);
         const uint64_t i = loc / kBN, j = loc % kBN;
-        C[pdep64(ta * kBM + i, a.maskA) | pdep64(tb * kBN + j, a.maskB)] = uint32_t(sum % p);
+        const uint64_t c = pdep64(ta * kBM + i, a.maskA) | pdep64(tb * kBN + j, a.maskB);
+        const uint32_t r = uint32_t(sum % p);
+        if (digits_out) {
+            // entry c's digit d at byte 256 (c / 64) + 64 d + c % 64
+            int32_t x = r > (p >> 1) ? int32_t(r - p) : int32_t(r);
+            uint8_t* cb = reinterpret_cast<uint8_t*>(C) + (c >> 6) * 256 + (c & 63);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int32_t dig = d < 3 ? int32_t(int8_t(x & 0xff)) : x;
+                cb[64 * d] = uint8_t(uint32_t(dig) & 0xffu);
+                x = (x - dig) >> 8;
+            }
+        } else {
+            C[c] = r;
+        }
     }
 }
 
 hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
-                       double step_macs, char* scratch, int64_t scratch_per_plane) {
+                       double step_macs, char* scratch, int64_t scratch_per_plane, unsigned dig) {
     MfmaExtra ex{};
+    ex.digits_out = (dig & 4u) ? 1u : 0u;
     for (int g = 0; g < G; ++g) {
         const uint64_t p = a.p[g];
         ex.off[g] = p * ((uint64_t(1) << 59) / p + 1);
@@ -447,17 +480,26 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* p
     auto blocks = [](uint64_t n) { return dim3(uint32_t(std::min<uint64_t>((n + 255) / 256, 1u << 16)), 1, 1); };
     dim3 gA = blocks(nA), gB = blocks(nB);
     gA.z = gB.z = G;
-    prof->before(stream);
-    hipLaunchKernelGGL(k_digits, gA, dim3(256), 0, stream, static_cast<uint32_t*>(const_cast<void*>(a.A)),
-                       a.strideA, nA, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_digits, gB, dim3(256), 0, stream, static_cast<uint32_t*>(const_cast<void*>(a.B)),
-                       a.strideB, nB, a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // the digit pass reads and rewrites both operands in place
-    prof->after_raw(stream, KC_DIGITS, 2.0 * 16.0 * double(nA + nB) * G, 0.0);
+    // the digit pass reads and rewrites in place the operands that are not
+    // digit planes already (those came from a matrix-core step's epilogue)
+    hipError_t e = hipSuccess;
+    if ((dig & 3u) != 3u) {
+        prof->before(stream);
+        if (!(dig & 1u)) {
+            hipLaunchKernelGGL(k_digits, gA, dim3(256), 0, stream, static_cast<uint32_t*>(const_cast<void*>(a.A)),
+                               a.strideA, nA, a);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (!(dig & 2u)) {
+            hipLaunchKernelGGL(k_digits, gB, dim3(256), 0, stream, static_cast<uint32_t*>(const_cast<void*>(a.B)),
+                               a.strideB, nB, a);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        const double n4 = double((dig & 1u) ? 0 : nA) + double((dig & 2u) ? 0 : nB);
+        prof->after_raw(stream, KC_DIGITS, 2.0 * 16.0 * n4 * G, 0.0);
+    }
     const uint64_t T = (uint64_t(1) << (a.fA - 7)) * (uint64_t(1) << (a.fB - 6));
     // too few output tiles to fill the GPU: split K over block rows (powers
     // of two, at most 128 partial tiles per plane in the scratch area, at
@@ -474,7 +516,7 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* p
     if (splits > 1) {
         const uint64_t n = T * (kBM * kBN);
         dim3 gr(uint32_t(std::min<uint64_t>((n + 255) / 256, 4096)), 1, G);
-        hipLaunchKernelGGL(k_mfma_reduce, gr, dim3(256), 0, stream, a, part, part_stride, splits);
+        hipLaunchKernelGGL(k_mfma_reduce, gr, dim3(256), 0, stream, a, part, part_stride, splits, int(ex.digits_out));
     }
     prof->after_raw(stream, KC_MFMA, step_bytes, step_macs);
     return hipGetLastError();

@@ -14,6 +14,7 @@ struct MfmaExtra {
     // of the word k (< 4) after a position whose two lowest bits are 0
     uint64_t hiOff[4];
     uint32_t hiI[4], hiJ[4], dI[4], dJ[4];
+    uint32_t digits_out;  // 1: write C as digit planes (its consumer is a matrix-core step)
 };
 
 // A step qualifies when K = 2^s is at least 64 and the free sides give at
@@ -25,7 +26,9 @@ struct Profiler;
 // Digit pass on both operands, then the GEMM; each launch is bracketed by
 // the profiler (no-op unless timing is on) with its algorithmic work.
 // scratch: scratch_per_plane bytes for each of the G planes (split-K partials)
+// dig: bit 0 / bit 1 = A / B are digit planes already (no digit pass), bit 2
+// = write C as digit planes
 hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
-                       double step_macs, char* scratch, int64_t scratch_per_plane);
+                       double step_macs, char* scratch, int64_t scratch_per_plane, unsigned dig = 0);
 
 }  // namespace tn
