@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # of known size); used only while the kernel source is the one measured
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mfma_cvc200_batch16_traffic.txt")
 INT8_PEAK_TOPS = 5000.0   # dense int8 MFMA, MI355X
-INT8_OPS_PER_MODMAC = 32  # 16 digit-pair products, multiply + add each
+INT8_OPS_PER_MODMAC = 8   # 4 digit-pair products, multiply + add each
 
 
 def measured_traffic():
@@ -57,7 +57,7 @@ def roofline_of(name, d):
     """Achieved vs peak for one kernel class from its hipEvent total.
 
     Matrix-core GEMM (mfma): algorithmic multiply-adds modulo p, each costing
-    16 int8 digit-pair products (32 int8 ops), against the dense int8 MFMA
+    4 int8 digit-pair products (8 int8 ops), against the dense int8 MFMA
     peak. Every other class: algorithmic bytes (entries of A and B read, C
     written) against the HBM peak."""
     sec = d["ms"] * 1e-3
@@ -98,12 +98,14 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(formula, plan_steps, n_primes, budget_s):
+def cpu_baseline(formula, plan_steps, budget_s):
     """Oracle O-B (numpy pairwise contraction) on one prime of one instance,
     following the same contraction order, stopped after ``budget_s``; the
-    instance time is extrapolated linearly in multiply-adds done."""
+    instance time is extrapolated linearly in multiply-adds done and in the
+    oracle's own number of primes (31-bit ones)."""
     import numpy as np
     from oracle import contract, cost, rns, tensors
+    n_primes = rns.n_primes_for(formula.n_vars)
     nets, _ = tensors.network_of_formula(formula)
     rep = cost.replay([ls for _, ls in nets], plan_steps)
     macs = [s["macs"] for s in rep["steps"]]
@@ -189,7 +191,7 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "cvc":
         formulas = [I.cvc(args.n, s) for s in range(args.batch)]
-        k_primes = (args.n + 30) // 31 + 1
+        k_primes = tn.primes_for(args.n)
         workload = (f"#Cubic-Vertex-Cover, uniform random cubic graphs n={args.n} (configuration model), "
                     f"batch of {args.batch} seeds, {args.order} order, {k_primes} primes + CRT")
     else:
@@ -197,7 +199,7 @@ def main():
         k_primes = None
         workload = (f"mixed batch of {args.batch}: even index monotone 1-in-3 n~U[30,120] m=round(0.66n), "
                     f"odd index cubic vertex cover n~U[30,120] (even); {args.order} order; u64 for n<=63 else "
-                    f"residues mod ceil(n/31)+1 primes")
+                    f"residues mod 16-bit primes (the fewest whose product exceeds 2^(n+1))")
     ws = tn.default_workspace()
     ws.get(64 << 30)
     if args.copy_calibration:
@@ -248,7 +250,7 @@ def main():
         "metric": "exact counts/sec + contraction HBM GB/s; learned vs greedy order wall-time",
         "value": round(value, 4), "unit": "counts/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32 residues mod 31-bit primes (exact)",
+        "scaling": "weak", "vs_baseline": None, "dtype": "residues mod 16-bit primes in u32 words (exact)",
         "data": "synthetic",
         "config": {"workload": workload, "batch": args.batch, "n": args.n if args.workload == "cvc" else None,
                    "order": args.order, "primes": k_primes},
@@ -261,8 +263,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         p0 = plans[0]
-        kp = k_primes if k_primes else (formulas[0].n_vars + 30) // 31 + 1
-        out["cpu_baseline"] = cpu_baseline(formulas[0], p0.steps(), kp, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(formulas[0], p0.steps(), args.cpu_seconds)
         log("cpu baseline done")
     print(json.dumps(out))
 

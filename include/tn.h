@@ -12,7 +12,7 @@
  * tensor-METIS style recursive bisection, tensor-GN community detection, or
  * a learned scorer) fixes the sequence of pairwise contractions; HIP kernels
  * run them on the GPU. Counts are exact: 64-bit unsigned arithmetic while the
- * formula has at most 63 variables, otherwise residues modulo 31-bit primes
+ * formula has at most 63 variables, otherwise residues modulo 16-bit primes
  * combined on the host by the Chinese remainder theorem (the exact-precision
  * remark of Sec. 3.2, at a cost linear in the number of primes).
  *
@@ -54,8 +54,8 @@ typedef enum {
 #define TN_MAX_RANK 34
 /* Largest rank of an initial (clause or COPY) tensor. */
 #define TN_MAX_INIT_RANK 24
-/* Most primes one contraction may use (counts up to ~2^1900). */
-#define TN_MAX_PRIMES 64
+/* Most primes one contraction may use (counts up to ~2^2000). */
+#define TN_MAX_PRIMES 128
 
 /* Clause kinds: OR (Eq. 3) and exactly-one (Eq. 6, with negation allowed). */
 typedef enum { TN_CLAUSE_OR = 0, TN_CLAUSE_EXACTLY_ONE = 1 } tn_clause_kind;
@@ -106,7 +106,7 @@ typedef enum { TN_ARITH_AUTO = 0, TN_ARITH_U64 = 1, TN_ARITH_RNS = 2 } tn_arith;
 
 typedef struct {
     int32_t arith;            /* tn_arith; AUTO = U64 if n_vars <= 63 else RNS */
-    int32_t n_primes;         /* RNS primes; 0 = ceil(n_vars / 31) + 1 */
+    int32_t n_primes;         /* RNS primes; 0 = the fewest whose product exceeds 2^(n_vars + 1) */
     void* workspace;          /* device memory owned by the caller */
     size_t workspace_bytes;
     void* stream;             /* hipStream_t; NULL = null stream */
@@ -207,8 +207,8 @@ tn_status tn_profile_launches(tn_launch_record* out, int64_t cap, int64_t* n);
  * where xA gathers the bits of c selected by maskA and xB the remaining bits
  * of c below 2^(rA + rB - 2s) (the shared bonds are the low s bits of both
  * operands, Sec. 2.1 / Eq. 5 form). Entries are uint32 residues modulo
- * ``prime`` (arith TN_ARITH_RNS; prime in (2^30, 2^31) with 2^32 mod prime
- * below 2^12) or uint64 wrapping (TN_ARITH_U64). ``kernel`` forces a
+ * ``prime`` (arith TN_ARITH_RNS; a prime in (2^16 - 2^11, 65280), as
+ * tn_primes returns) or uint64 wrapping (TN_ARITH_U64). ``kernel`` forces a
  * tn_kernel_class (-1 = the library's choice); TN_EUNSUPPORTED if that kernel
  * cannot run this shape. The workspace (device) must hold the three tensors,
  * each rounded up to 256 bytes, plus 4 MiB of scratch; A and B may be
@@ -257,8 +257,14 @@ tn_status tn_mlp_adam(float* params, const float* grad, float* m, float* v, int3
                       float beta2, float eps, void* stream);
 
 /* -------------------------------------------------------------- utilities */
-/* The k largest primes below 2^31, descending, as used by the RNS path. */
+/* The k largest primes below 65280, descending, as used by the RNS path
+ * (k <= TN_MAX_PRIMES; all lie above 2^16 - 2^11). */
 tn_status tn_primes(int32_t k, uint32_t* out);
+/* Number of primes the RNS path uses by default for a formula with n_vars
+ * variables: the fewest leading primes of tn_primes whose product exceeds
+ * 2^(n_vars + 1) (every count is at most 2^n_vars). TN_EINVAL if n_vars < 0
+ * or more than TN_MAX_PRIMES primes would be needed. */
+tn_status tn_primes_for(int32_t n_vars, int32_t* k);
 /* Chinese remaindering of residues modulo the first k primes of tn_primes
  * into little-endian base-2^32 limbs. */
 tn_status tn_crt(const uint32_t* residues, int32_t k, uint32_t* limbs, size_t cap, size_t* n_limbs);

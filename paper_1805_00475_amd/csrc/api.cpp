@@ -59,7 +59,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         // threads while the GPU contracts, so a few host microseconds per
         // device microsecond still pay for themselves.
         const auto t0 = std::chrono::steady_clock::now();
-        const double planes = N.n_vars <= 63 ? 1.0 : double((N.n_vars + 30) / 31 + 1);
+        const double planes = N.n_vars <= 63 ? 1.0 : double(primes_needed(N.n_vars));
         auto over_budget = [&]() {
             const double spent_us =
                 std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
@@ -180,6 +180,14 @@ tn_status tn_primes(int32_t k, uint32_t* out) {
     if (k < 0 || k > TN_MAX_PRIMES || (k > 0 && !out)) return TN_EINVAL;
     const auto& P = prime_table(k);
     std::copy(P.begin(), P.begin() + k, out);
+    return TN_OK;
+}
+
+tn_status tn_primes_for(int32_t n_vars, int32_t* k) {
+    if (n_vars < 0 || !k) return TN_EINVAL;
+    const int32_t need = primes_needed(n_vars);
+    if (need > TN_MAX_PRIMES) return TN_EINVAL;
+    *k = need;
     return TN_OK;
 }
 

@@ -467,7 +467,7 @@ tn_status resolve(const Plan& plan, const tn_contract_opts* o, Resolved& r) {
     }
     if (arith != TN_ARITH_RNS) return TN_EINVAL;
     r.u64 = false;
-    r.k = (o && o->n_primes > 0) ? o->n_primes : (plan.n_vars + 30) / 31 + 1;
+    r.k = (o && o->n_primes > 0) ? o->n_primes : primes_needed(plan.n_vars);
     if (r.k > TN_MAX_PRIMES) return TN_EINVAL;
     const auto& P = prime_table(r.k);
     r.primes.assign(P.begin(), P.begin() + r.k);
@@ -635,8 +635,8 @@ extern "C" tn_status tn_step(const void* A, int32_t rA, const void* B, int32_t r
     const uint64_t cmask = (uint64_t(1) << rC) - 1;
     if ((maskA & ~cmask) || __builtin_popcountll(maskA) != rA - s) return TN_EINVAL;
     const bool u64 = arith == TN_ARITH_U64;
-    if (!u64 && (arith != TN_ARITH_RNS || prime < (1u << 30) || prime >= (1u << 31) ||
-                 ((uint64_t(1) << 32) % prime) >= (1u << 12)))
+    // the residue kernels need 2^16 - 2^11 < p < 65280 (any odd prime there)
+    if (!u64 && (arith != TN_ARITH_RNS || prime <= 65536u - 2048u || prime >= kPrimeBound || prime % 2 == 0))
         return TN_EINVAL;
     if (kernel < -1 || kernel > KC_DOT || kernel == KC_BATCH) return TN_EINVAL;
     const int64_t es = u64 ? 8 : 4;

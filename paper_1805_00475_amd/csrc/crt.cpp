@@ -2,12 +2,14 @@
 // integer (little-endian base-2^32 limbs).
 //
 // Every entry of every intermediate tensor is a count of partial
-// assignments, at most 2^n for n variables, so the final count is below
+// assignments, at most 2^n for n variables, so the final count is at most
 // 2^n and residues modulo primes whose product exceeds 2^n determine it.
-// The primes are the largest ones below 2^31, each above 2^30, so
-// k = ceil(n/31) + 1 of them multiply to more than 2^(30k) >= 2^n.
-// Being of the form 2^31 - d with small d, they also allow the cheap
-// folding reduction used by the kernels (2^32 = 2d mod p).
+// The primes are the largest ones below kPrimeBound = 65280: their centred
+// residues (|r| <= 32639) are exactly two signed base-256 digits, which is
+// what the matrix-core kernel multiplies, and being above 2^16 - 2^11 they
+// allow the kernels' folding reduction (2^16 = 2^16 - p mod p, below 2^11).
+// primes_needed(n) is the fewest leading primes whose product exceeds 2^n.
+#include <cmath>
 #include <mutex>
 
 #include "internal.hpp"
@@ -26,12 +28,21 @@ const std::vector<uint32_t>& prime_table(int32_t k) {
     static std::mutex mu;
     static std::vector<uint32_t> table;
     std::lock_guard<std::mutex> lk(mu);
-    uint32_t q = table.empty() ? 0x7FFFFFFFu : table.back() - 1;
+    uint32_t q = table.empty() ? kPrimeBound - 1 : table.back() - 1;
     while (int32_t(table.size()) < k) {
         if (is_prime_u32(q)) table.push_back(q);
         --q;
     }
     return table;
+}
+
+int32_t primes_needed(int32_t n_vars) {
+    const std::vector<uint32_t>& P = prime_table(TN_MAX_PRIMES);
+    double bits = 0.0;
+    int32_t k = 0;
+    // a margin of one bit over n absorbs any rounding in the logarithms
+    while (k < TN_MAX_PRIMES && bits <= double(n_vars) + 1.0) bits += std::log2(double(P[size_t(k++)]));
+    return bits > double(n_vars) + 1.0 ? k : TN_MAX_PRIMES + 1;
 }
 
 static uint32_t powmod(uint64_t b, uint64_t e, uint32_t p) {

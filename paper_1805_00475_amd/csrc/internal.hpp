@@ -112,7 +112,10 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
                    std::vector<uint32_t>& residues, uint64_t* u64v);
 
 // crt.cpp
+// primes of the residue path: the largest below kPrimeBound, descending
+constexpr uint32_t kPrimeBound = 65280;
 const std::vector<uint32_t>& prime_table(int32_t k);
+int32_t primes_needed(int32_t n_vars);  // > TN_MAX_PRIMES when n_vars is too large
 void crt_limbs(const uint32_t* residues, int32_t k, std::vector<uint32_t>& limbs);
 
 }  // namespace tn

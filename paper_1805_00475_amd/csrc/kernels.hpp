@@ -22,20 +22,25 @@ struct StepArgs {
     uint32_t r2[kMaxGroup];             // 2^32 mod p (small for p close to 2^31)
 };
 
-// Residues modulo p = 2^31 - d with 2d < 2^12. A 64-bit value x = h 2^32 + l
-// is congruent to h (2^32 mod p) + l, which is below 2^45 (fold). Three
-// products below 2^62 added to a folded value stay below 2^64, so the
-// accumulator folds after every third product. Two folds bring any 64-bit
-// value below 2^32 + 2^25 < 3p; two conditional subtractions finish.
+// Residues modulo primes p in (2^16 - 2^11, 2^16), r = 2^32 mod p < 2^16.
+// A 64-bit value x = h 2^32 + l is congruent to h r + l, below 2^48 + 2^32
+// (fold); products of residues are below 2^32, so a folded accumulator
+// takes at least 2^15 more products before it could overflow (the kernels
+// fold after every third). To finish, a second fold brings x below 2^33,
+// and four folds at 2^16 (2^16 = 2^16 - p mod p, below 2^11) bring it
+// below 2^33 -> 2^28.01 -> 2^23.02 -> 2^18.35 -> 75776 < 2p; one
+// conditional subtraction ends below p.
 struct ModP {
     uint32_t p, r;
     __device__ __forceinline__ uint64_t fold(uint64_t x) const { return (x >> 32) * r + (x & 0xffffffffull); }
     __device__ __forceinline__ uint32_t finish(uint64_t x) const {
         x = fold(fold(x));
-        const uint64_t p2 = uint64_t(p) << 1;
-        x = x >= p2 ? x - p2 : x;
-        x = x >= p ? x - p : x;
-        return uint32_t(x);
+        const uint32_t r16 = 65536u - p;
+        uint32_t y = uint32_t(x >> 16) * r16 + uint32_t(x & 0xffffu);  // < 2^28.01
+        y = (y >> 16) * r16 + (y & 0xffffu);
+        y = (y >> 16) * r16 + (y & 0xffffu);
+        y = (y >> 16) * r16 + (y & 0xffffu);
+        return y >= p ? y - p : y;
     }
 };
 

@@ -1,25 +1,25 @@
 // Dense contraction steps on the matrix cores, exactly.
 //
 // A step whose shared dimension K = 2^s is wide and whose two free sides are
-// large is a plain matrix product C = A B^T over residues modulo p < 2^31
+// large is a plain matrix product C = A B^T over residues modulo p < 65280
 // (rows of A and B are contiguous along the shared bonds in the plan's
-// layout). Each residue r is centred to r' in (-p/2, p/2] and written as four
-// signed base-256 digits r' = d0 + d1 2^8 + d2 2^16 + d3 2^24 with d0..d2 in
-// [-128, 127] and |d3| <= 64. Then
-//     C = sum over t = 0..6 of 2^(8t) T_t,   T_t = sum_{i+j=t} A_i B_j^T,
+// layout). Each residue r is centred to r' in (-p/2, p/2] (|r'| <= 32639) and
+// written as two signed base-256 digits r' = d0 + d1 2^8, d0 and d1 in
+// [-128, 127]. Then
+//     C = T0 + 2^8 T1 + 2^16 T2,   T_t = sum_{i+j=t} A_i B_j^T,
 // where A_i, B_j are int8 digit matrices; every T_t is accumulated by the
 // int8 MFMA into int32 registers. Each product of digits is at most 2^14 in
-// magnitude, at most four digit pairs share a shift, so K <= 2^14 keeps every
-// T_t below 2^30 -- exact; wider K is summed in chunks of 2^14 whose results
-// are reduced to residues and added modulo p. The epilogue forms
-//     X = (T0 + T1 2^8 + T2 2^16 + T3 2^24) + (T4 + T5 2^8 + T6 2^16) (2^32 mod p)
-// in 64-bit integers (|X| < 2^59), adds a multiple of p above 2^59, and
-// reduces with the folding reduction of the other kernels.
+// magnitude and at most two digit pairs share a shift, so K <= 2^15 keeps
+// every T_t at most 2^30 -- exact; wider K is summed in ranges of 2^15 whose
+// results are reduced to residues and added modulo p. The epilogue forms
+// X = T0 + 2^8 T1 + 2^16 T2 in 64-bit integers (|X| < 2^47), adds a multiple
+// of p of at least 2^47, and reduces with the folding reduction of the other
+// kernels.
 //
 // Two kernels per step: k_digits rewrites A and B in place (they die at this
-// step) so that every 64-entry chunk of a row holds its four digit planes of
-// 64 bytes each; k_mfma then copies digit tiles into LDS and runs
-// v_mfma_i32_16x16x64_i8. Output tiles are staged in LDS and written in
+// step) so that every 64-entry chunk of a row (256 bytes) starts with its two
+// digit planes of 64 bytes each; k_mfma then copies digit tiles into LDS and
+// runs v_mfma_i32_16x16x64_i8. Output tiles are staged in LDS and written in
 // C-address order so stores stay coalesced for any bit interleaving.
 #include <hip/hip_runtime.h>
 
@@ -34,23 +34,22 @@ namespace tn {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------- digit pass
+constexpr int kDigits = 2;
 // Digit planes of four consecutive residues: word d holds digit d of each
 // (byte k = residue k). In a digit-plane tensor, entry e's digit d is byte
-// 256 (e / 64) + 64 d + e % 64, so the word of entries 4m..4m+3 (m = e / 4)
-// of plane d sits at word 64 (e / 64) + 16 d + (e % 64) / 4.
-__device__ __forceinline__ void digit_words(const uint32_t (&r)[4], uint32_t p, uint32_t (&w)[4]) {
+// 256 (e / 64) + 64 d + e % 64 (bytes 128..255 of every 64-entry chunk are
+// unused), so the word of entries 4m..4m+3 (m = e / 4) of plane d sits at
+// word 64 (e / 64) + 16 d + (e % 64) / 4.
+__device__ __forceinline__ void digit_words(const uint32_t (&r)[4], uint32_t p, uint32_t (&w)[kDigits]) {
     const uint32_t half = p >> 1;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) w[d] = 0;
+    w[0] = w[1] = 0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        int32_t c = r[e] > half ? int32_t(r[e] - p) : int32_t(r[e]);
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            int32_t dig = d < 3 ? int32_t(int8_t(c & 0xff)) : c;
-            w[d] |= (uint32_t(dig) & 0xffu) << (8 * e);
-            c = (c - dig) >> 8;
-        }
+        const int32_t c = r[e] > half ? int32_t(r[e] - p) : int32_t(r[e]);
+        const int32_t d0 = int32_t(int8_t(c & 0xff));
+        const int32_t d1 = (c - d0) >> 8;  // in [-128, 127] since |c| <= 32639
+        w[0] |= (uint32_t(d0) & 0xffu) << (8 * e);
+        w[1] |= (uint32_t(d1) & 0xffu) << (8 * e);
     }
 }
 
@@ -65,58 +64,53 @@ __global__ __launch_bounds__(256) void k_digits(uint32_t* X, int64_t stride, uin
          v += uint64_t(gridDim.x) * blockDim.x) {
         uint4 r = reinterpret_cast<const uint4*>(base)[v];
         const uint32_t rv[4] = {r.x, r.y, r.z, r.w};
-        uint32_t w[4];
+        uint32_t w[kDigits];
         digit_words(rv, p, w);
         // chunk = 16 vec4 of 64 entries; plane d of the chunk at byte 64 d
         const uint64_t chunk = v >> 4;
         const uint32_t lane16 = uint32_t(v & 15);
         uint32_t* cbase = base + chunk * 64;
 #pragma unroll
-        for (int d = 0; d < 4; ++d) cbase[d * 16 + lane16] = w[d];
+        for (int d = 0; d < kDigits; ++d) cbase[d * 16 + lane16] = w[d];
     }
 }
 
 // --------------------------------------------------------------- GEMM
 // Work-group tile 128 (xA) x 64 (xB), 8 waves of 32 x 32 (two per SIMD), K
-// consumed in chunks of 64 entries (one 16x16x64 MFMA per digit pair and
-// 16x16 block). Digit tiles go from global memory straight into LDS
+// consumed in stages of 128 entries: the two digit planes of two 64-entry
+// chunks (one 16x16x64 MFMA per chunk, digit pair and 16x16 block, 32 per
+// wave and stage). Digit tiles go from global memory straight into LDS
 // (global_load_lds_dwordx4: one wave instruction fills 1 KiB, four 256-byte
-// rows) through three buffers, so the loads of chunk k+2 are in flight while
-// chunk k is multiplied: every chunk is first read by one of the work-groups
-// sharing it, which waits for HBM or the last-level cache, and one chunk of
-// look-ahead does not cover that latency. One barrier per chunk; the next
-// tile's first two chunks are requested before the current tile's epilogue.
+// rows) through three buffers, so the loads of stage k+2 are in flight while
+// stage k is multiplied: every stage is first read by one of the work-groups
+// sharing it, which waits for HBM or the last-level cache, and one stage of
+// look-ahead does not cover that latency. One barrier per stage; the next
+// tile's first two stages are requested before the current tile's epilogue.
+// When K = 64 a stage holds one chunk (loaded twice, multiplied once).
 //
-// LDS rows are 256 bytes (one chunk of one row, 16 slots of 16 bytes) with
-// slot c of row r stored at slot c ^ (r % 16). A fragment read has the 16
-// lanes of a quarter-wave on 16 consecutive rows at one logical slot, so the
-// XOR spreads them over all 16 slots (all 64 banks): conflict-free. Plain
-// rows would put them on one slot.
+// LDS rows are 256 bytes (one stage of one row, 16 slots of 16 bytes; slot
+// 8 h + 4 d + q = bytes 16 q.. of plane d of chunk h) with slot c of row r
+// stored at slot c ^ (r % 16). A fragment read has the 16 lanes of a
+// quarter-wave on 16 consecutive rows at one logical slot, so the XOR spreads
+// them over all 16 slots (all 64 banks): conflict-free. Plain rows would put
+// them on one slot.
 constexpr int kBM = 128, kBN = 64, kRowB = 256;  // LDS row stride (bytes)
 constexpr int kBuf = (kBM + kBN) * kRowB;        // one LDS buffer (48 KiB)
 constexpr int kStages = 3;
 constexpr int kThreads = 512;
 
-// V = sum_t 2^(8t) T_t is congruent to sum_t T_t w_t with w_t = 2^(8t) mod p:
-// w_0..w_3 = 1, 2^8, 2^16, 2^24 and w_4..w_6 = r, r 2^8, r 2^16 with
-// r = 2^32 mod p < 2^12. Every |T_t| < 2^30 (|T_6| < 2^26), so every term is
-// below 2^55 in magnitude and seven signed 32x32->64 multiply-adds are
-// exact; adding off (a multiple of p of at least 2^59) makes the sum
-// positive for the folding reduction.
-__device__ __forceinline__ uint32_t combine_digits(const int32_t T[7], uint32_t p, uint32_t r, uint64_t off) {
-    const int32_t ri = int32_t(r);
-    int64_t x = int64_t(T[0]);
-    x += int64_t(T[1]) * 256;
-    x += int64_t(T[2]) * 65536;
-    x += int64_t(T[3]) * 16777216;
-    x += int64_t(T[4]) * int64_t(ri);
-    x += int64_t(T[5]) * int64_t(ri << 8);
-    x += int64_t(T[6]) * int64_t(ri << 16);
+// X = T0 + 2^8 T1 + 2^16 T2 with every |T_t| <= 2^30 is below 2^47 in
+// magnitude; adding off (a multiple of p of at least 2^47) makes it positive
+// for the folding reduction.
+constexpr int kShifts = 2 * kDigits - 1;
+__device__ __forceinline__ uint32_t combine_digits(const int32_t (&T)[kShifts], uint32_t p, uint32_t r,
+                                                   uint64_t off) {
+    const int64_t x = int64_t(T[0]) + int64_t(T[1]) * 256 + int64_t(T[2]) * 65536;
     const ModP m{p, r};
     return m.finish(uint64_t(x) + off);
 }
 
-constexpr int kFlushChunks = (1 << 14) / 64;  // K chunks of 64 per exact int32 accumulation
+constexpr int kFlushStages = (1 << 15) / 128;  // K stages of 128 per exact int32 accumulation
 
 // Tile traversal. Work-groups are dealt to the 8 XCDs round-robin, so tile
 // t runs on XCD t % 8. Each XCD owns a band of A tiles (or of B tiles when
@@ -148,7 +142,7 @@ __device__ __forceinline__ void tile_coords(uint64_t tile, uint64_t tilesA, uint
     }
 }
 
-__device__ __forceinline__ void flush(v4i (&acc)[7][2][2], uint32_t (&racc)[2][2][4], uint32_t p, uint32_t r2,
+__device__ __forceinline__ void flush(v4i (&acc)[kShifts][2][2], uint32_t (&racc)[2][2][4], uint32_t p, uint32_t r2,
                                       uint64_t off) {
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
@@ -156,14 +150,14 @@ __device__ __forceinline__ void flush(v4i (&acc)[7][2][2], uint32_t (&racc)[2][2
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int32_t Tt[7];
+                int32_t Tt[kShifts];
 #pragma unroll
-                for (int t = 0; t < 7; ++t) Tt[t] = acc[t][rb][cb][v];
+                for (int t = 0; t < kShifts; ++t) Tt[t] = acc[t][rb][cb][v];
                 const uint32_t x = combine_digits(Tt, p, r2, off) + racc[rb][cb][v];
                 racc[rb][cb][v] = x >= p ? x - p : x;
             }
 #pragma unroll
-    for (int t = 0; t < 7; ++t)
+    for (int t = 0; t < kShifts; ++t)
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -191,7 +185,7 @@ __device__ __forceinline__ void chunk_barrier() {
     __asm__ volatile("" ::: "memory");
 }
 
-// One chunk of a tile into LDS buffer `dst` (wave's 1 KiB slice): A rows
+// One stage of a tile into LDS buffer `dst` (wave's 1 KiB slice): A rows
 // 4 (w + 8 i) + lane / 16 for i < 4, B rows 4 (w + 8 i) + lane / 16 for i < 2.
 __device__ __forceinline__ void fetch_chunk(const uint8_t* gA, const uint8_t* gB, uint64_t rows32, uint8_t* dst) {
     __builtin_amdgcn_global_load_lds(gA, (lds_ptr_t)dst, 16, 0, 0);
@@ -203,51 +197,48 @@ __device__ __forceinline__ void fetch_chunk(const uint8_t* gA, const uint8_t* gB
 }
 constexpr int kLoadsPerChunk = 6;
 
-// One K chunk: request the chunk at byte kb of the rows into LDS buffer
-// `dst` (wave slice; skipped when fetch is false) and multiply the chunk held
-// in buffer `src` into the shift-group accumulators. The buffers are
-// distinct, and the restrict qualifiers tell the compiler so: its wait-count
-// insertion otherwise makes every LDS read wait for all loads into LDS in
-// flight, which would undo the look-ahead. Ordering between chunks is kept
-// by chunk_barrier.
+// One K stage: request the stage at byte kb of the rows into LDS buffer
+// `dst` (wave slice; skipped when fetch is false) and multiply the stage held
+// in buffer `src` into the shift-group accumulators (its second chunk only
+// when two is set). The buffers are distinct, and the restrict qualifiers
+// tell the compiler so: its wait-count insertion otherwise makes every LDS
+// read wait for all loads into LDS in flight, which would undo the
+// look-ahead. Ordering between stages is kept by chunk_barrier.
 __device__ __forceinline__ void chunk_step(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, bool fetch,
-                                           const uint8_t* gA, const uint8_t* gB, uint64_t kb, uint64_t rows32,
-                                           int wr, int wc, int fr, const int (&sw)[4], v4i (&acc)[7][2][2]) {
-    // A fragments are double-buffered in registers: the reads of digit i+1
-    // are issued before the 16 MFMAs of digit i, so that no MFMA waits for
-    // LDS after the chunk's first reads; B fragments are read once.
+                                           bool two, const uint8_t* gA, const uint8_t* gB, uint64_t kb,
+                                           uint64_t rows32, int wr, int wc, int fr, const int (&sw)[2][kDigits],
+                                           v4i (&acc)[kShifts][2][2]) {
+    // all fragments of the stage are read first; the second chunk's reads
+    // complete while the first chunk's 16 MFMAs run
     const uint8_t* rA = src + (wr + fr) * kRowB;        // A rows of block 0 (block 1: 16 rows on)
     const uint8_t* rB = src + (kBM + wc + fr) * kRowB;  // B rows of block 0
     auto ld = [](const uint8_t* q) { return *reinterpret_cast<const v4i*>(q); };
-    v4i fb[4][2], fx[2], fy[2];
-    fx[0] = ld(rA + sw[0]);
-    fx[1] = ld(rA + 16 * kRowB + sw[0]);
+    v4i fa[2][kDigits][2], fb[2][kDigits][2];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        fb[j][0] = ld(rB + sw[j]);
-        fb[j][1] = ld(rB + 16 * kRowB + sw[j]);
-    }
-    fy[0] = ld(rA + sw[1]);
-    fy[1] = ld(rA + 16 * kRowB + sw[1]);
-    auto block = [&](int i, const v4i(&f)[2]) {
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int d = 0; d < kDigits; ++d) {
+            if (h == 1 && !two) break;
+            fa[h][d][0] = ld(rA + sw[h][d]);
+            fa[h][d][1] = ld(rA + 16 * kRowB + sw[h][d]);
+            fb[h][d][0] = ld(rB + sw[h][d]);
+            fb[h][d][1] = ld(rB + 16 * kRowB + sw[h][d]);
+        }
+    auto chunk = [&](int h) {
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+        for (int i = 0; i < kDigits; ++i)
 #pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
-                    acc[i + j][rb][cb] =
-                        __builtin_amdgcn_mfma_i32_16x16x64_i8(f[rb], fb[j][cb], acc[i + j][rb][cb], 0, 0, 0);
+            for (int j = 0; j < kDigits; ++j)
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+                        acc[i + j][rb][cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[h][i][rb], fb[h][j][cb],
+                                                                                  acc[i + j][rb][cb], 0, 0, 0);
     };
-    block(0, fx);
+    chunk(0);
     if (fetch) fetch_chunk(gA + kb, gB + kb, rows32, dst);
-    fx[0] = ld(rA + sw[2]);
-    fx[1] = ld(rA + 16 * kRowB + sw[2]);
-    block(1, fy);
-    fy[0] = ld(rA + sw[3]);
-    fy[1] = ld(rA + 16 * kRowB + sw[3]);
-    block(2, fx);
-    block(3, fy);
+    if (two) chunk(1);
 }
 
 __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, int splits, uint32_t* part,
@@ -267,9 +258,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: LDS slice bases stay scalar
     const int wr = (w & 3) * 32, wc = (w >> 2) * 32;
-    const uint64_t rowBytes = uint64_t(4) << a.s;  // K entries of 4 bytes (4 digit planes)
-    const int nk_all = 1 << (a.s - 6);
-    // split-K: block row blockIdx.y owns chunks [kc0, kc0 + nk)
+    const uint64_t rowBytes = uint64_t(4) << a.s;  // K entries of 4 bytes (digit planes in the first half of each chunk)
+    const bool two = a.s >= 7;                     // chunks per stage: 2, or 1 when K = 64
+    const int nk_all = two ? 1 << (a.s - 7) : 1;  // stages of 128 entries
+    // split-K: block row blockIdx.y owns stages [kc0, kc0 + nk)
     const int nk = nk_all / splits;
     const int kc0 = int(blockIdx.y) * nk;
     const uint64_t tilesA = uint64_t(1) << (a.fA - 7), tilesB = uint64_t(1) << (a.fB - 6);
@@ -285,29 +277,34 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
     const uint64_t offLow = pdep64(uint64_t(4 * tid), TM);
     const uint32_t iLow = uint32_t(pext64(offLow, a.maskA)), jLow = uint32_t(pext64(offLow, a.maskB));
     // loads: lane l of wave w brings row ldRow = 4 w + l / 16 (+ 32 i) into
-    // physical slot l % 16, i.e. logical slot (l % 16) ^ (ldRow % 16)
+    // physical slot l % 16, i.e. logical slot c = (l % 16) ^ (ldRow % 16):
+    // bytes 16 (c % 8).. of chunk c / 8 of the stage (chunk 0 when K = 64);
+    // stage k starts at byte 512 k of the row
     const int ldRow = 4 * w + (lane >> 4);
-    const uint64_t ldOff = uint64_t(ldRow) * rowBytes + uint64_t(((lane & 15) ^ (ldRow & 15)) * 16);
+    const int ldSlot = (lane & 15) ^ (ldRow & 15);
+    const uint64_t ldOff = uint64_t(ldRow) * rowBytes + uint64_t(two ? (ldSlot >> 3) * 256 : 0) +
+                           uint64_t((ldSlot & 7) * 16);
     const uint64_t rows32 = 32 * rowBytes;
     uint8_t* const ldsW = lds + w * 1024;
     const int fr = lane & 15;
-    // fragment of digit d: logical slot 4 d + lane / 16 of row (.. + fr)
+    // fragment of digit d of chunk h: logical slot 8 h + 4 d + lane / 16 of
+    // row (.. + fr)
     const int q4 = (lane >> 4) ^ fr;
-    const int sw[4] = {q4 * 16, (q4 ^ 4) * 16, (q4 ^ 8) * 16, (q4 ^ 12) * 16};
+    const int sw[2][kDigits] = {{q4 * 16, (q4 ^ 4) * 16}, {(q4 ^ 8) * 16, (q4 ^ 12) * 16}};
     __syncthreads();
 
     uint64_t tile = blockIdx.x, ta, tb;
     tile_coords(tile, tilesA, tilesB, ta, tb);
     const uint8_t* gA = A + ta * kBM * rowBytes + ldOff;
     const uint8_t* gB = B + tb * kBN * rowBytes + ldOff;
-    fetch_chunk(gA + uint64_t(kc0) * 256, gB + uint64_t(kc0) * 256, rows32, ldsW);
-    if (nk > 1) fetch_chunk(gA + uint64_t(kc0 + 1) * 256, gB + uint64_t(kc0 + 1) * 256, rows32, ldsW + kBuf);
+    fetch_chunk(gA + uint64_t(kc0) * 512, gB + uint64_t(kc0) * 512, rows32, ldsW);
+    if (nk > 1) fetch_chunk(gA + uint64_t(kc0 + 1) * 512, gB + uint64_t(kc0 + 1) * 512, rows32, ldsW + kBuf);
 
     for (;;) {
-        v4i acc[7][2][2];
+        v4i acc[kShifts][2][2];
         uint32_t racc[2][2][4];  // residues of the K chunks already flushed
 #pragma unroll
-        for (int t = 0; t < 7; ++t)
+        for (int t = 0; t < kShifts; ++t)
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -326,11 +323,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
             else
                 chunk_barrier<0>();
             const int nb = buf == 0 ? 2 : buf - 1;  // (kc + 2) % 3
-            chunk_step(lds + buf * kBuf, ldsW + nb * kBuf, kc + 2 < nk, gA, gB, uint64_t(kc0 + kc + 2) * 256,
+            chunk_step(lds + buf * kBuf, ldsW + nb * kBuf, kc + 2 < nk, two, gA, gB, uint64_t(kc0 + kc + 2) * 512,
                        rows32, wr, wc, fr, sw, acc);
             // every 2^14 entries of K, fold the exact int32 sums into residues
             // so they never exceed 2^30
-            if (((kc + 1) & (kFlushChunks - 1)) == 0 && kc + 1 < nk) flush(acc, racc, p, r2, off);
+            if (((kc + 1) & (kFlushStages - 1)) == 0 && kc + 1 < nk) flush(acc, racc, p, r2, off);
             buf = buf == 2 ? 0 : buf + 1;
         }
         // no wave reads this tile's chunks any more: buffers 0 and 1 may be
@@ -344,8 +341,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
             tile_coords(next, tilesA, tilesB, nta, ntb);
             nA = A + nta * kBM * rowBytes + ldOff;
             nB = B + ntb * kBN * rowBytes + ldOff;
-            fetch_chunk(nA + uint64_t(kc0) * 256, nB + uint64_t(kc0) * 256, rows32, ldsW);
-            if (nk > 1) fetch_chunk(nA + uint64_t(kc0 + 1) * 256, nB + uint64_t(kc0 + 1) * 256, rows32, ldsW + kBuf);
+            fetch_chunk(nA + uint64_t(kc0) * 512, nB + uint64_t(kc0) * 512, rows32, ldsW);
+            if (nk > 1) fetch_chunk(nA + uint64_t(kc0 + 1) * 512, nB + uint64_t(kc0 + 1) * 512, rows32, ldsW + kBuf);
         }
         // epilogue: lane holds rows 4 (lane / 16) + v, column lane % 16 of each 16x16 block
         if (splits > 1) {
@@ -357,9 +354,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
                 for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        int32_t Tt[7];
+                        int32_t Tt[kShifts];
 #pragma unroll
-                        for (int t = 0; t < 7; ++t) Tt[t] = acc[t][rb][cb][v];
+                        for (int t = 0; t < kShifts; ++t) Tt[t] = acc[t][rb][cb][v];
                         const int i = wr + rb * 16 + 4 * (lane >> 4) + v;
                         const int j = wc + cb * 16 + fr;
                         const uint32_t x = combine_digits(Tt, p, r2, off) + racc[rb][cb][v];
@@ -372,9 +369,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
                 for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        int32_t Tt[7];
+                        int32_t Tt[kShifts];
 #pragma unroll
-                        for (int t = 0; t < 7; ++t) Tt[t] = acc[t][rb][cb][v];
+                        for (int t = 0; t < kShifts; ++t) Tt[t] = acc[t][rb][cb][v];
                         const int i = wr + rb * 16 + 4 * (lane >> 4) + v;
                         const int j = wc + cb * 16 + fr;
                         const uint32_t x = combine_digits(Tt, p, r2, off) + racc[rb][cb][v];  // < 2p < 2^32
@@ -394,11 +391,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
                 const uint64_t e = baseC | o;
                 if (ex.digits_out) {
                     // the consumer is a matrix-core step: hand over digit planes
-                    uint32_t w[4];
+                    uint32_t w[kDigits];
                     digit_words(v, p, w);
                     uint32_t* cw = C + (e >> 6) * 64 + ((e & 63) >> 2);
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) cw[16 * d] = w[d];
+                    for (int d = 0; d < kDigits; ++d) cw[16 * d] = w[d];
                 } else {
                     *reinterpret_cast<uint4*>(C + e) = uint4{v[0], v[1], v[2], v[3]};
                 }
@@ -434,14 +431,11 @@ __global__ __launch_bounds__(256) void k_mfma_reduce(StepArgs a, const uint32_t*
         const uint32_t r = uint32_t(sum % p);
         if (digits_out) {
             // entry c's digit d at byte 256 (c / 64) + 64 d + c % 64
-            int32_t x = r > (p >> 1) ? int32_t(r - p) : int32_t(r);
+            const int32_t x = r > (p >> 1) ? int32_t(r - p) : int32_t(r);
+            const int32_t d0 = int32_t(int8_t(x & 0xff));
             uint8_t* cb = reinterpret_cast<uint8_t*>(C) + (c >> 6) * 256 + (c & 63);
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                const int32_t dig = d < 3 ? int32_t(int8_t(x & 0xff)) : x;
-                cb[64 * d] = uint8_t(uint32_t(dig) & 0xffu);
-                x = (x - dig) >> 8;
-            }
+            cb[0] = uint8_t(uint32_t(d0) & 0xffu);
+            cb[64] = uint8_t(uint32_t((x - d0) >> 8) & 0xffu);
         } else {
             C[c] = r;
         }
@@ -454,7 +448,7 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* p
     ex.digits_out = (dig & 4u) ? 1u : 0u;
     for (int g = 0; g < G; ++g) {
         const uint64_t p = a.p[g];
-        ex.off[g] = p * ((uint64_t(1) << 59) / p + 1);
+        ex.off[g] = p * ((uint64_t(1) << 47) / p + 1);
     }
     auto pdep = [](uint64_t x, uint64_t m) {
         uint64_t r = 0;
@@ -503,9 +497,9 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* p
     const uint64_t T = (uint64_t(1) << (a.fA - 7)) * (uint64_t(1) << (a.fB - 6));
     // too few output tiles to fill the GPU: split K over block rows (powers
     // of two, at most 128 partial tiles per plane in the scratch area, at
-    // least one 64-entry chunk each)
+    // least one 128-entry stage each)
     int splits = 1;
-    const int nk = 1 << (a.s - 6);
+    const int nk = a.s >= 7 ? 1 << (a.s - 7) : 1;
     const uint64_t cap_tiles = uint64_t(scratch_per_plane) / (4 * kBM * kBN);
     while (T * G * splits * 2 <= 1024 && splits * 2 <= nk && T * splits * 2 <= cap_tiles) splits *= 2;
     uint32_t* part = reinterpret_cast<uint32_t*>(scratch);

@@ -79,22 +79,22 @@ struct Arena {
 // Predicted device time in microseconds of one step for one prime, from
 // the kernels' measured behaviour on MI355X. Dense steps (the int8-limb
 // MFMA path: s >= 6, larger free side >= 7 bits, smaller >= 6) run at the
-// int8 peak (5e15 ops/s, 32 ops per modular multiply-add) times an
-// efficiency that grows with K = 2^s (the per-tile epilogue is amortized
-// over K): measured 0.14, 0.20, 0.35, 0.47, 0.59, 0.66, 0.69 for s = 6..12
-// and ~0.70 beyond, plus a digit pass over both operands at ~5e12 B/s and
-// the output write. Other wide steps (s >= 6) run on vector units at ~2.3e11
+// int8 peak (5e15 ops/s, 8 ops per modular multiply-add: four digit-pair
+// products) times an efficiency that grows with K = 2^s (the per-tile
+// epilogue is amortized over K; table below for s = 6..13 and beyond),
+// plus a digit pass over both operands (4 bytes read, 2 written per entry)
+// at ~5e12 B/s and the output write. Other wide steps (s >= 6) run on vector units at ~2.3e11
 // B/s of algorithmic traffic (wave per output); streaming steps move
 // 4 (2^rA + 2^rB + 2^rC) bytes at ~1e12 B/s; every launch costs ~3 us.
 double step_cost_model(int rA, int rB, int s, int rC) {
-    static const double eff[] = {0.14, 0.20, 0.35, 0.47, 0.59, 0.66, 0.69, 0.70};
+    static const double eff[] = {0.11, 0.16, 0.28, 0.38, 0.47, 0.53, 0.55, 0.56};
     const double bytes = 4.0 * (std::ldexp(1.0, rA) + std::ldexp(1.0, rB) + std::ldexp(1.0, rC));
     const double macs = std::ldexp(1.0, rA + rB - s);
     const int fa = std::max(rA, rB) - s, fb = std::min(rA, rB) - s;
     double t;
     if (s >= 6 && fa >= 7 && fb >= 6) {
         const double e = eff[std::min(s, 13) - 6];
-        t = macs * 32.0 / (5e15 * e) + 2.0 * 4.0 * (std::ldexp(1.0, rA) + std::ldexp(1.0, rB)) / 5e12 +
+        t = macs * 8.0 / (5e15 * e) + 6.0 * (std::ldexp(1.0, rA) + std::ldexp(1.0, rB)) / 5e12 +
             4.0 * std::ldexp(1.0, rC) / 2.5e12;
     } else if (s >= 6 && rC <= 6 && s >= 10) {
         t = bytes / 5e12;  // split-K dot

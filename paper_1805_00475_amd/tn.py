@@ -26,7 +26,7 @@ FLAG_TIMING = 4
 FLAG_NO_GRAPH = 8
 KERNEL_CLASSES = ["generic", "stream", "rowdot", "mfma", "batch", "dot", "digits"]
 MAX_RANK = 34
-MAX_PRIMES = 64
+MAX_PRIMES = 128
 
 
 class TNError(RuntimeError):
@@ -85,6 +85,7 @@ _SIGS = {
     "tn_count_batch": ([_P(Formula_c), ctypes.c_int32, ctypes.c_int, ctypes.c_uint64, _P(ContractOpts_c),
                         _P(ctypes.c_uint32), ctypes.c_size_t, _P(ctypes.c_size_t), _P(PlanStats_c)], ctypes.c_int),
     "tn_primes": ([ctypes.c_int32, _P(ctypes.c_uint32)], ctypes.c_int),
+    "tn_primes_for": ([ctypes.c_int32, _P(ctypes.c_int32)], ctypes.c_int),
     "tn_crt": ([_P(ctypes.c_uint32), ctypes.c_int32, _P(ctypes.c_uint32), ctypes.c_size_t, _P(ctypes.c_size_t)],
                ctypes.c_int),
     "tn_profile_get": ([_P(KernelProfile_c)], ctypes.c_int),
@@ -275,7 +276,7 @@ def contract(net: Network, plan: Plan, arith="auto", n_primes=0, workspace: Work
     n_vars = net.formula.n_vars
     if arith == "u64" or (arith == "auto" and n_vars <= 63):
         return int(u.value)
-    k = n_primes if n_primes > 0 else (n_vars + 30) // 31 + 1
+    k = n_primes if n_primes > 0 else primes_for(n_vars)
     return [int(res[i]) for i in range(k)]
 
 
@@ -432,6 +433,13 @@ def primes(k: int) -> List[int]:
     buf = (ctypes.c_uint32 * max(1, k))()
     _check(load().tn_primes(k, buf), "tn_primes")
     return [int(buf[i]) for i in range(k)]
+
+
+def primes_for(n_vars: int) -> int:
+    """Number of primes the residue path uses for n_vars variables."""
+    k = ctypes.c_int32()
+    _check(load().tn_primes_for(n_vars, ctypes.byref(k)), "tn_primes_for")
+    return int(k.value)
 
 
 def crt(residues: Sequence[int]) -> int:

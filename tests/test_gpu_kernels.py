@@ -9,7 +9,7 @@ from oracle import contract, rns
 from paper_1805_00475_amd import tn
 
 pytestmark = pytest.mark.gpu
-P = rns.largest_primes_below(1 << 31, 8)
+P = rns.largest_primes_below(65280, 8)
 
 
 def _say(*a):
