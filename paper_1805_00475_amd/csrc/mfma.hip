@@ -99,15 +99,23 @@ constexpr int kBuf = (kBM + kBN) * kRowB;        // one LDS buffer (48 KiB)
 constexpr int kStages = 3;
 constexpr int kThreads = 512;
 
-// X = T0 + 2^8 T1 + 2^16 T2 with every |T_t| <= 2^30 is below 2^47 in
-// magnitude; adding off (a multiple of p of at least 2^47) makes it positive
-// for the folding reduction.
+// X = T0 + 2^8 T1 + 2^16 T2 with every |T_t| <= 2^30 is an integer below
+// 2^47 in magnitude, so double precision holds it and every step below
+// exactly: X itself (two fused multiply-adds), q = floor(X inv_p) with
+// inv_p the double nearest 1/p (off from floor(X / p) by at most one, as
+// X / p < 2^32 and the product's error is below 2^-20), and X - q p (below
+// 2p in magnitude, one fused multiply-add). Two conditional corrections
+// give X mod p. Double-precision operations run at the full vector rate,
+// which makes this cheaper than 64-bit integer folds.
 constexpr int kShifts = 2 * kDigits - 1;
-__device__ __forceinline__ uint32_t combine_digits(const int32_t (&T)[kShifts], uint32_t p, uint32_t r,
-                                                   uint64_t off) {
-    const int64_t x = int64_t(T[0]) + int64_t(T[1]) * 256 + int64_t(T[2]) * 65536;
-    const ModP m{p, r};
-    return m.finish(uint64_t(x) + off);
+__device__ __forceinline__ uint32_t combine_digits(const int32_t (&T)[kShifts], uint32_t p, double inv_p) {
+    const double x = fma(double(T[2]), 65536.0, fma(double(T[1]), 256.0, double(T[0])));
+    const double pd = double(p);
+    const double q = floor(x * inv_p);
+    int32_t r = int32_t(fma(-q, pd, x));
+    r += r < 0 ? int32_t(p) : 0;
+    r -= r >= int32_t(p) ? int32_t(p) : 0;
+    return uint32_t(r);
 }
 
 constexpr int kFlushStages = (1 << 15) / 128;  // K stages of 128 per exact int32 accumulation
@@ -142,8 +150,8 @@ __device__ __forceinline__ void tile_coords(uint64_t tile, uint64_t tilesA, uint
     }
 }
 
-__device__ __forceinline__ void flush(v4i (&acc)[kShifts][2][2], uint32_t (&racc)[2][2][4], uint32_t p, uint32_t r2,
-                                      uint64_t off) {
+__device__ __forceinline__ void flush(v4i (&acc)[kShifts][2][2], uint32_t (&racc)[2][2][4], uint32_t p,
+                                      double inv_p) {
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -153,7 +161,7 @@ __device__ __forceinline__ void flush(v4i (&acc)[kShifts][2][2], uint32_t (&racc
                 int32_t Tt[kShifts];
 #pragma unroll
                 for (int t = 0; t < kShifts; ++t) Tt[t] = acc[t][rb][cb][v];
-                const uint32_t x = combine_digits(Tt, p, r2, off) + racc[rb][cb][v];
+                const uint32_t x = combine_digits(Tt, p, inv_p) + racc[rb][cb][v];
                 racc[rb][cb][v] = x >= p ? x - p : x;
             }
 #pragma unroll
@@ -252,8 +260,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
     const uint8_t* A = reinterpret_cast<const uint8_t*>(static_cast<const uint32_t*>(a.A) + g * a.strideA);
     const uint8_t* B = reinterpret_cast<const uint8_t*>(static_cast<const uint32_t*>(a.B) + g * a.strideB);
     uint32_t* C = static_cast<uint32_t*>(a.C) + g * a.strideC;
-    const uint32_t p = a.p[g], r2 = a.r2[g];
-    const uint64_t off = ex.off[g];
+    const uint32_t p = a.p[g];
+    const double inv_p = ex.inv_p[g];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: LDS slice bases stay scalar
@@ -327,7 +335,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
                        rows32, wr, wc, fr, sw, acc);
             // every 2^14 entries of K, fold the exact int32 sums into residues
             // so they never exceed 2^30
-            if (((kc + 1) & (kFlushStages - 1)) == 0 && kc + 1 < nk) flush(acc, racc, p, r2, off);
+            if (((kc + 1) & (kFlushStages - 1)) == 0 && kc + 1 < nk) flush(acc, racc, p, inv_p);
             buf = buf == 2 ? 0 : buf + 1;
         }
         // no wave reads this tile's chunks any more: buffers 0 and 1 may be
@@ -359,7 +367,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
                         for (int t = 0; t < kShifts; ++t) Tt[t] = acc[t][rb][cb][v];
                         const int i = wr + rb * 16 + 4 * (lane >> 4) + v;
                         const int j = wc + cb * 16 + fr;
-                        const uint32_t x = combine_digits(Tt, p, r2, off) + racc[rb][cb][v];
+                        const uint32_t x = combine_digits(Tt, p, inv_p) + racc[rb][cb][v];
                         pt[i * kBN + j] = x >= p ? x - p : x;
                     }
         } else {
@@ -374,7 +382,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
                         for (int t = 0; t < kShifts; ++t) Tt[t] = acc[t][rb][cb][v];
                         const int i = wr + rb * 16 + 4 * (lane >> 4) + v;
                         const int j = wc + cb * 16 + fr;
-                        const uint32_t x = combine_digits(Tt, p, r2, off) + racc[rb][cb][v];  // < 2p < 2^32
+                        const uint32_t x = combine_digits(Tt, p, inv_p) + racc[rb][cb][v];  // < 2p
                         sOut[i * kBN + j] = x >= p ? x - p : x;
                     }
             // staging complete (the next tile's loads may stay in flight)
@@ -447,8 +455,7 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* p
     MfmaExtra ex{};
     ex.digits_out = (dig & 4u) ? 1u : 0u;
     for (int g = 0; g < G; ++g) {
-        const uint64_t p = a.p[g];
-        ex.off[g] = p * ((uint64_t(1) << 47) / p + 1);
+        ex.inv_p[g] = 1.0 / double(a.p[g]);
     }
     auto pdep = [](uint64_t x, uint64_t m) {
         uint64_t r = 0;

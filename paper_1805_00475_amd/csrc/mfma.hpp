@@ -8,7 +8,7 @@
 namespace tn {
 
 struct MfmaExtra {
-    uint64_t off[kMaxGroup];  // a multiple of p at least 2^47, per prime
+    double inv_p[kMaxGroup];  // the double nearest 1/p, per prime
     // output tile positions 2048 q (q < 4) beyond a thread's first: C offset
     // bits and the A-side and B-side tile-local indices; dI, dJ: the indices
     // of the word k (< 4) after a position whose two lowest bits are 0

@@ -87,7 +87,7 @@ struct Arena {
 // B/s of algorithmic traffic (wave per output); streaming steps move
 // 4 (2^rA + 2^rB + 2^rC) bytes at ~1e12 B/s; every launch costs ~3 us.
 double step_cost_model(int rA, int rB, int s, int rC) {
-    static const double eff[] = {0.11, 0.16, 0.28, 0.38, 0.47, 0.53, 0.55, 0.56};
+    static const double eff[] = {0.042, 0.087, 0.12, 0.22, 0.31, 0.39, 0.45, 0.45};
     const double bytes = 4.0 * (std::ldexp(1.0, rA) + std::ldexp(1.0, rB) + std::ldexp(1.0, rC));
     const double macs = std::ldexp(1.0, rA + rB - s);
     const int fa = std::max(rA, rB) - s, fb = std::min(rA, rB) - s;
