@@ -150,8 +150,10 @@ __device__ __forceinline__ void tile_coords(uint64_t tile, uint64_t tilesA, uint
     }
 }
 
-__device__ __forceinline__ void flush(v4i (&acc)[kShifts][2][2], uint32_t (&racc)[2][2][4], uint32_t p,
-                                      double inv_p) {
+// Every 2^15 entries of K the exact sums are reduced: T0 takes the residue
+// of X (below p < 2^16) and T1, T2 restart from zero, so the next range adds
+// at most 2^29 to T0 and the bounds above hold again.
+__device__ __forceinline__ void flush(v4i (&acc)[kShifts][2][2], uint32_t p, double inv_p) {
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -161,15 +163,10 @@ __device__ __forceinline__ void flush(v4i (&acc)[kShifts][2][2], uint32_t (&racc
                 int32_t Tt[kShifts];
 #pragma unroll
                 for (int t = 0; t < kShifts; ++t) Tt[t] = acc[t][rb][cb][v];
-                const uint32_t x = combine_digits(Tt, p, inv_p) + racc[rb][cb][v];
-                racc[rb][cb][v] = x >= p ? x - p : x;
+                acc[0][rb][cb][v] = int32_t(combine_digits(Tt, p, inv_p));
+#pragma unroll
+                for (int t = 1; t < kShifts; ++t) acc[t][rb][cb][v] = 0;
             }
-#pragma unroll
-    for (int t = 0; t < kShifts; ++t)
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) acc[t][rb][cb] = v4i{0, 0, 0, 0};
 }
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
@@ -310,19 +307,12 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
 
     for (;;) {
         v4i acc[kShifts][2][2];
-        uint32_t racc[2][2][4];  // residues of the K chunks already flushed
 #pragma unroll
         for (int t = 0; t < kShifts; ++t)
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) acc[t][i][j] = v4i{0, 0, 0, 0};
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) racc[i][j][v] = 0;
 
         int buf = 0;  // kc % 3
         for (int kc = 0; kc < nk; ++kc) {
@@ -333,9 +323,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
             const int nb = buf == 0 ? 2 : buf - 1;  // (kc + 2) % 3
             chunk_step(lds + buf * kBuf, ldsW + nb * kBuf, kc + 2 < nk, two, gA, gB, uint64_t(kc0 + kc + 2) * 512,
                        rows32, wr, wc, fr, sw, acc);
-            // every 2^14 entries of K, fold the exact int32 sums into residues
-            // so they never exceed 2^30
-            if (((kc + 1) & (kFlushStages - 1)) == 0 && kc + 1 < nk) flush(acc, racc, p, inv_p);
+            if (((kc + 1) & (kFlushStages - 1)) == 0 && kc + 1 < nk) flush(acc, p, inv_p);
             buf = buf == 2 ? 0 : buf + 1;
         }
         // no wave reads this tile's chunks any more: buffers 0 and 1 may be
@@ -367,8 +355,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
                         for (int t = 0; t < kShifts; ++t) Tt[t] = acc[t][rb][cb][v];
                         const int i = wr + rb * 16 + 4 * (lane >> 4) + v;
                         const int j = wc + cb * 16 + fr;
-                        const uint32_t x = combine_digits(Tt, p, inv_p) + racc[rb][cb][v];
-                        pt[i * kBN + j] = x >= p ? x - p : x;
+                        pt[i * kBN + j] = combine_digits(Tt, p, inv_p);
                     }
         } else {
 #pragma unroll
@@ -382,8 +369,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
                         for (int t = 0; t < kShifts; ++t) Tt[t] = acc[t][rb][cb][v];
                         const int i = wr + rb * 16 + 4 * (lane >> 4) + v;
                         const int j = wc + cb * 16 + fr;
-                        const uint32_t x = combine_digits(Tt, p, inv_p) + racc[rb][cb][v];  // < 2p
-                        sOut[i * kBN + j] = x >= p ? x - p : x;
+                        sOut[i * kBN + j] = combine_digits(Tt, p, inv_p);
                     }
             // staging complete (the next tile's loads may stay in flight)
             chunk_barrier<63>();

@@ -71,7 +71,7 @@ SMALL = [
     ("stream", 14, 5, 3), ("stream", 12, 3, 1), ("stream", 13, 7, 5), ("stream", 10, 2, 0),
     ("rowdot", 12, 10, 8), ("rowdot", 9, 9, 9), ("rowdot", 14, 8, 7),
     ("mfma", 13, 12, 6), ("mfma", 18, 17, 8), ("mfma", 16, 15, 9), ("mfma", 21, 20, 14), ("mfma", 15, 14, 7),
-    ("mfma", 22, 21, 15), ("mfma", 23, 22, 14), ("mfma", 17, 16, 10),
+    ("mfma", 22, 21, 15), ("mfma", 23, 22, 14), ("mfma", 17, 16, 10), ("mfma", 23, 23, 16),
     ("dot", 14, 14, 14), ("dot", 16, 15, 13), ("dot", 12, 12, 10),
     ("auto", 16, 15, 9), ("auto", 12, 3, 1), ("auto", 18, 18, 16),
 ]
@@ -84,8 +84,8 @@ def test_kernel_rns(kernel, rA, rB, s):
 
 
 @pytest.mark.parametrize("kind", ["max", "half"])
-@pytest.mark.parametrize("kernel,rA,rB,s", [("mfma", 16, 15, 9), ("stream", 13, 7, 5), ("rowdot", 12, 10, 8),
-                                            ("generic", 9, 7, 3)])
+@pytest.mark.parametrize("kernel,rA,rB,s", [("mfma", 16, 15, 9), ("mfma", 23, 22, 16), ("stream", 13, 7, 5),
+                                            ("rowdot", 12, 10, 8), ("generic", 9, 7, 3)])
 def test_kernel_extreme_residues(kernel, rA, rB, s, kind):
     _check(rA, rB, s, kernel, P[-1], seed=7, kind=kind, samples=2000)
 
