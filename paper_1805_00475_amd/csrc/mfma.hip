@@ -10,11 +10,10 @@
 // where A_i, B_j are int8 digit matrices; every T_t is accumulated by the
 // int8 MFMA into int32 registers. Each product of digits is at most 2^14 in
 // magnitude and at most two digit pairs share a shift, so K <= 2^15 keeps
-// every T_t at most 2^30 -- exact; wider K is summed in ranges of 2^15 whose
-// results are reduced to residues and added modulo p. The epilogue forms
-// X = T0 + 2^8 T1 + 2^16 T2 in 64-bit integers (|X| < 2^47), adds a multiple
-// of p of at least 2^47, and reduces with the folding reduction of the other
-// kernels.
+// every T_t at most 2^30 -- exact; wider K is summed in ranges of 2^15, each
+// reduced to a residue that seeds the next range. The epilogue forms
+// X = T0 + 2^8 T1 + 2^16 T2 (|X| < 2^47) and reduces it modulo p in double
+// precision, where every step is exact.
 //
 // Two kernels per step: k_digits rewrites A and B in place (they die at this
 // step) so that every 64-entry chunk of a row (256 bytes) starts with its two
@@ -76,17 +75,23 @@ __global__ __launch_bounds__(256) void k_digits(uint32_t* X, int64_t stride, uin
 }
 
 // --------------------------------------------------------------- GEMM
-// Work-group tile 128 (xA) x 64 (xB), 8 waves of 32 x 32 (two per SIMD), K
+// Work-group tile 128 (xA) x 64 (xB), used when B's free side has 6 bits.
+// Each launch row sums at most 2^15 entries of K (one exact range; wider K
+// is always split over block rows). 8 waves of 32 x 32 (two per SIMD), K
 // consumed in stages of 128 entries: the two digit planes of two 64-entry
-// chunks (one 16x16x64 MFMA per chunk, digit pair and 16x16 block, 32 per
-// wave and stage). Digit tiles go from global memory straight into LDS
+// chunks (one 16x16x64 MFMA per chunk, digit pair and 16x16 block, 16 per
+// wave and chunk). Digit tiles go from global memory straight into LDS
 // (global_load_lds_dwordx4: one wave instruction fills 1 KiB, four 256-byte
-// rows) through three buffers, so the loads of stage k+2 are in flight while
-// stage k is multiplied: every stage is first read by one of the work-groups
-// sharing it, which waits for HBM or the last-level cache, and one stage of
-// look-ahead does not cover that latency. One barrier per stage; the next
-// tile's first two stages are requested before the current tile's epilogue.
-// When K = 64 a stage holds one chunk (loaded twice, multiplied once).
+// rows) through three buffers; stage k+3 is requested while stage k is
+// multiplied, two stages before it is read, since every stage is first read
+// by one of the work-groups sharing it, which waits for HBM or the last-level
+// cache. The barrier that makes stage k+1 visible sits between the two
+// chunks of stage k: the fragments of stage k's second chunk are read while
+// its first chunk is multiplied, and those of stage k+1's first chunk while
+// its second chunk is, so the matrix cores do not wait for LDS reads after a
+// barrier. The next tile's first two stages are requested at the last
+// barrier of the current tile, before its last chunk and epilogue. When
+// K = 64 a stage holds one chunk (loaded twice, multiplied once).
 //
 // LDS rows are 256 bytes (one stage of one row, 16 slots of 16 bytes; slot
 // 8 h + 4 d + q = bytes 16 q.. of plane d of chunk h) with slot c of row r
@@ -118,7 +123,6 @@ __device__ __forceinline__ uint32_t combine_digits(const int32_t (&T)[kShifts], 
     return uint32_t(r);
 }
 
-constexpr int kFlushStages = (1 << 15) / 128;  // K stages of 128 per exact int32 accumulation
 
 // Tile traversal. Work-groups are dealt to the 8 XCDs round-robin, so tile
 // t runs on XCD t % 8. Each XCD owns a band of A tiles (or of B tiles when
@@ -153,11 +157,12 @@ __device__ __forceinline__ void tile_coords(uint64_t tile, uint64_t tilesA, uint
 // Every 2^15 entries of K the exact sums are reduced: T0 takes the residue
 // of X (below p < 2^16) and T1, T2 restart from zero, so the next range adds
 // at most 2^29 to T0 and the bounds above hold again.
-__device__ __forceinline__ void flush(v4i (&acc)[kShifts][2][2], uint32_t p, double inv_p) {
+template <int RB, int CB>
+__device__ __forceinline__ void flush(v4i (&acc)[kShifts][RB][CB], uint32_t p, double inv_p) {
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+        for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 int32_t Tt[kShifts];
@@ -202,50 +207,42 @@ __device__ __forceinline__ void fetch_chunk(const uint8_t* gA, const uint8_t* gB
 }
 constexpr int kLoadsPerChunk = 6;
 
-// One K stage: request the stage at byte kb of the rows into LDS buffer
-// `dst` (wave slice; skipped when fetch is false) and multiply the stage held
-// in buffer `src` into the shift-group accumulators (its second chunk only
-// when two is set). The buffers are distinct, and the restrict qualifiers
-// tell the compiler so: its wait-count insertion otherwise makes every LDS
-// read wait for all loads into LDS in flight, which would undo the
-// look-ahead. Ordering between stages is kept by chunk_barrier.
-__device__ __forceinline__ void chunk_step(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, bool fetch,
-                                           bool two, const uint8_t* gA, const uint8_t* gB, uint64_t kb,
-                                           uint64_t rows32, int wr, int wc, int fr, const int (&sw)[2][kDigits],
-                                           v4i (&acc)[kShifts][2][2]) {
-    // all fragments of the stage are read first; the second chunk's reads
-    // complete while the first chunk's 16 MFMAs run
-    const uint8_t* rA = src + (wr + fr) * kRowB;        // A rows of block 0 (block 1: 16 rows on)
-    const uint8_t* rB = src + (kBM + wc + fr) * kRowB;  // B rows of block 0
+// Fragments of chunk h of the stage in LDS buffer `src`: A rows wr + fr
+// (+16) and B rows wc + fr (+16) at the wave's logical slot of each digit.
+struct Frags {
+    v4i a[kDigits][2], b[kDigits][2];
+};
+__device__ __forceinline__ void read_frags(const uint8_t* src, int wr, int wc, int fr,
+                                           const int (&sw)[kDigits], Frags& f) {
+    const uint8_t* rA = src + (wr + fr) * kRowB;
+    const uint8_t* rB = src + (kBM + wc + fr) * kRowB;
     auto ld = [](const uint8_t* q) { return *reinterpret_cast<const v4i*>(q); };
-    v4i fa[2][kDigits][2], fb[2][kDigits][2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int d = 0; d < kDigits; ++d) {
-            if (h == 1 && !two) break;
-            fa[h][d][0] = ld(rA + sw[h][d]);
-            fa[h][d][1] = ld(rA + 16 * kRowB + sw[h][d]);
-            fb[h][d][0] = ld(rB + sw[h][d]);
-            fb[h][d][1] = ld(rB + 16 * kRowB + sw[h][d]);
-        }
-    auto chunk = [&](int h) {
-#pragma unroll
-        for (int i = 0; i < kDigits; ++i)
-#pragma unroll
-            for (int j = 0; j < kDigits; ++j)
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                    for (int cb = 0; cb < 2; ++cb)
-                        acc[i + j][rb][cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[h][i][rb], fb[h][j][cb],
-                                                                                  acc[i + j][rb][cb], 0, 0, 0);
-    };
-    chunk(0);
-    if (fetch) fetch_chunk(gA + kb, gB + kb, rows32, dst);
-    if (two) chunk(1);
+    for (int d = 0; d < kDigits; ++d) {
+        f.a[d][0] = ld(rA + sw[d]);
+        f.a[d][1] = ld(rA + 16 * kRowB + sw[d]);
+        f.b[d][0] = ld(rB + sw[d]);
+        f.b[d][1] = ld(rB + 16 * kRowB + sw[d]);
+    }
 }
 
+// 16 MFMAs of one chunk: digit pair (i, j) of every 16x16 block pair into
+// shift group i + j.
+__device__ __forceinline__ void mfma_chunk(const Frags& f, v4i (&acc)[kShifts][2][2]) {
+#pragma unroll
+    for (int i = 0; i < kDigits; ++i)
+#pragma unroll
+        for (int j = 0; j < kDigits; ++j)
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    acc[i + j][rb][cb] =
+                        __builtin_amdgcn_mfma_i32_16x16x64_i8(f.a[i][rb], f.b[j][cb], acc[i + j][rb][cb], 0, 0, 0);
+}
+
+// TWO: K >= 128 (two chunks per stage); otherwise K = 64 (one chunk).
+template <bool TWO>
 __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, int splits, uint32_t* part,
                                                       int64_t part_stride) {
     __shared__ __align__(1024) uint8_t lds[kStages * kBuf];
@@ -264,8 +261,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: LDS slice bases stay scalar
     const int wr = (w & 3) * 32, wc = (w >> 2) * 32;
     const uint64_t rowBytes = uint64_t(4) << a.s;  // K entries of 4 bytes (digit planes in the first half of each chunk)
-    const bool two = a.s >= 7;                     // chunks per stage: 2, or 1 when K = 64
-    const int nk_all = two ? 1 << (a.s - 7) : 1;  // stages of 128 entries
+    const int nk_all = TWO ? 1 << (a.s - 7) : 1;  // stages of 128 entries
     // split-K: block row blockIdx.y owns stages [kc0, kc0 + nk)
     const int nk = nk_all / splits;
     const int kc0 = int(blockIdx.y) * nk;
@@ -287,7 +283,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
     // stage k starts at byte 512 k of the row
     const int ldRow = 4 * w + (lane >> 4);
     const int ldSlot = (lane & 15) ^ (ldRow & 15);
-    const uint64_t ldOff = uint64_t(ldRow) * rowBytes + uint64_t(two ? (ldSlot >> 3) * 256 : 0) +
+    const uint64_t ldOff = uint64_t(ldRow) * rowBytes + uint64_t(TWO ? (ldSlot >> 3) * 256 : 0) +
                            uint64_t((ldSlot & 7) * 16);
     const uint64_t rows32 = 32 * rowBytes;
     uint8_t* const ldsW = lds + w * 1024;
@@ -314,25 +310,44 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
 #pragma unroll
                 for (int j = 0; j < 2; ++j) acc[t][i][j] = v4i{0, 0, 0, 0};
 
-        int buf = 0;  // kc % 3
-        for (int kc = 0; kc < nk; ++kc) {
-            if (kc + 1 < nk)
-                chunk_barrier<kLoadsPerChunk>();
-            else
-                chunk_barrier<0>();
-            const int nb = buf == 0 ? 2 : buf - 1;  // (kc + 2) % 3
-            chunk_step(lds + buf * kBuf, ldsW + nb * kBuf, kc + 2 < nk, two, gA, gB, uint64_t(kc0 + kc + 2) * 512,
-                       rows32, wr, wc, fr, sw, acc);
-            if (((kc + 1) & (kFlushStages - 1)) == 0 && kc + 1 < nk) flush(acc, p, inv_p);
-            buf = buf == 2 ? 0 : buf + 1;
-        }
-        // no wave reads this tile's chunks any more: buffers 0 and 1 may be
-        // refilled and buffer 2 may hold the output staging
-        chunk_barrier<0>();
+        // stage 0 has landed (stage 1 may still be in flight), and every
+        // wave is done with the previous tile's output staging in buffer 2
+        if (nk > 1)
+            chunk_barrier<kLoadsPerChunk>();
+        else
+            chunk_barrier<0>();
+        if (nk > 2) fetch_chunk(gA + uint64_t(kc0 + 2) * 512, gB + uint64_t(kc0 + 2) * 512, rows32, ldsW + 2 * kBuf);
+        Frags f0, f1;
+        read_frags(lds, wr, wc, fr, sw[0], f0);
+
         const uint64_t next = tile + gridDim.x;
         const bool more = next < T;
         uint64_t nta = 0, ntb = 0;
         const uint8_t *nA = gA, *nB = gB;
+        int buf = 0;  // kc % 3
+        for (int kc = 0; kc + 1 < nk; ++kc) {
+            const int nb = buf == 2 ? 0 : buf + 1;
+            read_frags(lds + buf * kBuf, wr, wc, fr, sw[1], f1);
+            mfma_chunk(f0, acc);
+            // stage kc + 1 has landed (kc + 2 may be in flight) and no wave
+            // reads stage kc any more: its buffer takes stage kc + 3
+            if (kc + 2 < nk)
+                chunk_barrier<kLoadsPerChunk>();
+            else
+                chunk_barrier<0>();
+            if (kc + 3 < nk)
+                fetch_chunk(gA + uint64_t(kc0 + kc + 3) * 512, gB + uint64_t(kc0 + kc + 3) * 512, rows32,
+                            ldsW + buf * kBuf);
+            read_frags(lds + nb * kBuf, wr, wc, fr, sw[0], f0);
+            mfma_chunk(f1, acc);
+            buf = nb;
+        }
+        // last stage
+        if (TWO) read_frags(lds + buf * kBuf, wr, wc, fr, sw[1], f1);
+        mfma_chunk(f0, acc);
+        // every fragment of this tile is in registers: buffers 0 and 1 take
+        // the next tile's first stages, buffer 2 the output staging
+        chunk_barrier<63>();
         if (more) {
             tile_coords(next, tilesA, tilesB, nta, ntb);
             nA = A + nta * kBM * rowBytes + ldOff;
@@ -340,6 +355,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
             fetch_chunk(nA + uint64_t(kc0) * 512, nB + uint64_t(kc0) * 512, rows32, ldsW);
             if (nk > 1) fetch_chunk(nA + uint64_t(kc0 + 1) * 512, nB + uint64_t(kc0 + 1) * 512, rows32, ldsW + kBuf);
         }
+        if (TWO) mfma_chunk(f1, acc);
         // epilogue: lane holds rows 4 (lane / 16) + v, column lane % 16 of each 16x16 block
         if (splits > 1) {
             // partial residue of this K range, tile-local order (i, j)
@@ -404,24 +420,281 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
     }
 }
 
+
+// ------------------------------------------------------ square-tile GEMM
+// Work-group tile 128 (xA) x 128 (xB), 8 waves of 64 x 32 (two per SIMD),
+// used when both free sides have at least 7 bits. Per entry of K the tile
+// loads 512 bytes of digits for 16384 outputs, a third less than the
+// 128 x 64 tile above, and each wave reads 48 fragment registers per chunk
+// for 32 MFMAs instead of 32 for 16: the loads into LDS, not the matrix
+// cores, bound the narrower tile. K goes in stages of one 64-entry chunk
+// (128-byte LDS rows: the two digit planes) through four 32 KiB buffers.
+// Chunk k+4 is requested while chunk k is multiplied; one barrier per chunk
+// makes chunk k+1 visible and frees chunk k's buffer, after which the wave
+// reads chunk k+1's fragments while chunk k's MFMAs run (fragment register
+// sets alternate between chunks). The next tile's first two chunks are
+// requested at the tile's last barrier; the output staging (64 KiB) uses
+// buffers 2 and 3.
+//
+// LDS rows are 128 bytes (8 slots of 16 bytes; slot 4 d + q = bytes 16 q..
+// of plane d), slot c of row r stored at slot c ^ ((r / 2) % 8). A fragment
+// read has a quarter-wave on 16 consecutive rows at one logical slot: rows
+// of equal parity land on 8 distinct slots and the two parities on the two
+// halves of the 256-byte bank width, so all 64 banks are hit once.
+constexpr int kSqM = 128, kSqN = 128, kSqRow = 128;
+constexpr int kSqBuf = (kSqM + kSqN) * kSqRow;  // 32 KiB
+constexpr int kSqBufs = 4;
+constexpr int kSqLoads = 4;               // load instructions per wave and chunk
+constexpr int kSqFlush = (1 << 15) / 64;  // chunks per exact int32 range
+
+struct SqFrags {
+    v4i a[kDigits][4], b[kDigits][2];
+};
+
+// fragments of the chunk in buffer `src`: A rows wr + 16 rb + fr, B rows
+// wc + 16 cb + fr, each at the lane's slot of digit plane d
+__device__ __forceinline__ void sq_read(const uint8_t* src, int wr, int wc, int fr, const int (&sw)[kDigits],
+                                        SqFrags& f) {
+    const uint8_t* rA = src + (wr + fr) * kSqRow;
+    const uint8_t* rB = src + (kSqM + wc + fr) * kSqRow;
+    auto ld = [](const uint8_t* q) { return *reinterpret_cast<const v4i*>(q); };
+#pragma unroll
+    for (int d = 0; d < kDigits; ++d) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) f.a[d][rb] = ld(rA + rb * 16 * kSqRow + sw[d]);
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) f.b[d][cb] = ld(rB + cb * 16 * kSqRow + sw[d]);
+    }
+}
+
+__device__ __forceinline__ void sq_mfma(const SqFrags& f, v4i (&acc)[kShifts][4][2]) {
+#pragma unroll
+    for (int i = 0; i < kDigits; ++i)
+#pragma unroll
+        for (int j = 0; j < kDigits; ++j)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    acc[i + j][rb][cb] =
+                        __builtin_amdgcn_mfma_i32_16x16x64_i8(f.a[i][rb], f.b[j][cb], acc[i + j][rb][cb], 0, 0, 0);
+}
+
+// One chunk of a tile into LDS buffer `dst` (wave's 1 KiB slices): lane l
+// of wave w brings tile row 8 w + l / 8 (+ 64) of A and of B, 16 bytes at
+// byte voff of that row; tA, tB are the tiles' first rows (wave-uniform).
+__device__ __forceinline__ void sq_fetch(const uint8_t* tA, const uint8_t* tB, uint64_t chunk, uint64_t rows64,
+                                         uint32_t voff, uint8_t* dst) {
+    const uint64_t co = chunk * 256;
+    __builtin_amdgcn_global_load_lds(tA + co + voff, (lds_ptr_t)dst, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(tA + co + rows64 + voff, (lds_ptr_t)(dst + 8 * 1024), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(tB + co + voff, (lds_ptr_t)(dst + 16 * 1024), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(tB + co + rows64 + voff, (lds_ptr_t)(dst + 24 * 1024), 16, 0, 0);
+}
+
+__global__ __launch_bounds__(kThreads, 1) void k_mfma_sq(StepArgs a, MfmaExtra ex, int splits, uint32_t* part,
+                                                         int64_t part_stride) {
+    __shared__ __align__(1024) uint8_t lds[kSqBufs * kSqBuf];
+    uint32_t* sOut = reinterpret_cast<uint32_t*>(lds + 2 * kSqBuf);  // buffers 2 and 3
+
+    const int g = blockIdx.z;
+    const uint8_t* A = reinterpret_cast<const uint8_t*>(static_cast<const uint32_t*>(a.A) + g * a.strideA);
+    const uint8_t* B = reinterpret_cast<const uint8_t*>(static_cast<const uint32_t*>(a.B) + g * a.strideB);
+    uint32_t* C = static_cast<uint32_t*>(a.C) + g * a.strideC;
+    const uint32_t p = a.p[g];
+    const double inv_p = ex.inv_p[g];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = (w & 1) * 64, wc = (w >> 1) * 32;
+    const uint64_t rowBytes = uint64_t(4) << a.s;
+    const int nk_all = 1 << (a.s - 6);  // chunks of 64 entries
+    const int nk = nk_all / splits;
+    const int kc0 = int(blockIdx.y) * nk;
+    const uint64_t tilesA = uint64_t(1) << (a.fA - 7), tilesB = uint64_t(1) << (a.fB - 7);
+    const uint64_t T = tilesA * tilesB;
+    if (uint64_t(blockIdx.x) >= T) return;
+
+    // output mapping: tile-local t = 4 tid + k + 2048 q (k < 4, q < 8) at
+    // position pdep(t, TM), TM = the 7 lowest A bits and 7 lowest B bits of
+    // C; the 7 lowest bits of C are always tile bits, so k adds to the
+    // position and each thread writes four consecutive words per q
+    const uint64_t TM = pdep64(127, a.maskA) | pdep64(127, a.maskB);
+    const uint64_t offLow = pdep64(uint64_t(4 * tid), TM);
+    const uint32_t iLow = uint32_t(pext64(offLow, a.maskA)), jLow = uint32_t(pext64(offLow, a.maskB));
+    // loads: lane l of wave w fills physical slot l % 8 of row 8 w + l / 8,
+    // i.e. logical slot c = (l % 8) ^ ((4 w + l / 16) % 8): bytes 16 c.. of
+    // the row's chunk (plane c / 4)
+    const uint32_t ldRow = uint32_t(8 * w + (lane >> 3));
+    const uint32_t ldSlot = uint32_t((lane & 7) ^ ((4 * (w & 1) + (lane >> 4)) & 7));
+    const uint32_t voff = ldRow * uint32_t(rowBytes) + 16 * ldSlot;
+    const uint64_t rows64 = 64 * rowBytes;
+    uint8_t* const ldsW = lds + w * 1024;
+    const int fr = lane & 15, q = lane >> 4;
+    const int sw[kDigits] = {((0 + q) ^ (fr >> 1)) * 16, ((4 + q) ^ (fr >> 1)) * 16};
+    __syncthreads();
+
+    uint64_t tile = blockIdx.x, ta, tb;
+    tile_coords(tile, tilesA, tilesB, ta, tb);
+    const uint8_t* tA = A + ta * kSqM * rowBytes;
+    const uint8_t* tB = B + tb * kSqN * rowBytes;
+    sq_fetch(tA, tB, uint64_t(kc0), rows64, voff, ldsW);
+    if (nk > 1) sq_fetch(tA, tB, uint64_t(kc0 + 1), rows64, voff, ldsW + kSqBuf);
+
+    for (;;) {
+        v4i acc[kShifts][4][2];
+#pragma unroll
+        for (int t = 0; t < kShifts; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[t][i][j] = v4i{0, 0, 0, 0};
+
+        // chunk 0 has landed (chunk 1 may be in flight), and every wave is
+        // done with the previous tile's output staging in buffers 2 and 3
+        if (nk > 1)
+            chunk_barrier<kSqLoads>();
+        else
+            chunk_barrier<0>();
+        if (nk > 2) sq_fetch(tA, tB, uint64_t(kc0 + 2), rows64, voff, ldsW + 2 * kSqBuf);
+        if (nk > 3) sq_fetch(tA, tB, uint64_t(kc0 + 3), rows64, voff, ldsW + 3 * kSqBuf);
+        SqFrags f0, f1;
+        sq_read(lds, wr, wc, fr, sw, f0);
+
+        const uint64_t next = tile + gridDim.x;
+        const bool more = next < T;
+        uint64_t nta = 0, ntb = 0;
+        const uint8_t *nA = tA, *nB = tB;
+
+        // chunk kc (fragments in cur) while chunk kc + 1 is read into nxt
+        auto step = [&](int kc, SqFrags& cur, SqFrags& nxt) {
+            // chunk kc + 1 has landed (up to two later ones may be in
+            // flight) and no wave reads chunk kc any more: its buffer takes
+            // chunk kc + 4
+            const int ahead = nk - 2 - kc;
+            if (ahead >= 2)
+                chunk_barrier<2 * kSqLoads>();
+            else if (ahead == 1)
+                chunk_barrier<kSqLoads>();
+            else
+                chunk_barrier<0>();
+            if (kc + 4 < nk) sq_fetch(tA, tB, uint64_t(kc0 + kc + 4), rows64, voff, ldsW + (kc & 3) * kSqBuf);
+            sq_read(lds + ((kc + 1) & 3) * kSqBuf, wr, wc, fr, sw, nxt);
+            sq_mfma(cur, acc);
+            if (((kc + 1) & (kSqFlush - 1)) == 0) flush(acc, p, inv_p);
+        };
+        // the tile's last chunk: every fragment is in registers, so buffers
+        // 0 and 1 take the next tile's first chunks
+        auto last = [&](SqFrags& cur) {
+            chunk_barrier<63>();
+            if (more) {
+                tile_coords(next, tilesA, tilesB, nta, ntb);
+                nA = A + nta * kSqM * rowBytes;
+                nB = B + ntb * kSqN * rowBytes;
+                sq_fetch(nA, nB, uint64_t(kc0), rows64, voff, ldsW);
+                if (nk > 1) sq_fetch(nA, nB, uint64_t(kc0 + 1), rows64, voff, ldsW + kSqBuf);
+            }
+            sq_mfma(cur, acc);
+        };
+        int kc = 0;
+        for (; kc + 2 < nk; kc += 2) {
+            step(kc, f0, f1);
+            step(kc + 1, f1, f0);
+        }
+        if (kc + 1 < nk) {
+            step(kc, f0, f1);
+            last(f1);
+        } else {
+            last(f0);
+        }
+
+        // epilogue: lane holds rows 4 (lane / 16) + v, column lane % 16 of each 16x16 block
+        if (splits > 1) {
+            uint32_t* pt = part + blockIdx.z * part_stride + (uint64_t(blockIdx.y) * T + tile) * (kSqM * kSqN);
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        int32_t Tt[kShifts];
+#pragma unroll
+                        for (int t = 0; t < kShifts; ++t) Tt[t] = acc[t][rb][cb][v];
+                        const int i = wr + rb * 16 + 4 * q + v;
+                        const int j = wc + cb * 16 + fr;
+                        pt[i * kSqN + j] = combine_digits(Tt, p, inv_p);
+                    }
+        } else {
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        int32_t Tt[kShifts];
+#pragma unroll
+                        for (int t = 0; t < kShifts; ++t) Tt[t] = acc[t][rb][cb][v];
+                        const int i = wr + rb * 16 + 4 * q + v;
+                        const int j = wc + cb * 16 + fr;
+                        sOut[i * kSqN + j] = combine_digits(Tt, p, inv_p);
+                    }
+            // staging complete (the next tile's loads may stay in flight)
+            chunk_barrier<63>();
+            const uint64_t baseC = pdep64(ta * kSqM, a.maskA) | pdep64(tb * kSqN, a.maskB);
+            // the store addresses are formed here, per tile: hoisted out of
+            // the tile loop they would hold 48 registers through the K loop
+            uint64_t oLow = offLow;
+            uint32_t iL = iLow, jL = jLow;
+            __asm__ volatile("" : "+v"(oLow), "+v"(iL), "+v"(jL));
+#pragma unroll
+            for (int qq = 0; qq < 8; ++qq) {
+                const uint64_t o = oLow | ex.hiOff[qq];
+                const uint32_t i = iL | ex.hiI[qq];
+                const uint32_t j = jL | ex.hiJ[qq];
+                const uint32_t v[4] = {sOut[i * kSqN + j], sOut[(i | ex.dI[1]) * kSqN + (j | ex.dJ[1])],
+                                       sOut[(i | ex.dI[2]) * kSqN + (j | ex.dJ[2])],
+                                       sOut[(i | ex.dI[3]) * kSqN + (j | ex.dJ[3])]};
+                const uint64_t e = baseC | o;
+                if (ex.digits_out) {
+                    uint32_t wd[kDigits];
+                    digit_words(v, p, wd);
+                    uint32_t* cw = C + (e >> 6) * 64 + ((e & 63) >> 2);
+#pragma unroll
+                    for (int d = 0; d < kDigits; ++d) cw[16 * d] = wd[d];
+                } else {
+                    *reinterpret_cast<uint4*>(C + e) = uint4{v[0], v[1], v[2], v[3]};
+                }
+            }
+        }
+        if (!more) break;
+        tile = next;
+        ta = nta;
+        tb = ntb;
+        tA = nA;
+        tB = nB;
+    }
+}
+
 // split-K: add the partial residues of every K range and scatter into C
+// (tiles of 128 x BN)
+template <int BN>
 __global__ __launch_bounds__(256) void k_mfma_reduce(StepArgs a, const uint32_t* part, int64_t part_stride,
                                                      int splits, int digits_out) {
     const int g = blockIdx.z;
     const uint32_t p = a.p[g];
     uint32_t* C = static_cast<uint32_t*>(a.C) + g * a.strideC;
-    const uint64_t tilesA = uint64_t(1) << (a.fA - 7), tilesB = uint64_t(1) << (a.fB - 6);
+    const uint64_t tilesA = uint64_t(1) << (a.fA - 7), tilesB = uint64_t(1) << (a.fB - (BN == 128 ? 7 : 6));
     const uint64_t T = tilesA * tilesB;
-    const uint64_t n = T * (kBM * kBN);
+    const uint64_t n = T * (kBM * BN);
     const uint32_t* pg = part + g * part_stride;
     for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += uint64_t(gridDim.x) * blockDim.x) {
-        const uint64_t tile = e / (kBM * kBN), loc = e % (kBM * kBN);
+        const uint64_t tile = e / (kBM * BN), loc = e % (kBM * BN);
         uint64_t sum = 0;
-        for (int y = 0; y < splits; ++y) sum += pg[(uint64_t(y) * T + tile) * (kBM * kBN) + loc];
+        for (int y = 0; y < splits; ++y) sum += pg[(uint64_t(y) * T + tile) * (kBM * BN) + loc];
         uint64_t ta, tb;
         tile_coords(tile, tilesA, tilesB, ta, tb);
-        const uint64_t i = loc / kBN, j = loc % kBN;
-        const uint64_t c = pdep64(ta * kBM + i, a.maskA) | pdep64(tb * kBN + j, a.maskB);
+        const uint64_t i = loc / BN, j = loc % BN;
+        const uint64_t c = pdep64(ta * kBM + i, a.maskA) | pdep64(tb * BN + j, a.maskB);
         const uint32_t r = uint32_t(sum % p);
         if (digits_out) {
             // entry c's digit d at byte 256 (c / 64) + 64 d + c % 64
@@ -455,14 +728,32 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* p
             if (x & m & (~m + 1)) r |= bit;
         return r;
     };
-    const uint64_t TM = pdep(127, a.maskA) | pdep(63, a.maskB);
-    for (int q = 0; q < 4; ++q) {
+    // 128 x 128 tiles when both free sides allow them (and a tile's rows
+    // span less than 4 GiB: the square kernel's load offsets are 32-bit)
+    const bool sq = a.fB >= 7 && a.s <= 24;
+    const int bn = sq ? kSqN : kBN;
+    const uint64_t TM = pdep(127, a.maskA) | pdep(uint64_t(bn - 1), a.maskB);
+    for (int q = 0; q < (sq ? 8 : 4); ++q) {
         ex.hiOff[q] = pdep(uint64_t(q) << 11, TM);
         ex.hiI[q] = uint32_t(pext(ex.hiOff[q], a.maskA));
         ex.hiJ[q] = uint32_t(pext(ex.hiOff[q], a.maskB));
+    }
+    for (int q = 0; q < 4; ++q) {
         ex.dI[q] = uint32_t(pext(uint64_t(q), a.maskA));
         ex.dJ[q] = uint32_t(pext(uint64_t(q), a.maskB));
     }
+    const uint64_t T = (uint64_t(1) << (a.fA - 7)) * (uint64_t(1) << (a.fB - (sq ? 7 : 6)));
+    // too few output tiles to fill the GPU: split K over block rows (powers
+    // of two, as many partial tiles per plane as the scratch area holds, at
+    // least one stage each)
+    int splits = 1;
+    const int nk = sq ? 1 << (a.s - 6) : a.s >= 7 ? 1 << (a.s - 7) : 1;
+    const uint64_t cap_tiles = uint64_t(scratch_per_plane) / (4 * kBM * uint64_t(bn));
+    // the 128 x 64 kernel sums at most 2^15 entries (256 stages) per block row
+    if (!sq)
+        while (nk / splits > (1 << 15) / 128) splits *= 2;
+    if (T * uint64_t(splits) > cap_tiles && splits > 1) return hipErrorInvalidValue;
+    while (T * G * splits * 2 <= 1024 && splits * 2 <= nk && T * splits * 2 <= cap_tiles) splits *= 2;
     const uint64_t nA = (uint64_t(1) << (a.fA + a.s)) / 4, nB = (uint64_t(1) << (a.fB + a.s)) / 4;
     auto blocks = [](uint64_t n) { return dim3(uint32_t(std::min<uint64_t>((n + 255) / 256, 1u << 16)), 1, 1); };
     dim3 gA = blocks(nA), gB = blocks(nB);
@@ -487,30 +778,37 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* p
         const double n4 = double((dig & 1u) ? 0 : nA) + double((dig & 2u) ? 0 : nB);
         prof->after_raw(stream, KC_DIGITS, 2.0 * 16.0 * n4 * G, 0.0);
     }
-    const uint64_t T = (uint64_t(1) << (a.fA - 7)) * (uint64_t(1) << (a.fB - 6));
-    // too few output tiles to fill the GPU: split K over block rows (powers
-    // of two, at most 128 partial tiles per plane in the scratch area, at
-    // least one 128-entry stage each)
-    int splits = 1;
-    const int nk = a.s >= 7 ? 1 << (a.s - 7) : 1;
-    const uint64_t cap_tiles = uint64_t(scratch_per_plane) / (4 * kBM * kBN);
-    while (T * G * splits * 2 <= 1024 && splits * 2 <= nk && T * splits * 2 <= cap_tiles) splits *= 2;
     uint32_t* part = reinterpret_cast<uint32_t*>(scratch);
     const int64_t part_stride = scratch_per_plane / 4;
     dim3 grid(uint32_t(std::min<uint64_t>(T, 1024)), uint32_t(splits), G);
     prof->before(stream);
-    hipLaunchKernelGGL(k_mfma, grid, dim3(kThreads), 0, stream, a, ex, splits, part, part_stride);
+    if (sq)
+        hipLaunchKernelGGL(k_mfma_sq, grid, dim3(kThreads), 0, stream, a, ex, splits, part, part_stride);
+    else if (a.s >= 7)
+        hipLaunchKernelGGL(k_mfma<true>, grid, dim3(kThreads), 0, stream, a, ex, splits, part, part_stride);
+    else
+        hipLaunchKernelGGL(k_mfma<false>, grid, dim3(kThreads), 0, stream, a, ex, splits, part, part_stride);
     if (splits > 1) {
-        const uint64_t n = T * (kBM * kBN);
+        const uint64_t n = T * (kBM * uint64_t(bn));
         dim3 gr(uint32_t(std::min<uint64_t>((n + 255) / 256, 4096)), 1, G);
-        hipLaunchKernelGGL(k_mfma_reduce, gr, dim3(256), 0, stream, a, part, part_stride, splits, int(ex.digits_out));
+        if (sq)
+            hipLaunchKernelGGL(k_mfma_reduce<kSqN>, gr, dim3(256), 0, stream, a, part, part_stride, splits,
+                               int(ex.digits_out));
+        else
+            hipLaunchKernelGGL(k_mfma_reduce<kBN>, gr, dim3(256), 0, stream, a, part, part_stride, splits,
+                               int(ex.digits_out));
     }
     prof->after_raw(stream, KC_MFMA, step_bytes, step_macs);
     return hipGetLastError();
 }
 
 bool mfma_eligible(const StepArgs& a) {
-    return a.s >= 6 && a.fA >= 7 && a.fB >= 6;
+    // 128 x 128 tiles: K up to 2^24 (32-bit load offsets within a tile).
+    // 128 x 64 tiles (B's free side of 6 bits): K split into ranges of 2^15
+    // whose partial tiles (2^(fA - 7) per range, 32 KiB each) fit the 4 MiB
+    // scratch of a prime
+    return a.s >= 6 && a.fA >= 7 &&
+           ((a.fB >= 7 && a.s <= 24) || (a.fB == 6 && (a.s <= 15 || (a.fA - 7) + (a.s - 15) <= 7)));
 }
 
 }  // namespace tn

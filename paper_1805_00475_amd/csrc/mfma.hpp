@@ -9,16 +9,18 @@ namespace tn {
 
 struct MfmaExtra {
     double inv_p[kMaxGroup];  // the double nearest 1/p, per prime
-    // output tile positions 2048 q (q < 4) beyond a thread's first: C offset
-    // bits and the A-side and B-side tile-local indices; dI, dJ: the indices
-    // of the word k (< 4) after a position whose two lowest bits are 0
-    uint64_t hiOff[4];
-    uint32_t hiI[4], hiJ[4], dI[4], dJ[4];
+    // output tile positions 2048 q (q < 4 for 128 x 64 tiles, q < 8 for
+    // 128 x 128) beyond a thread's first: C offset bits and the A-side and
+    // B-side tile-local indices; dI, dJ: the indices of the word k (< 4)
+    // after a position whose two lowest bits are 0
+    uint64_t hiOff[8];
+    uint32_t hiI[8], hiJ[8], dI[4], dJ[4];
     uint32_t digits_out;  // 1: write C as digit planes (its consumer is a matrix-core step)
 };
 
 // A step qualifies when K = 2^s is at least 64 and the free sides give at
-// least one 128 x 64 output tile. The caller must also ensure that neither
+// least one 128 x 64 output tile (128 x 128 tiles are used when B's free
+// side has at least 7 bits). The caller must also ensure that neither
 // operand is a shared initial tensor: both are rewritten in place into digit
 // planes.
 bool mfma_eligible(const StepArgs& a);

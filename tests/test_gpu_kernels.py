@@ -84,7 +84,8 @@ def test_kernel_rns(kernel, rA, rB, s):
 
 
 @pytest.mark.parametrize("kind", ["max", "half"])
-@pytest.mark.parametrize("kernel,rA,rB,s", [("mfma", 16, 15, 9), ("mfma", 23, 22, 16), ("stream", 13, 7, 5),
+@pytest.mark.parametrize("kernel,rA,rB,s", [("mfma", 16, 15, 9), ("mfma", 23, 22, 16), ("mfma", 23, 23, 16),
+                                            ("stream", 13, 7, 5),
                                             ("rowdot", 12, 10, 8), ("generic", 9, 7, 3)])
 def test_kernel_extreme_residues(kernel, rA, rB, s, kind):
     _check(rA, rB, s, kernel, P[-1], seed=7, kind=kind, samples=2000)
@@ -108,3 +109,15 @@ def test_mfma_refuses_small_or_u64():
 def test_kernel_full_size_sampled(kernel, rA, rB, s):
     # shapes of the largest steps of the n=200 cubic vertex-cover plans
     _check(rA, rB, s, kernel, P[3], seed=11, samples=400)
+
+
+def test_mfma_exact_range_flush():
+    # K = 2^16 over 64 output tiles of 128 x 128: no K split, so the exact
+    # int32 sums are reduced once in the middle of K (after 2^15 entries)
+    _check(26, 26, 16, "mfma", P[5], seed=13, samples=300)
+
+
+def test_mfma_narrow_tile_wide_k():
+    # 128 x 64 tiles (B's free side of 6 bits) with K = 2^17: the launch
+    # splits K into exact ranges of at most 2^15 entries
+    _check(24, 23, 17, "mfma", P[6], seed=17, samples=300)
