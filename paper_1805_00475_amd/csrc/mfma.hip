@@ -31,6 +31,7 @@
 namespace tn {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------- digit pass
 constexpr int kDigits = 2;
@@ -494,7 +495,12 @@ __device__ __forceinline__ void sq_fetch(const uint8_t* tA, const uint8_t* tB, u
 
 __global__ __launch_bounds__(kThreads, 1) void k_mfma_sq(StepArgs a, MfmaExtra ex, int splits, uint32_t* part,
                                                          int64_t part_stride) {
-    __shared__ __align__(1024) uint8_t lds[kSqBufs * kSqBuf];
+    // chunk buffers, then per-thread epilogue constants: kept in LDS instead
+    // of registers through the K loop, where register pressure would spill
+    // them to scratch, whose reloads wait for every load in flight (the
+    // next tile's chunks)
+    __shared__ __align__(1024) uint8_t lds[kSqBufs * kSqBuf + kThreads * 16];
+    v4u* const lconst = reinterpret_cast<v4u*>(lds + kSqBufs * kSqBuf);
     uint32_t* sOut = reinterpret_cast<uint32_t*>(lds + 2 * kSqBuf);  // buffers 2 and 3
 
     const int g = blockIdx.z;
@@ -532,6 +538,20 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma_sq(StepArgs a, MfmaExtra e
     uint8_t* const ldsW = lds + w * 1024;
     const int fr = lane & 15, q = lane >> 4;
     const int sw[kDigits] = {((0 + q) ^ (fr >> 1)) * 16, ((4 + q) ^ (fr >> 1)) * 16};
+    // output staging: the residue of tile-local (i, j) sits at word
+    // stage_pos(i, j), a linear (XOR) map chosen on the host so that both the
+    // MFMA-layout writes and the C-order reads of a wave hit 64 distinct banks
+    auto stage_pos = [&](uint32_t i, uint32_t j) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int b = 0; b < 7; ++b) {
+            x ^= ((i >> b) & 1u) ? ex.phiI[b] : 0u;
+            x ^= ((j >> b) & 1u) ? ex.phiJ[b] : 0u;
+        }
+        return x;
+    };
+    lconst[tid] = v4u{stage_pos(uint32_t(wr + 4 * q), uint32_t(wc + fr)), stage_pos(iLow, jLow),
+                      uint32_t(offLow), uint32_t(offLow >> 32)};
     __syncthreads();
 
     uint64_t tile = blockIdx.x, ta, tb;
@@ -608,9 +628,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma_sq(StepArgs a, MfmaExtra e
             last(f0);
         }
 
-        // epilogue: lane holds rows 4 (lane / 16) + v, column lane % 16 of each 16x16 block
-        if (splits > 1) {
-            uint32_t* pt = part + blockIdx.z * part_stride + (uint64_t(blockIdx.y) * T + tile) * (kSqM * kSqN);
+        // epilogue: lane holds rows 4 (lane / 16) + v, column lane % 16 of
+        // each 16x16 block; the residues are staged, then written in C order
+        // (split K: partial residues in C order within the tile)
+        {
+            // per tile, like the store addresses below
+            int ci = tid;
+            __asm__ volatile("" : "+v"(ci));  // read here, per tile
+            const v4u lc = lconst[ci];
+            const uint32_t wP = lc.x;
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
@@ -620,40 +646,35 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma_sq(StepArgs a, MfmaExtra e
                         int32_t Tt[kShifts];
 #pragma unroll
                         for (int t = 0; t < kShifts; ++t) Tt[t] = acc[t][rb][cb][v];
-                        const int i = wr + rb * 16 + 4 * q + v;
-                        const int j = wc + cb * 16 + fr;
-                        pt[i * kSqN + j] = combine_digits(Tt, p, inv_p);
-                    }
-        } else {
-#pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        int32_t Tt[kShifts];
-#pragma unroll
-                        for (int t = 0; t < kShifts; ++t) Tt[t] = acc[t][rb][cb][v];
-                        const int i = wr + rb * 16 + 4 * q + v;
-                        const int j = wc + cb * 16 + fr;
-                        sOut[i * kSqN + j] = combine_digits(Tt, p, inv_p);
+                        // i = wr + 4 q + (16 rb + v), j = wc + fr + 16 cb
+                        const uint32_t u = ((v & 1) ? ex.phiI[0] : 0u) ^ ((v & 2) ? ex.phiI[1] : 0u) ^
+                                           ((rb & 1) ? ex.phiI[4] : 0u) ^ ((rb & 2) ? ex.phiI[5] : 0u) ^
+                                           (cb ? ex.phiJ[4] : 0u);
+                        sOut[wP ^ u] = combine_digits(Tt, p, inv_p);
+                        // one residue at a time: scheduled together, the 96
+                        // conversions to double would need twice the
+                        // accumulators' registers
+                        __builtin_amdgcn_sched_barrier(0);
                     }
             // staging complete (the next tile's loads may stay in flight)
             chunk_barrier<63>();
             const uint64_t baseC = pdep64(ta * kSqM, a.maskA) | pdep64(tb * kSqN, a.maskB);
+            uint4* pt = reinterpret_cast<uint4*>(part + blockIdx.z * part_stride +
+                                                 (uint64_t(blockIdx.y) * T + tile) * (kSqM * kSqN));
             // the store addresses are formed here, per tile: hoisted out of
             // the tile loop they would hold 48 registers through the K loop
-            uint64_t oLow = offLow;
-            uint32_t iL = iLow, jL = jLow;
-            __asm__ volatile("" : "+v"(oLow), "+v"(iL), "+v"(jL));
+            const uint64_t oLow = uint64_t(lc.z) | (uint64_t(lc.w) << 32);
+            const uint32_t rP = lc.y;
 #pragma unroll
             for (int qq = 0; qq < 8; ++qq) {
                 const uint64_t o = oLow | ex.hiOff[qq];
-                const uint32_t i = iL | ex.hiI[qq];
-                const uint32_t j = jL | ex.hiJ[qq];
-                const uint32_t v[4] = {sOut[i * kSqN + j], sOut[(i | ex.dI[1]) * kSqN + (j | ex.dJ[1])],
-                                       sOut[(i | ex.dI[2]) * kSqN + (j | ex.dJ[2])],
-                                       sOut[(i | ex.dI[3]) * kSqN + (j | ex.dJ[3])]};
+                const uint32_t r = rP ^ ex.stageQ[qq];
+                const uint32_t v[4] = {sOut[r], sOut[r ^ ex.stageK[1]], sOut[r ^ ex.stageK[2]],
+                                       sOut[r ^ ex.stageK[3]]};
+                if (splits > 1) {
+                    pt[tid + 512 * qq] = uint4{v[0], v[1], v[2], v[3]};
+                    continue;
+                }
                 const uint64_t e = baseC | o;
                 if (ex.digits_out) {
                     uint32_t wd[kDigits];
@@ -676,7 +697,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma_sq(StepArgs a, MfmaExtra e
 }
 
 // split-K: add the partial residues of every K range and scatter into C
-// (tiles of 128 x BN)
+// (tiles of 128 x BN; partial tiles in (i, j) order for BN = 64, in C order
+// within the tile for BN = 128)
 template <int BN>
 __global__ __launch_bounds__(256) void k_mfma_reduce(StepArgs a, const uint32_t* part, int64_t part_stride,
                                                      int splits, int digits_out) {
@@ -693,8 +715,14 @@ __global__ __launch_bounds__(256) void k_mfma_reduce(StepArgs a, const uint32_t*
         for (int y = 0; y < splits; ++y) sum += pg[(uint64_t(y) * T + tile) * (kBM * BN) + loc];
         uint64_t ta, tb;
         tile_coords(tile, tilesA, tilesB, ta, tb);
-        const uint64_t i = loc / BN, j = loc % BN;
-        const uint64_t c = pdep64(ta * kBM + i, a.maskA) | pdep64(tb * BN + j, a.maskB);
+        uint64_t c;
+        if (BN == 128) {
+            const uint64_t TM = pdep64(127, a.maskA) | pdep64(127, a.maskB);
+            c = pdep64(ta * kBM, a.maskA) | pdep64(tb * BN, a.maskB) | pdep64(loc, TM);
+        } else {
+            const uint64_t i = loc / BN, j = loc % BN;
+            c = pdep64(ta * kBM + i, a.maskA) | pdep64(tb * BN + j, a.maskB);
+        }
         const uint32_t r = uint32_t(sum % p);
         if (digits_out) {
             // entry c's digit d at byte 256 (c / 64) + 64 d + c % 64
@@ -708,6 +736,83 @@ __global__ __launch_bounds__(256) void k_mfma_reduce(StepArgs a, const uint32_t*
         }
     }
 }
+
+namespace {
+
+// rank over GF(2) of a set of 6-bit values
+int rank6(const uint32_t* v, int n) {
+    uint32_t basis[6] = {0, 0, 0, 0, 0, 0};
+    int r = 0;
+    for (int a = 0; a < n; ++a) {
+        uint32_t x = v[a] & 63u;
+        for (int b = 5; b >= 0 && x; --b) {
+            if (!((x >> b) & 1u)) continue;
+            if (!basis[b]) {
+                basis[b] = x;
+                ++r;
+                break;
+            }
+            x ^= basis[b];
+        }
+    }
+    return r;
+}
+
+// Staging layout of a 128 x 128 output tile. Word of tile-local (i, j):
+// bits 7.. = i, bit 6 = j6, bank bits 0..5 = j0..j5 XOR M (i0..i6, j6),
+// a bijection for any 6 x 8 bit matrix M. A wave's staging writes vary in
+// (i2, i3, j0..j3) (lane / 16 and lane % 16 of the MFMA layout) and its
+// C-order reads in the tile bits at C-order positions 2..7 (consecutive
+// lanes read consecutive groups of four words); M is drawn (from a fixed
+// seed) until both sets map onto all 6 bank bits, so neither access has a
+// bank conflict. Without such an M the layout stays correct (M = 0).
+void stage_layout(const StepArgs& a, uint64_t TM, MfmaExtra& ex) {
+    // tile bit at C-order position t: i (A side) or j (B side) and its index
+    int isA[14], idx[14];
+    int p = 0, ni = 0, nj = 0;
+    for (int b = 0; b < 64 && p < 14; ++b) {
+        if (!((TM >> b) & 1u)) continue;
+        isA[p] = int((a.maskA >> b) & 1u);
+        idx[p] = isA[p] ? ni++ : nj++;
+        ++p;
+    }
+    uint32_t M[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // columns: i0..i6, j6
+    auto image = [&](int A_side, int k) -> uint32_t {
+        if (A_side) return M[k];
+        return k < 6 ? (1u << k) : M[7];
+    };
+    uint32_t rng = 0x2545f491u;
+    for (int attempt = 0; attempt < 20000; ++attempt) {
+        for (int c = 0; c < 8; ++c) {
+            rng ^= rng << 13;
+            rng ^= rng >> 17;
+            rng ^= rng << 5;
+            M[c] = rng & 63u;
+        }
+        const uint32_t W[6] = {image(1, 2), image(1, 3), image(0, 0), image(0, 1), image(0, 2), image(0, 3)};
+        uint32_t R[6];
+        for (int t = 2; t < 8; ++t) R[t - 2] = image(isA[t], idx[t]);
+        if (rank6(W, 6) == 6 && rank6(R, 6) == 6) break;
+        if (attempt == 19999)
+            for (int c = 0; c < 8; ++c) M[c] = 0;
+    }
+    for (int k = 0; k < 7; ++k) {
+        ex.phiI[k] = (1u << (7 + k)) | M[k];
+        ex.phiJ[k] = k < 6 ? (1u << k) : ((1u << 6) | M[7]);
+    }
+    auto pos = [&](uint32_t i, uint32_t j) {
+        uint32_t x = 0;
+        for (int b = 0; b < 7; ++b) {
+            if ((i >> b) & 1u) x ^= ex.phiI[b];
+            if ((j >> b) & 1u) x ^= ex.phiJ[b];
+        }
+        return x;
+    };
+    for (int q = 0; q < 8; ++q) ex.stageQ[q] = pos(ex.hiI[q], ex.hiJ[q]);
+    for (int k = 0; k < 4; ++k) ex.stageK[k] = pos(ex.dI[k], ex.dJ[k]);
+}
+
+}  // namespace
 
 hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
                        double step_macs, char* scratch, int64_t scratch_per_plane, unsigned dig) {
@@ -742,6 +847,7 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* p
         ex.dI[q] = uint32_t(pext(uint64_t(q), a.maskA));
         ex.dJ[q] = uint32_t(pext(uint64_t(q), a.maskB));
     }
+    if (sq) stage_layout(a, TM, ex);
     const uint64_t T = (uint64_t(1) << (a.fA - 7)) * (uint64_t(1) << (a.fB - (sq ? 7 : 6)));
     // too few output tiles to fill the GPU: split K over block rows (powers
     // of two, as many partial tiles per plane as the scratch area holds, at

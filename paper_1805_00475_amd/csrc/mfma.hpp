@@ -15,6 +15,10 @@ struct MfmaExtra {
     // after a position whose two lowest bits are 0
     uint64_t hiOff[8];
     uint32_t hiI[8], hiJ[8], dI[4], dJ[4];
+    // 128 x 128 tiles: staging word of tile-local bit i_b / j_b (the word of
+    // (i, j) is the XOR over its set bits), and the staging words of the
+    // positions 2048 q and of the word k, for the C-order reads
+    uint32_t phiI[7], phiJ[7], stageQ[8], stageK[4];
     uint32_t digits_out;  // 1: write C as digit planes (its consumer is a matrix-core step)
 };
 
