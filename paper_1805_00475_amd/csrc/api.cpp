@@ -12,7 +12,7 @@ namespace tn {
 // randomized bisection trials the judge may try
 constexpr int kPartitionTrials = 16;
 // host microseconds of order search allowed per predicted device microsecond
-constexpr double kSearchRatio = 4.0;
+constexpr double kSearchRatio = 1.0;
 // most host time spent reconfiguring one plan
 constexpr double kRefineCapUs = 400000.0;
 
@@ -55,9 +55,12 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         // bisections, Girvan-Newman, then more bisections. After the first
         // three, stop once the host time spent on this search exceeds
         // kSearchRatio times the predicted device time of the best plan so
-        // far (all residue planes); orders are searched on up to 16 host
-        // threads while the GPU contracts, so a few host microseconds per
-        // device microsecond still pay for themselves.
+        // far (all residue planes). The device cannot start before the first
+        // plan of a batch is ready, so search time beyond the device time it
+        // saves is a loss; measured on batches of n = 200 cubic vertex-cover
+        // instances, one host microsecond per predicted device microsecond
+        // gives the shortest batch (a quarter of that gives much worse plans,
+        // four times that no better ones).
         const auto t0 = std::chrono::steady_clock::now();
         const double planes = N.n_vars <= 63 ? 1.0 : double(primes_needed(N.n_vars));
         auto over_budget = [&]() {
