@@ -21,64 +21,79 @@ namespace {
 
 struct EdgeList {
     std::vector<std::pair<int32_t, int32_t>> ends;
-    std::vector<std::vector<std::pair<int32_t, int32_t>>> inc;  // vertex -> (neighbour, edge)
+    // live incidences only: vertex -> (neighbour, edge); a removed edge is
+    // erased from both endpoints' lists, so no traversal tests for it
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> inc;
     std::vector<uint8_t> removed;
+    void remove(int32_t e) {
+        removed[size_t(e)] = 1;
+        for (int32_t x : {ends[size_t(e)].first, ends[size_t(e)].second}) {
+            auto& l = inc[size_t(x)];
+            for (size_t k = 0; k < l.size(); ++k)
+                if (l[k].second == e) {
+                    l.erase(l.begin() + std::ptrdiff_t(k));
+                    break;
+                }
+        }
+    }
 };
 
 // Brandes edge betweenness restricted to the vertices of one component.
-void betweenness(const EdgeList& el, const std::vector<int32_t>& comp, std::vector<double>& eb) {
-    const int32_t n = int32_t(el.inc.size());
-    std::vector<int32_t> dist(n, -1);
-    std::vector<double> sigma(n, 0.0), delta(n, 0.0);
-    std::vector<int32_t> order;
-    order.reserve(comp.size());
-    for (int32_t s : comp) {
-        order.clear();
-        for (int32_t v : comp) {
-            dist[v] = -1;
-            sigma[v] = 0.0;
-            delta[v] = 0.0;
-        }
-        dist[s] = 0;
-        sigma[s] = 1.0;
-        order.push_back(s);
-        for (size_t h = 0; h < order.size(); ++h) {
-            int32_t v = order[h];
-            for (const auto& pr : el.inc[v]) {
-                if (el.removed[pr.second]) continue;
-                int32_t w = pr.first;
-                if (dist[w] < 0) {
-                    dist[w] = dist[v] + 1;
-                    order.push_back(w);
-                }
-                if (dist[w] == dist[v] + 1) sigma[w] += sigma[v];
+struct Brandes {
+    std::vector<int32_t> dist, order;
+    std::vector<double> sigma, delta;
+    explicit Brandes(size_t n) : dist(n, -1), sigma(n, 0.0), delta(n, 0.0) { order.reserve(n); }
+    void run(const EdgeList& el, const std::vector<int32_t>& comp, std::vector<double>& eb) {
+        for (int32_t s : comp) {
+            order.clear();
+            for (int32_t v : comp) {
+                dist[size_t(v)] = -1;
+                sigma[size_t(v)] = 0.0;
+                delta[size_t(v)] = 0.0;
             }
-        }
-        for (size_t h = order.size(); h-- > 0;) {
-            int32_t w = order[h];
-            for (const auto& pr : el.inc[w]) {
-                if (el.removed[pr.second]) continue;
-                int32_t v = pr.first;
-                if (dist[v] == dist[w] - 1) {
-                    double c = sigma[v] / sigma[w] * (1.0 + delta[w]);
-                    eb[pr.second] += c;
-                    delta[v] += c;
+            dist[size_t(s)] = 0;
+            sigma[size_t(s)] = 1.0;
+            order.push_back(s);
+            for (size_t h = 0; h < order.size(); ++h) {
+                const int32_t v = order[h];
+                const int32_t dv = dist[size_t(v)] + 1;
+                const double sv = sigma[size_t(v)];
+                for (const auto& pr : el.inc[size_t(v)]) {
+                    const int32_t w = pr.first;
+                    if (dist[size_t(w)] < 0) {
+                        dist[size_t(w)] = dv;
+                        order.push_back(w);
+                    }
+                    if (dist[size_t(w)] == dv) sigma[size_t(w)] += sv;
+                }
+            }
+            for (size_t h = order.size(); h-- > 0;) {
+                const int32_t w = order[h];
+                const int32_t dw = dist[size_t(w)] - 1;
+                const double sw = sigma[size_t(w)], dl = 1.0 + delta[size_t(w)];
+                for (const auto& pr : el.inc[size_t(w)]) {
+                    const int32_t v = pr.first;
+                    if (dist[size_t(v)] == dw) {
+                        const double c = sigma[size_t(v)] / sw * dl;
+                        eb[size_t(pr.second)] += c;
+                        delta[size_t(v)] += c;
+                    }
                 }
             }
         }
     }
-}
+};
 
-std::vector<int32_t> reach(const EdgeList& el, int32_t s) {
+std::vector<int32_t> reach(const EdgeList& el, int32_t s, std::vector<uint8_t>& seen) {
     std::vector<int32_t> out{s};
-    std::vector<uint8_t> seen(el.inc.size(), 0);
-    seen[s] = 1;
+    seen[size_t(s)] = 1;
     for (size_t h = 0; h < out.size(); ++h)
-        for (const auto& pr : el.inc[out[h]])
-            if (!el.removed[pr.second] && !seen[pr.first]) {
-                seen[pr.first] = 1;
+        for (const auto& pr : el.inc[size_t(out[h])])
+            if (!seen[size_t(pr.first)]) {
+                seen[size_t(pr.first)] = 1;
                 out.push_back(pr.first);
             }
+    for (int32_t x : out) seen[size_t(x)] = 0;
     std::sort(out.begin(), out.end());
     return out;
 }
@@ -123,6 +138,8 @@ std::vector<std::pair<int32_t, int32_t>> order_community(const Network& net) {
     }
     std::vector<double> eb(el.ends.size(), 0.0);
     std::vector<uint8_t> dirty(comm_verts.size(), 1);
+    Brandes brandes(size_t(g.n));
+    std::vector<uint8_t> seen(size_t(g.n), 0);
     // betweenness is kept per edge; recomputed for communities marked dirty
     int32_t live_edges = int32_t(el.ends.size());
     while (live_edges > 0) {
@@ -131,7 +148,7 @@ std::vector<std::pair<int32_t, int32_t>> order_community(const Network& net) {
             for (int32_t v : comm_verts[cid])
                 for (const auto& pr : el.inc[v])
                     if (v < pr.first) eb[pr.second] = 0.0;
-            betweenness(el, comm_verts[cid], eb);
+            brandes.run(el, comm_verts[cid], eb);
             dirty[cid] = 0;
         }
         int32_t best = -1;
@@ -139,11 +156,11 @@ std::vector<std::pair<int32_t, int32_t>> order_community(const Network& net) {
             if (el.removed[e]) continue;
             if (best < 0 || eb[e] > eb[best] * (1.0 + 1e-12) + 1e-12) best = e;
         }
-        el.removed[best] = 1;
+        el.remove(best);
         --live_edges;
         int32_t u = el.ends[best].first, v = el.ends[best].second;
         int32_t cid = comm_of[u];
-        std::vector<int32_t> ru = reach(el, u);
+        std::vector<int32_t> ru = reach(el, u, seen);
         if (std::binary_search(ru.begin(), ru.end(), v)) {
             dirty[cid] = 1;
             continue;
