@@ -32,7 +32,10 @@ HBM_PEAK_GBS = 8000.0
 # of known size); used only while the kernel source is the one measured
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mfma_cvc200_batch16_traffic.txt")
 INT8_PEAK_TOPS = 5000.0   # dense int8 MFMA, MI355X
-INT8_OPS_PER_MODMAC = 8   # 4 digit-pair products, multiply + add each
+# int8 products per multiply-add modulo one modulus: 4 digit pairs for the
+# 16-bit primes, 1 for small moduli (centred int8 residues); an int8 op is a
+# multiply or an add, 2 per product
+INT8_PRODUCTS_PER_MODMAC = {"wide": 4, "small": 1}
 
 
 def measured_traffic():
@@ -53,18 +56,18 @@ def measured_traffic():
         return None
 
 
-def roofline_of(name, d):
+def roofline_of(name, d, mode="small"):
     """Achieved vs peak for one kernel class from its hipEvent total.
 
-    Matrix-core GEMM (mfma): algorithmic multiply-adds modulo p, each costing
-    4 int8 digit-pair products (8 int8 ops), against the dense int8 MFMA
-    peak. Every other class: algorithmic bytes (entries of A and B read, C
-    written) against the HBM peak."""
+    Matrix-core GEMM (mfma): algorithmic multiply-adds modulo each modulus,
+    each costing INT8_PRODUCTS_PER_MODMAC[mode] int8 products (2 int8 ops
+    apiece), against the dense int8 MFMA peak. Every other class: algorithmic
+    bytes (entries of A and B read, C written) against the HBM peak."""
     sec = d["ms"] * 1e-3
     per = {"kernel_class": name, "launches": d["launches"],
            "avg_launch_us": round(1e6 * sec / max(1, d["launches"]), 3)}
     if name == "mfma":
-        tops = d["macs"] * INT8_OPS_PER_MODMAC / sec / 1e12 if sec > 0 else 0.0
+        tops = d["macs"] * 2 * INT8_PRODUCTS_PER_MODMAC[mode] / sec / 1e12 if sec > 0 else 0.0
         per.update({"bound": "mfma", "achieved": round(tops, 2), "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                     "frac": round(tops / INT8_PEAK_TOPS, 4), "traffic": measured_traffic(),
                     "algorithmic_modmacs_per_launch": d["macs"] / max(1, d["launches"]),
@@ -95,6 +98,8 @@ def parse():
                          "hardware byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--single", action="store_true", help="count one formula at a time instead of the batch API")
+    ap.add_argument("--wide-rns", action="store_true",
+                    help="residues modulo 16-bit primes even where small int8 moduli suffice")
     return ap.parse_args()
 
 
@@ -189,17 +194,23 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    base_flags = tn.FLAG_WIDE_RNS if args.wide_rns else 0
+    mode = "wide" if args.wide_rns else "small"
+    res_desc = ("residues mod 16-bit primes (the fewest whose product exceeds 2^(n+1))" if args.wide_rns else
+                "centred int8 residues mod pairwise coprime moduli <= 255 (the fewest whose product exceeds "
+                "2^(n+1))")
     if args.workload == "cvc":
         formulas = [I.cvc(args.n, s) for s in range(args.batch)]
-        k_primes = tn.primes_for(args.n)
+        mods = tn.moduli(tn.Network(formulas[0]).order("community"), flags=base_flags)
+        k_primes = len(mods)
         workload = (f"#Cubic-Vertex-Cover, uniform random cubic graphs n={args.n} (configuration model), "
-                    f"batch of {args.batch} seeds, {args.order} order, {k_primes} primes + CRT")
+                    f"batch of {args.batch} seeds, {args.order} order, {k_primes} moduli + CRT; {res_desc}")
     else:
         formulas = [I.batch_instance(i) for i in range(args.batch)]
         k_primes = None
         workload = (f"mixed batch of {args.batch}: even index monotone 1-in-3 n~U[30,120] m=round(0.66n), "
                     f"odd index cubic vertex cover n~U[30,120] (even); {args.order} order; u64 for n<=63 else "
-                    f"residues mod 16-bit primes (the fewest whose product exceeds 2^(n+1))")
+                    f"{res_desc}")
     ws = tn.default_workspace()
     ws.get(64 << 30)
     if args.copy_calibration:
@@ -210,6 +221,7 @@ def main():
         del src, dst
 
     def one_pass(flags=0):
+        flags |= base_flags
         if args.single:
             return [tn.count(f, args.order, seed=i, flags=flags, workspace=ws) for i, f in enumerate(formulas)]
         return tn.count_batch(formulas, args.order, seed=0, flags=flags, workspace=ws, with_stats=False)
@@ -238,7 +250,7 @@ def main():
     prof = tn.profile()
     log("timing pass done")
     dom = max(prof, key=lambda k: prof[k]["ms"])
-    roofline = roofline_of(dom, prof[dom])
+    roofline = roofline_of(dom, prof[dom], mode)
     per_class = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                      "algorithmic_GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None,
                      "avg_launch_us": round(1000.0 * v["ms"] / v["launches"], 3)}
@@ -250,10 +262,11 @@ def main():
         "metric": "exact counts/sec + contraction HBM GB/s; learned vs greedy order wall-time",
         "value": round(value, 4), "unit": "counts/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "residues mod 16-bit primes in u32 words (exact)",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32" if args.wide_rns else "i8",
         "data": "synthetic",
         "config": {"workload": workload, "batch": args.batch, "n": args.n if args.workload == "cvc" else None,
-                   "order": args.order, "primes": k_primes},
+                   "order": args.order, "moduli": k_primes, "residue_mode": mode},
         "roofline": roofline,
         "hbm_roofline_stream": roofline_of("stream", prof["stream"]) if prof["stream"]["launches"] else None,
         "kernel_classes": per_class,

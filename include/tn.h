@@ -106,7 +106,9 @@ typedef enum { TN_ARITH_AUTO = 0, TN_ARITH_U64 = 1, TN_ARITH_RNS = 2 } tn_arith;
 
 typedef struct {
     int32_t arith;            /* tn_arith; AUTO = U64 if n_vars <= 63 else RNS */
-    int32_t n_primes;         /* RNS primes; 0 = the fewest whose product exceeds 2^(n_vars + 1) */
+    int32_t n_primes;         /* RNS: 0 = the fewest small moduli (see tn_moduli) or, if those do
+                                 not hold 2^(n_vars + 1), the fewest primes of tn_primes that do;
+                                 k > 0 = the first k primes of tn_primes */
     void* workspace;          /* device memory owned by the caller */
     size_t workspace_bytes;
     void* stream;             /* hipStream_t; NULL = null stream */
@@ -115,9 +117,10 @@ typedef struct {
 } tn_contract_opts;
 
 #define TN_FLAG_GENERIC_ONLY 1   /* use only the generic kernel (testing) */
-#define TN_FLAG_NO_MFMA 2        /* never use the int8-limb MFMA kernel */
+#define TN_FLAG_NO_MFMA 2        /* never use the int8 matrix-core kernels */
 #define TN_FLAG_TIMING 4         /* record per-kernel-class device times */
 #define TN_FLAG_NO_GRAPH 8       /* batch: launch waves directly, no hipGraph */
+#define TN_FLAG_WIDE_RNS 16      /* RNS with 16-bit primes even where small moduli suffice */
 
 /* ------------------------------------------------------------------ build
  * Formula -> network (Sec. 2.1). Validates every literal and clause kind;
@@ -148,16 +151,16 @@ tn_status tn_plan_verify(const tn_plan* plan);
 
 /* --------------------------------------------------------------- contract
  * Device workspace needed for a plan under opts (arith, n_primes,
- * prime_group; workspace fields ignored). With prime_group = 0 the answer
- * is for one prime resident at a time. */
+ * prime_group, flags; workspace fields ignored). With prime_group = 0 the
+ * answer is for one residue plane resident at a time. */
 tn_status tn_workspace_bytes(const tn_network* net, const tn_plan* plan,
                              const tn_contract_opts* opts, size_t* bytes);
 
-/* Runs the plan on the GPU. RNS: writes the count modulo each of the
- * n_primes primes (see tn_primes) to residues[0..n_primes-1]. U64: writes
- * the exact count to *u64. Either output pointer may be NULL when unused.
- * Returns TN_ETOOBIG before any device work when the workspace cannot hold
- * one prime's arena. */
+/* Runs the plan on the GPU. RNS: writes the count modulo each modulus that
+ * tn_moduli lists for the same plan and opts, in that order, to
+ * residues[0..k-1]. U64: writes the exact count to *u64. Either output
+ * pointer may be NULL when unused. Returns TN_ETOOBIG before any device work
+ * when the workspace cannot hold one residue plane's arena. */
 tn_status tn_contract(const tn_network* net, const tn_plan* plan, const tn_contract_opts* opts,
                       uint32_t* residues, int32_t residues_cap, uint64_t* u64);
 
@@ -179,7 +182,8 @@ tn_status tn_count_batch(const tn_formula* fs, int32_t n, tn_order_kind kind, ui
  * tn_count_batch call of the calling thread made with TN_FLAG_TIMING
  * (hipEvents around every launch, on the caller's stream). bytes and macs
  * are the algorithmic totals of those launches: 2^rA + 2^rB + 2^rC entries
- * of 4 or 8 bytes and 2^(rA + rB - s) multiply-adds per step and prime. */
+ * of 1 (small-modulus residues), 4 or 8 bytes and 2^(rA + rB - s)
+ * multiply-adds per step and residue plane. */
 typedef enum {
     TN_KC_GENERIC = 0, TN_KC_STREAM = 1, TN_KC_ROWDOT = 2, TN_KC_MFMA = 3, TN_KC_BATCH = 4, TN_KC_DOT = 5,
     TN_KC_DIGITS = 6   /* in-place digit pass before TN_KC_MFMA */
@@ -208,7 +212,9 @@ tn_status tn_profile_launches(tn_launch_record* out, int64_t cap, int64_t* n);
  * of c below 2^(rA + rB - 2s) (the shared bonds are the low s bits of both
  * operands, Sec. 2.1 / Eq. 5 form). Entries are uint32 residues modulo
  * ``prime`` (arith TN_ARITH_RNS; a prime in (2^16 - 2^11, 65280), as
- * tn_primes returns) or uint64 wrapping (TN_ARITH_U64). ``kernel`` forces a
+ * tn_primes returns, or a small modulus 2 <= m <= 255, computed on the
+ * device as centred int8 residues; inputs are taken modulo m, outputs are
+ * in [0, m)) or uint64 wrapping (TN_ARITH_U64). ``kernel`` forces a
  * tn_kernel_class (-1 = the library's choice); TN_EUNSUPPORTED if that kernel
  * cannot run this shape. The workspace (device) must hold the three tensors,
  * each rounded up to 256 bytes, plus 4 MiB of scratch; A and B may be
@@ -265,6 +271,15 @@ tn_status tn_primes(int32_t k, uint32_t* out);
  * 2^(n_vars + 1) (every count is at most 2^n_vars). TN_EINVAL if n_vars < 0
  * or more than TN_MAX_PRIMES primes would be needed. */
 tn_status tn_primes_for(int32_t n_vars, int32_t* k);
+/* Residue moduli of a contraction of ``plan`` under ``opts`` (RNS): the
+ * first k small moduli -- pairwise coprime integers of at most 255 taken
+ * greedily from 255 down (255, 254, 253, 251, 247, ...), whose centred
+ * residues are single int8 values -- when their product exceeds
+ * 2^(n_vars + 1) (n_vars up to about 332) and neither opts->n_primes nor
+ * TN_FLAG_WIDE_RNS asks for primes; otherwise the primes of tn_primes the
+ * contraction uses. tn_contract's residues are modulo these, in order.
+ * *k = 0 for 64-bit arithmetic; TN_EBUFSIZE (with *k set) if cap < *k. */
+tn_status tn_moduli(const tn_plan* plan, const tn_contract_opts* opts, uint32_t* out, int32_t cap, int32_t* k);
 /* Chinese remaindering of residues modulo the first k primes of tn_primes
  * into little-endian base-2^32 limbs. */
 tn_status tn_crt(const uint32_t* residues, int32_t k, uint32_t* limbs, size_t cap, size_t* n_limbs);

@@ -36,10 +36,12 @@ struct BItem {
     const void* B;
     void* C;
     uint64_t maskA, maskB;
-    uint64_t c0;       // first output entry of the tile
-    uint32_t p, r2;    // prime and 2^32 mod p (RNS planes)
-    int32_t s, tlog;   // shared bonds; log2 of the tile's outputs
-    int32_t u64, pad;  // 64-bit wrapping plane
+    uint64_t c0;         // first output entry of the tile
+    uint32_t p, r2;      // modulus and 2^32 mod p (RNS planes)
+    uint32_t r16;        // 2^16 mod p (small moduli)
+    float pinv;          // 1 / p (small moduli)
+    int32_t s, tlog;     // shared bonds; log2 of the tile's outputs
+    int32_t el, pad;     // element kind (kernels.hpp)
 };
 
 // Persistent wave kernel: a fixed grid walks the wave's work list; each
@@ -55,12 +57,19 @@ __global__ __launch_bounds__(256) void k_batch(const BItem* items, int64_t n) {
         for (uint64_t t = lane; t < nOut; t += 64) {
             const uint64_t c = it.c0 + t;
             const uint64_t xa = pext64(c, it.maskA) << it.s, xb = pext64(c, it.maskB) << it.s;
-            if (it.u64) {
+            if (it.el == EL_U64) {
                 const uint64_t* A = static_cast<const uint64_t*>(it.A) + xa;
                 const uint64_t* B = static_cast<const uint64_t*>(it.B) + xb;
                 uint64_t acc = 0;
                 for (uint64_t z = 0; z < K; ++z) acc += A[z] * B[z];
                 static_cast<uint64_t*>(it.C)[c] = acc;
+            } else if (it.el == EL_I8) {
+                const int8_t* A = static_cast<const int8_t*>(it.A) + xa;
+                const int8_t* B = static_cast<const int8_t*>(it.B) + xb;
+                const ModSmall ms{int32_t(it.p), it.r2, it.r16, it.pinv};
+                int64_t acc = 0;
+                for (uint64_t z = 0; z < K; ++z) acc += int32_t(A[z]) * int32_t(B[z]);
+                static_cast<int8_t*>(it.C)[c] = int8_t(ms.center64(acc));
             } else {
                 const uint32_t* A = static_cast<const uint32_t*>(it.A) + xa;
                 const uint32_t* B = static_cast<const uint32_t*>(it.B) + xb;
@@ -82,12 +91,17 @@ __global__ __launch_bounds__(256) void k_batch(const BItem* items, int64_t n) {
 
 struct GItem {
     const void* src;
-    int64_t u64;
+    int64_t el;  // element kind
 };
 
+// int8 residues are returned sign-extended (centred)
 __global__ void k_gather(const GItem* g, uint64_t* out, int64_t n) {
     const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j < n) out[j] = g[j].u64 ? *static_cast<const uint64_t*>(g[j].src) : *static_cast<const uint32_t*>(g[j].src);
+    if (j >= n) return;
+    const void* src = g[j].src;
+    out[j] = g[j].el == EL_U64  ? *static_cast<const uint64_t*>(src)
+             : g[j].el == EL_I8 ? uint64_t(int64_t(*static_cast<const int8_t*>(src)))
+                                : *static_cast<const uint32_t*>(src);
 }
 
 struct Inst {
@@ -105,6 +119,7 @@ struct Inst {
     uint64_t u64v = 0;
     bool host_only = false;   // the count is known without device work
     std::vector<uint8_t> dig;  // per step: digit-plane bits of launch_step
+    int el() const { return R.u64 ? EL_U64 : R.i8 ? EL_I8 : EL_U32; }
 };
 
 int worker_count(int n) {
@@ -170,7 +185,7 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
     std::vector<uint8_t> init(size_t(std::max<int64_t>(init_total, 1)), 0);
     int max_level = 0;
     for (int32_t i : sb.ids) {
-        fill_init(ins[i].net, ins[i].plan, ins[i].R.u64, init.data() + ins[i].init_off);
+        fill_init(ins[i].net, ins[i].plan, ins[i].el(), init.data() + ins[i].init_off);
         for (const Step& st : ins[i].plan.steps) max_level = std::max(max_level, st.level);
     }
     std::vector<std::vector<BItem>> wave_items(size_t(max_level) + 1);
@@ -183,8 +198,8 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
         // in the wave kernel)
         std::vector<KernelClass> cls(I.plan.steps.size());
         for (size_t k = 0; k < cls.size(); ++k)
-            cls[k] = small_step(I.plan.steps[k]) ? KC_BATCH : choose_class(I.plan.steps[k], I.R.u64, o->flags);
-        I.dig = digit_plan(I.plan, cls);
+            cls[k] = small_step(I.plan.steps[k]) ? KC_BATCH : choose_class(I.plan.steps[k], I.el(), o->flags);
+        I.dig = digit_plan(I.plan, cls, I.el());
         char* ib = base + I.init_off;
         for (int32_t k = 0; k < int32_t(I.plan.steps.size()); ++k) {
             const Step& st = I.plan.steps[k];
@@ -204,10 +219,12 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
                 it.maskB = cmask & ~st.maskA;
                 it.s = st.s;
                 it.tlog = tlog;
-                it.u64 = I.R.u64;
+                it.el = I.el();
                 if (!I.R.u64) {
                     it.p = I.R.primes[q];
                     it.r2 = uint32_t((uint64_t(1) << 32) % it.p);
+                    it.r16 = uint32_t(65536u % it.p);
+                    it.pinv = 1.0f / float(it.p);
                 }
                 for (uint64_t c0 = 0; c0 < (uint64_t(1) << st.rC); c0 += uint64_t(1) << tlog) {
                     it.c0 = c0;
@@ -217,7 +234,7 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
         }
         const Step& last = I.plan.steps.back();
         for (int q = 0; q < I.P; ++q) {
-            gathers.push_back({base + I.arena_off + q * I.arena_bytes + last.woffC * I.es, I.R.u64 ? 1 : 0});
+            gathers.push_back({base + I.arena_off + q * I.arena_bytes + last.woffC * I.es, int64_t(I.el())});
             gather_of.push_back({i, q});
         }
     }
@@ -258,7 +275,7 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
             if (timing)
                 for (int64_t k = wave_off[L]; k < wave_off[L + 1]; ++k) {
                     const BItem& it = flat[size_t(k)];
-                    const double es = it.u64 ? 8.0 : 4.0;
+                    const double es = double(elem_size(it.el));
                     bytes += es * std::ldexp(1.0, it.tlog) * 1.0;  // outputs written
                     macs += std::ldexp(1.0, it.tlog + it.s);
                 }
@@ -279,7 +296,7 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
             for (int g0 = 0; g0 < I.P && err == hipSuccess; g0 += kMaxGroup) {
                 const int gn = std::min(kMaxGroup, I.P - g0);
                 KernelClass kc = KC_GENERIC;
-                err = launch_step(st, I.R.u64, o->flags, I.R.u64 ? nullptr : I.R.primes.data() + g0, gn,
+                err = launch_step(st, I.el(), o->flags, I.R.u64 ? nullptr : I.R.primes.data() + g0, gn,
                                   base + I.init_off, base + I.arena_off + g0 * I.arena_bytes, I.arena_bytes / I.es,
                                   base + scratch_off, stream, &kc, -1, I.dig[size_t(bk.second)]);
             }
@@ -313,10 +330,15 @@ tn_status run_sub(std::vector<Inst>& ins, const SubBatch& sb, const tn_contract_
     prof.collect();
     for (size_t j = 0; j < out.size(); ++j) {
         Inst& I = ins[gather_of[j].first];
-        if (I.R.u64)
+        const int q = gather_of[j].second;
+        if (I.R.u64) {
             I.u64v = out[j];
-        else
-            I.res[size_t(gather_of[j].second)] = uint32_t(out[j]);
+        } else if (I.R.i8) {
+            const int64_t m = I.R.primes[size_t(q)], c = int64_t(out[j]);
+            I.res[size_t(q)] = uint32_t(c < 0 ? c + m : c);
+        } else {
+            I.res[size_t(q)] = uint32_t(out[j]);
+        }
     }
     return TN_OK;
 }
@@ -400,7 +422,7 @@ extern "C" tn_status tn_count_batch(const tn_formula* fs, int32_t n, tn_order_ki
         I.st = resolve(I.plan, opts, I.R);
         if (I.st != TN_OK) continue;
         I.P = I.R.u64 ? 1 : I.R.k;
-        I.es = I.R.u64 ? 8 : 4;
+        I.es = I.R.es();
         I.res.assign(size_t(I.R.u64 ? 0 : I.R.k), 0);
         if (I.plan.n_init == 0 || I.plan.steps.empty()) {
             // empty network or a single scalar tensor: no device work
@@ -448,7 +470,7 @@ extern "C" tn_status tn_count_batch(const tn_formula* fs, int32_t n, tn_order_ki
             L = {uint32_t(I.u64v), uint32_t(I.u64v >> 32)};
             while (L.size() > 1 && L.back() == 0) L.pop_back();
         } else {
-            crt_limbs(I.res.data(), I.R.k, L);
+            crt_limbs(I.res.data(), I.R.primes.data(), I.R.k, L);
         }
         n_limbs[i] = L.size();
         if (limbs && L.size() <= cap_per)

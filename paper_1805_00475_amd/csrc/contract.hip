@@ -23,37 +23,51 @@
 namespace tn {
 
 // ------------------------------------------------------------------ kernels
+// Every kernel is instantiated per element kind (EL_U32: residues modulo
+// 16-bit primes, folded 64-bit sums; EL_U64: wrapping 64-bit counts; EL_I8:
+// centred int8 residues modulo small moduli, exact integer sums reduced
+// once at the end).
 
-template <bool U64>
+template <int E>
 __device__ __forceinline__ void load_planes(const StepArgs& a, const void*& A, const void*& B, void*& C) {
-    using T = typename std::conditional<U64, uint64_t, uint32_t>::type;
+    using T = typename ElemT<E>::T;
     const int g = blockIdx.z;
     A = static_cast<const T*>(a.A) + g * a.strideA;
     B = static_cast<const T*>(a.B) + g * a.strideB;
     C = static_cast<T*>(a.C) + g * a.strideC;
 }
 
+__device__ __forceinline__ ModSmall mod_small(const StepArgs& a) {
+    const int g = blockIdx.z;
+    return ModSmall{int32_t(a.p[g]), a.r2[g], a.r16[g], a.pinv[g]};
+}
+
 // Any shape: one thread per output entry, bit gathers by loops.
-template <bool U64>
+template <int E>
 __global__ __launch_bounds__(256) void k_generic(StepArgs a) {
-    using T = typename std::conditional<U64, uint64_t, uint32_t>::type;
+    using T = typename ElemT<E>::T;
     const void *pA, *pB;
     void* pC;
-    load_planes<U64>(a, pA, pB, pC);
+    load_planes<E>(a, pA, pB, pC);
     const T* A = static_cast<const T*>(pA);
     const T* B = static_cast<const T*>(pB);
     T* C = static_cast<T*>(pC);
     const ModP m{a.p[blockIdx.z], a.r2[blockIdx.z]};
+    const ModSmall ms = mod_small(a);
     const uint64_t total = uint64_t(1) << a.rC;
     const uint64_t K = uint64_t(1) << a.s;
     for (uint64_t c = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < total;
          c += uint64_t(gridDim.x) * blockDim.x) {
         const T* ra = A + (pext64(c, a.maskA) << a.s);
         const T* rb = B + (pext64(c, a.maskB) << a.s);
-        if constexpr (U64) {
+        if constexpr (E == EL_U64) {
             uint64_t acc = 0;
             for (uint64_t z = 0; z < K; ++z) acc += ra[z] * rb[z];
             C[c] = acc;
+        } else if constexpr (E == EL_I8) {
+            int64_t acc = 0;
+            for (uint64_t z = 0; z < K; ++z) acc += int32_t(ra[z]) * int32_t(rb[z]);
+            C[c] = T(ms.center64(acc));
         } else {
             uint64_t acc = 0;
             uint32_t n3 = 0;
@@ -74,17 +88,18 @@ __global__ __launch_bounds__(256) void k_generic(StepArgs a) {
 // coalesced) and NB consecutive xB of the block's xB chunk; the B slab is
 // uniform across the block. Output positions split into a uniform part
 // (block's xA base and xB chunk) and per-lane / per-j parts deposited once.
-template <bool U64, int LOGK, int NB>
+template <int E, int LOGK, int NB>
 __global__ __launch_bounds__(256) void k_stream(StepArgs a) {
-    using T = typename std::conditional<U64, uint64_t, uint32_t>::type;
+    using T = typename ElemT<E>::T;
     constexpr int K = 1 << LOGK;
     const void *pA, *pB;
     void* pC;
-    load_planes<U64>(a, pA, pB, pC);
+    load_planes<E>(a, pA, pB, pC);
     const T* A = static_cast<const T*>(pA);
     const T* B = static_cast<const T*>(pB);
     T* C = static_cast<T*>(pC);
     const ModP m{a.p[blockIdx.z], a.r2[blockIdx.z]};
+    const ModSmall ms = mod_small(a);
     const uint64_t lane = threadIdx.x;
     const uint64_t laneC = pdep64(lane, a.maskA);
     uint64_t offB[NB];
@@ -105,11 +120,17 @@ __global__ __launch_bounds__(256) void k_stream(StepArgs a) {
             for (int z = 0; z < K; ++z) av[z] = ra[z];
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
-                if constexpr (U64) {
+                if constexpr (E == EL_U64) {
                     uint64_t acc = 0;
 #pragma unroll
                     for (int z = 0; z < K; ++z) acc += av[z] * rb[j * K + z];
                     C[cA | offB[j]] = acc;
+                } else if constexpr (E == EL_I8) {
+                    // at most 32 products of magnitude 2^14: int32 is exact
+                    int32_t acc = 0;
+#pragma unroll
+                    for (int z = 0; z < K; ++z) acc += int32_t(av[z]) * int32_t(rb[j * K + z]);
+                    C[cA | offB[j]] = T(ms.center32(acc));
                 } else {
                     uint64_t acc = 0;
 #pragma unroll
@@ -126,16 +147,17 @@ __global__ __launch_bounds__(256) void k_stream(StepArgs a) {
 
 // Wide shared dimension, few outputs: one wavefront per output entry, lanes
 // stride over z (coalesced rows of A and B), then a wavefront reduction.
-template <bool U64>
+template <int E>
 __global__ __launch_bounds__(256) void k_rowdot(StepArgs a) {
-    using T = typename std::conditional<U64, uint64_t, uint32_t>::type;
+    using T = typename ElemT<E>::T;
     const void *pA, *pB;
     void* pC;
-    load_planes<U64>(a, pA, pB, pC);
+    load_planes<E>(a, pA, pB, pC);
     const T* A = static_cast<const T*>(pA);
     const T* B = static_cast<const T*>(pB);
     T* C = static_cast<T*>(pC);
     const ModP m{a.p[blockIdx.z], a.r2[blockIdx.z]};
+    const ModSmall ms = mod_small(a);
     const int lane = threadIdx.x & 63;
     const uint64_t wave = threadIdx.x >> 6;
     const uint64_t total = uint64_t(1) << a.rC;
@@ -143,11 +165,16 @@ __global__ __launch_bounds__(256) void k_rowdot(StepArgs a) {
     for (uint64_t c = uint64_t(blockIdx.x) * 4 + wave; c < total; c += uint64_t(gridDim.x) * 4) {
         const T* ra = A + (pext64(c, a.maskA) << a.s);
         const T* rb = B + (pext64(c, a.maskB) << a.s);
-        if constexpr (U64) {
+        if constexpr (E == EL_U64) {
             uint64_t acc = 0;
             for (uint64_t z = lane; z < K; z += 64) acc += ra[z] * rb[z];
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
             if (lane == 0) C[c] = acc;
+        } else if constexpr (E == EL_I8) {
+            int64_t acc = 0;
+            for (uint64_t z = lane; z < K; z += 64) acc += int32_t(ra[z]) * int32_t(rb[z]);
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+            if (lane == 0) C[c] = T(ms.center64(acc));
         } else {
             uint64_t acc = 0;
             uint32_t n3 = 0;
@@ -173,15 +200,16 @@ __global__ __launch_bounds__(256) void k_rowdot(StepArgs a) {
 // the grid. Block b sums its K slice for every output and writes one partial
 // per output; a second kernel adds the partials of each output.
 
-template <bool U64>
+template <int E>
 __global__ __launch_bounds__(256) void k_dot_partial(StepArgs a, uint64_t* scratch, int nblk) {
-    using T = typename std::conditional<U64, uint64_t, uint32_t>::type;
+    using T = typename ElemT<E>::T;
     const void *pA, *pB;
     void* pC;
-    load_planes<U64>(a, pA, pB, pC);
+    load_planes<E>(a, pA, pB, pC);
     const T* A = static_cast<const T*>(pA);
     const T* B = static_cast<const T*>(pB);
     const ModP m{a.p[blockIdx.z], a.r2[blockIdx.z]};
+    const ModSmall ms = mod_small(a);
     __shared__ uint64_t red[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t K = uint64_t(1) << a.s;
@@ -193,11 +221,16 @@ __global__ __launch_bounds__(256) void k_dot_partial(StepArgs a, uint64_t* scrat
         const T* ra = A + (pext64(c, a.maskA) << a.s) + z0;
         const T* rb = B + (pext64(c, a.maskB) << a.s) + z0;
         uint64_t v;
-        if constexpr (U64) {
+        if constexpr (E == EL_U64) {
             uint64_t acc = 0;
             for (uint64_t z = threadIdx.x; z < slice; z += blockDim.x) acc += ra[z] * rb[z];
             for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
             v = acc;
+        } else if constexpr (E == EL_I8) {
+            int64_t acc = 0;
+            for (uint64_t z = threadIdx.x; z < slice; z += blockDim.x) acc += int32_t(ra[z]) * int32_t(rb[z]);
+            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+            v = uint64_t(acc);
         } else {
             uint64_t acc = 0;
             uint32_t n3 = 0;
@@ -218,8 +251,12 @@ __global__ __launch_bounds__(256) void k_dot_partial(StepArgs a, uint64_t* scrat
         if (lane == 0) red[wave] = v;
         __syncthreads();
         if (threadIdx.x == 0) {
-            if constexpr (U64) {
+            if constexpr (E == EL_U64) {
                 out[c] = red[0] + red[1] + red[2] + red[3];
+            } else if constexpr (E == EL_I8) {
+                // a centred residue, kept as a signed 64-bit value
+                const int64_t t = int64_t(red[0]) + int64_t(red[1]) + int64_t(red[2]) + int64_t(red[3]);
+                out[c] = uint64_t(int64_t(ms.center64(t)));
             } else {
                 out[c] = (red[0] + red[1] + red[2] + red[3]) % m.p;
             }
@@ -228,19 +265,22 @@ __global__ __launch_bounds__(256) void k_dot_partial(StepArgs a, uint64_t* scrat
     }
 }
 
-template <bool U64>
+template <int E>
 __global__ __launch_bounds__(64) void k_dot_final(StepArgs a, const uint64_t* scratch, int nblk) {
-    using T = typename std::conditional<U64, uint64_t, uint32_t>::type;
+    using T = typename ElemT<E>::T;
     T* C = static_cast<T*>(a.C) + blockIdx.z * a.strideC;
     const uint32_t p = a.p[blockIdx.z];
+    const ModSmall ms = mod_small(a);
     const uint64_t c = blockIdx.x;
     const uint64_t* part = scratch + uint64_t(blockIdx.z) * nblk * 64;
     uint64_t acc = 0;
     for (int b = threadIdx.x; b < nblk; b += 64) acc += part[uint64_t(b) * 64 + c];  // < 1024 * 2^31
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (threadIdx.x == 0) {
-        if constexpr (U64)
+        if constexpr (E == EL_U64)
             C[c] = acc;
+        else if constexpr (E == EL_I8)
+            C[c] = T(ms.center64(int64_t(acc)));  // a sum of signed partials, in two's complement
         else
             C[c] = T(acc % p);
     }
@@ -248,33 +288,44 @@ __global__ __launch_bounds__(64) void k_dot_final(StepArgs a, const uint64_t* sc
 
 // ----------------------------------------------------------------- launches
 
-template <bool U64, int LOGK>
+template <int E, int LOGK>
 hipError_t launch_stream_nb(int nb, dim3 grid, hipStream_t st, const StepArgs& a) {
     switch (nb) {
-        case 1: hipLaunchKernelGGL((k_stream<U64, LOGK, 1>), grid, dim3(256), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((k_stream<U64, LOGK, 2>), grid, dim3(256), 0, st, a); break;
-        case 4: hipLaunchKernelGGL((k_stream<U64, LOGK, 4>), grid, dim3(256), 0, st, a); break;
-        case 8: hipLaunchKernelGGL((k_stream<U64, LOGK, 8>), grid, dim3(256), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_stream<U64, LOGK, 16>), grid, dim3(256), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_stream<E, LOGK, 1>), grid, dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_stream<E, LOGK, 2>), grid, dim3(256), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_stream<E, LOGK, 4>), grid, dim3(256), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_stream<E, LOGK, 8>), grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_stream<E, LOGK, 16>), grid, dim3(256), 0, st, a); break;
     }
     return hipGetLastError();
 }
 
-template <bool U64>
+template <int E>
 hipError_t launch_stream(int logk, int nb, dim3 grid, hipStream_t st, const StepArgs& a) {
     switch (logk) {
-        case 0: return launch_stream_nb<U64, 0>(nb, grid, st, a);
-        case 1: return launch_stream_nb<U64, 1>(nb, grid, st, a);
-        case 2: return launch_stream_nb<U64, 2>(nb, grid, st, a);
-        case 3: return launch_stream_nb<U64, 3>(nb, grid, st, a);
-        case 4: return launch_stream_nb<U64, 4>(nb, grid, st, a);
-        default: return launch_stream_nb<U64, 5>(nb, grid, st, a);
+        case 0: return launch_stream_nb<E, 0>(nb, grid, st, a);
+        case 1: return launch_stream_nb<E, 1>(nb, grid, st, a);
+        case 2: return launch_stream_nb<E, 2>(nb, grid, st, a);
+        case 3: return launch_stream_nb<E, 3>(nb, grid, st, a);
+        case 4: return launch_stream_nb<E, 4>(nb, grid, st, a);
+        default: return launch_stream_nb<E, 5>(nb, grid, st, a);
     }
 }
 
+// launch of a kernel template instantiated per element kind
+#define TN_LAUNCH_EL(el, kern, grid, block, stream, ...)                                     \
+    do {                                                                                     \
+        if ((el) == EL_U64)                                                                  \
+            hipLaunchKernelGGL(kern<EL_U64>, grid, block, 0, stream, __VA_ARGS__);           \
+        else if ((el) == EL_I8)                                                              \
+            hipLaunchKernelGGL(kern<EL_I8>, grid, block, 0, stream, __VA_ARGS__);            \
+        else                                                                                 \
+            hipLaunchKernelGGL(kern<EL_U32>, grid, block, 0, stream, __VA_ARGS__);           \
+    } while (0)
+
 inline uint32_t cap32(uint64_t x, uint32_t hi) { return uint32_t(std::min<uint64_t>(std::max<uint64_t>(x, 1), hi)); }
 
-KernelClass choose_class(const Step& st, bool u64, int flags) {
+KernelClass choose_class(const Step& st, int el, int flags) {
     StepArgs a{};
     a.s = st.s;
     a.rC = st.rC;
@@ -282,14 +333,16 @@ KernelClass choose_class(const Step& st, bool u64, int flags) {
     a.fB = std::min(st.rA, st.rB) - st.s;
     if (flags & TN_FLAG_GENERIC_ONLY) return KC_GENERIC;
     if (a.rC <= 6 && a.s >= 10) return KC_DOT;
-    if (!u64 && !st.initA && !st.initB && mfma_eligible(a) && !(flags & TN_FLAG_NO_MFMA)) return KC_MFMA;
+    if (el != EL_U64 && !st.initA && !st.initB && mfma_eligible(a, el) && !(flags & TN_FLAG_NO_MFMA)) return KC_MFMA;
     if (a.s <= 5 && a.fA >= 8) return KC_STREAM;
     if (a.s >= 6) return KC_ROWDOT;
     return KC_GENERIC;
 }
 
-std::vector<uint8_t> digit_plan(const Plan& plan, const std::vector<KernelClass>& cls) {
+std::vector<uint8_t> digit_plan(const Plan& plan, const std::vector<KernelClass>& cls, int el) {
     const size_t n = plan.steps.size();
+    std::vector<uint8_t> out_dig(n, 0), dig(n, 0);
+    if (el != EL_U32) return dig;  // int8 residues are the matrix-core operands as they are
     const size_t ids = size_t(plan.n_init) + n;
     std::vector<int32_t> prod(ids, -1), cons(ids, -1);
     for (size_t k = 0; k < n; ++k) {
@@ -298,7 +351,6 @@ std::vector<uint8_t> digit_plan(const Plan& plan, const std::vector<KernelClass>
         cons[size_t(st.a)] = int32_t(k);
         cons[size_t(st.b)] = int32_t(k);
     }
-    std::vector<uint8_t> out_dig(n, 0), dig(n, 0);
     for (size_t k = 0; k < n; ++k) {
         const int32_t c = cons[size_t(plan.steps[k].out)];
         out_dig[k] = cls[k] == KC_MFMA && c >= 0 && cls[size_t(c)] == KC_MFMA;
@@ -312,11 +364,23 @@ std::vector<uint8_t> digit_plan(const Plan& plan, const std::vector<KernelClass>
     return dig;
 }
 
-// Choose and launch the kernel of one step for a group of G primes.
-hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* primes, int G, char* init_base,
+int elem_size(int el) { return el == EL_U64 ? 8 : el == EL_I8 ? 1 : 4; }
+
+void fill_moduli(StepArgs& a, const uint32_t* primes, int G) {
+    for (int g = 0; g < G; ++g) {
+        const uint32_t p = primes ? primes[g] : 0;
+        a.p[g] = p;
+        a.r2[g] = p ? uint32_t((uint64_t(1) << 32) % p) : 0;
+        a.r16[g] = p ? uint32_t(65536u % p) : 0;
+        a.pinv[g] = p ? 1.0f / float(p) : 0.0f;
+    }
+}
+
+// Choose and launch the kernel of one step for a group of G residue planes.
+hipError_t launch_step(const Step& st0, int el, int flags, const uint32_t* primes, int G, char* init_base,
                        char* arena_base, int64_t arena_elems, char* scratch, hipStream_t stream, KernelClass* kc,
                        int force, unsigned dig) {
-    const size_t es = u64 ? 8 : 4;
+    const size_t es = size_t(elem_size(el));
     Profiler& prof = profiler();
     // algorithmic work of the step: entries read and written, multiply-adds
     const double step_bytes =
@@ -342,10 +406,7 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
     a.s = st.s;
     a.fA = st.rA - st.s;
     a.fB = st.rB - st.s;
-    for (int g = 0; g < G; ++g) {
-        a.p[g] = primes ? primes[g] : 0;
-        a.r2[g] = primes ? uint32_t((uint64_t(1) << 32) % primes[g]) : 0;
-    }
+    fill_moduli(a, primes, G);
     // the larger free side plays A
     if (a.fB > a.fA) {
         std::swap(a.A, a.B);
@@ -355,7 +416,7 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
         dig = (dig & 4u) | ((dig & 1u) << 1) | ((dig >> 1) & 1u);
     }
     const uint64_t total = uint64_t(1) << a.rC;
-    const bool can_mfma = !u64 && !st.initA && !st.initB && mfma_eligible(a);
+    const bool can_mfma = el != EL_U64 && !st.initA && !st.initB && mfma_eligible(a, el);
     const bool can_stream = a.s <= 5 && a.fA >= 8;
     if (force == KC_MFMA && !can_mfma) return hipErrorInvalidValue;
     if (force == KC_STREAM && !can_stream) return hipErrorInvalidValue;
@@ -363,7 +424,7 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
     const bool can_dot = a.rC <= 6 && a.s >= 10;
     if (force == KC_DOT && !can_dot) return hipErrorInvalidValue;
     // one decision rule for launches and for the digit-plane hand-over
-    const int pick = force >= 0 ? force : int(choose_class(st0, u64, flags));
+    const int pick = force >= 0 ? force : int(choose_class(st0, el, flags));
     if (pick != KC_MFMA && (dig & 3u)) return hipErrorInvalidValue;  // operands must be plain residues
     if (pick == KC_DOT) {
         const int nblk = int(std::min<uint64_t>(kDotBlocks, (uint64_t(1) << a.s) >> 8));
@@ -371,19 +432,14 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
         dim3 g1(nblk, 1, G), g2(uint32_t(total), 1, G);
         uint64_t* scr = reinterpret_cast<uint64_t*>(scratch);
         prof.before(stream);
-        if (u64)
-            hipLaunchKernelGGL(k_dot_partial<true>, g1, dim3(256), 0, stream, a, scr, nblk);
-        else
-            hipLaunchKernelGGL(k_dot_partial<false>, g1, dim3(256), 0, stream, a, scr, nblk);
+        TN_LAUNCH_EL(el, k_dot_partial, g1, dim3(256), stream, a, scr, nblk);
         prof.after_raw(stream, KC_DOT, step_bytes, step_macs);
-        if (u64)
-            hipLaunchKernelGGL(k_dot_final<true>, g2, dim3(64), 0, stream, a, scr, nblk);
-        else
-            hipLaunchKernelGGL(k_dot_final<false>, g2, dim3(64), 0, stream, a, scr, nblk);
+        TN_LAUNCH_EL(el, k_dot_final, g2, dim3(64), stream, a, scr, nblk);
         return hipGetLastError();
     }
     if (pick == KC_MFMA) {
         *kc = KC_MFMA;
+        if (el == EL_I8) return launch_mfma8(a, G, stream, &prof, step_bytes, step_macs, scratch, kScratchPerPrime);
         return launch_mfma(a, G, stream, &prof, step_bytes, step_macs, scratch, kScratchPerPrime, dig);
     }
     if (pick == KC_STREAM) {
@@ -393,8 +449,9 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
         dim3 grid(cap32(n_iter, 1u << 20), cap32(n_chunk, 65535), G);
         *kc = KC_STREAM;
         prof.before(stream);
-        hipError_t e = u64 ? launch_stream<true>(a.s, 1 << nb, grid, stream, a)
-                           : launch_stream<false>(a.s, 1 << nb, grid, stream, a);
+        hipError_t e = el == EL_U64  ? launch_stream<EL_U64>(a.s, 1 << nb, grid, stream, a)
+                       : el == EL_I8 ? launch_stream<EL_I8>(a.s, 1 << nb, grid, stream, a)
+                                     : launch_stream<EL_U32>(a.s, 1 << nb, grid, stream, a);
         prof.after_raw(stream, KC_STREAM, step_bytes, step_macs);
         return e;
     }
@@ -402,20 +459,14 @@ hipError_t launch_step(const Step& st0, bool u64, int flags, const uint32_t* pri
         dim3 grid(cap32((total + 3) / 4, 1u << 20), 1, G);
         *kc = KC_ROWDOT;
         prof.before(stream);
-        if (u64)
-            hipLaunchKernelGGL(k_rowdot<true>, grid, dim3(256), 0, stream, a);
-        else
-            hipLaunchKernelGGL(k_rowdot<false>, grid, dim3(256), 0, stream, a);
+        TN_LAUNCH_EL(el, k_rowdot, grid, dim3(256), stream, a);
         prof.after_raw(stream, KC_ROWDOT, step_bytes, step_macs);
         return hipGetLastError();
     }
     dim3 grid(cap32((total + 255) / 256, 1u << 20), 1, G);
     *kc = KC_GENERIC;
     prof.before(stream);
-    if (u64)
-        hipLaunchKernelGGL(k_generic<true>, grid, dim3(256), 0, stream, a);
-    else
-        hipLaunchKernelGGL(k_generic<false>, grid, dim3(256), 0, stream, a);
+    TN_LAUNCH_EL(el, k_generic, grid, dim3(256), stream, a);
     prof.after_raw(stream, KC_GENERIC, step_bytes, step_macs);
     return hipGetLastError();
 }
@@ -438,7 +489,7 @@ uint64_t init_entry(const InitTensor& t, const std::vector<int32_t>& pos, uint64
     return ntrue == 1 ? 1 : 0;
 }
 
-void fill_init(const Network& net, const Plan& plan, bool u64, uint8_t* host) {
+void fill_init(const Network& net, const Plan& plan, int el, uint8_t* host) {
     for (int32_t i = 0; i < plan.n_init; ++i) {
         const InitTensor& t = net.t[i];
         const auto& L = plan.layout[i];
@@ -447,9 +498,11 @@ void fill_init(const Network& net, const Plan& plan, bool u64, uint8_t* host) {
             pos[k] = int32_t(std::find(L.begin(), L.end(), t.bonds[k]) - L.begin());
         const uint64_t n = uint64_t(1) << t.bonds.size();
         for (uint64_t x = 0; x < n; ++x) {
-            const uint64_t v = init_entry(t, pos, x);
-            if (u64)
+            const uint64_t v = init_entry(t, pos, x);  // 0, 1 or 2: the same residue in every plane
+            if (el == EL_U64)
                 reinterpret_cast<uint64_t*>(host)[plan.init_off[i] + x] = v;
+            else if (el == EL_I8)
+                reinterpret_cast<int8_t*>(host)[plan.init_off[i] + x] = int8_t(v);
             else
                 reinterpret_cast<uint32_t*>(host)[plan.init_off[i] + x] = uint32_t(v);
         }
@@ -467,6 +520,17 @@ tn_status resolve(const Plan& plan, const tn_contract_opts* o, Resolved& r) {
     }
     if (arith != TN_ARITH_RNS) return TN_EINVAL;
     r.u64 = false;
+    // small moduli (int8 residues) unless a prime count is given, 16-bit
+    // primes are asked for, or the count needs more bits than they hold
+    const int32_t ks = small_moduli_needed(plan.n_vars);
+    if (!(o && o->n_primes > 0) && !(o && (o->flags & TN_FLAG_WIDE_RNS)) && ks > 0) {
+        r.i8 = true;
+        r.k = ks;
+        const auto& M = small_moduli();
+        r.primes.assign(M.begin(), M.begin() + ks);
+        return TN_OK;
+    }
+    r.i8 = false;
     r.k = (o && o->n_primes > 0) ? o->n_primes : primes_needed(plan.n_vars);
     if (r.k > TN_MAX_PRIMES) return TN_EINVAL;
     const auto& P = prime_table(r.k);
@@ -479,7 +543,8 @@ int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 // Runs the plan; fills residues (RNS) or *u64v (U64).
 tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts* o, const Resolved& R,
                    std::vector<uint32_t>& residues, uint64_t* u64v) {
-    const size_t es = R.u64 ? 8 : 4;
+    const int el = R.u64 ? EL_U64 : R.i8 ? EL_I8 : EL_U32;
+    const size_t es = size_t(R.es());
     residues.assign(R.u64 ? 0 : R.k, 0);
     // networks that need no device work
     if (plan.n_init == 0) {
@@ -511,7 +576,7 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
     char* scratch = arena_base + int64_t(G) * arena_bytes;
     // initial tensors in plan layout, identical for every prime (0/1/2 entries)
     std::vector<uint8_t> host(size_t(plan.init_elems) * es, 0);
-    fill_init(net, plan, R.u64, host.data());
+    fill_init(net, plan, el, host.data());
     Profiler& prof = profiler();
     hipError_t err = hipMemcpyAsync(init_base, host.data(), host.size(), hipMemcpyHostToDevice, stream);
     // on any failure, drain the stream before the host staging buffer goes away
@@ -523,14 +588,14 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
     if (err != hipSuccess) return fail();
     const Step& last = plan.steps.back();
     std::vector<KernelClass> cls(plan.steps.size());
-    for (size_t k = 0; k < cls.size(); ++k) cls[k] = choose_class(plan.steps[k], R.u64, o->flags);
-    const std::vector<uint8_t> dig = digit_plan(plan, cls);
+    for (size_t k = 0; k < cls.size(); ++k) cls[k] = choose_class(plan.steps[k], el, o->flags);
+    const std::vector<uint8_t> dig = digit_plan(plan, cls, el);
     std::vector<uint64_t> out(size_t(R.k), 0);
     for (int g0 = 0; g0 < R.k; g0 += G) {
         const int gn = std::min(G, R.k - g0);
         for (size_t k = 0; k < plan.steps.size(); ++k) {
             KernelClass kc = KC_GENERIC;
-            err = launch_step(plan.steps[k], R.u64, o->flags, R.u64 ? nullptr : R.primes.data() + g0, gn, init_base,
+            err = launch_step(plan.steps[k], el, o->flags, R.u64 ? nullptr : R.primes.data() + g0, gn, init_base,
                               arena_base, arena_elems, scratch, stream, &kc, -1, dig[k]);
             if (err != hipSuccess) return fail();
         }
@@ -545,6 +610,12 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
     prof.collect();
     if (R.u64) {
         *u64v = out[0];
+    } else if (R.i8) {
+        // a centred int8 residue in the low byte
+        for (int i = 0; i < R.k; ++i) {
+            const int32_t m = int32_t(R.primes[size_t(i)]), c = int32_t(int8_t(out[i] & 0xffu));
+            residues[i] = uint32_t(c < 0 ? c + m : c);
+        }
     } else {
         for (int i = 0; i < R.k; ++i) residues[i] = uint32_t(out[i] & 0xffffffffu);
     }
@@ -563,10 +634,22 @@ tn_status tn_workspace_bytes(const tn_network* net, const tn_plan* plan, const t
     Resolved R;
     tn_status st = resolve(plan->plan, opts, R);
     if (st != TN_OK) return st;
-    const int64_t es = R.u64 ? 8 : 4;
+    const int64_t es = R.es();
     int G = (opts && opts->prime_group > 0) ? std::min<int>(opts->prime_group, std::min(R.k, kMaxGroup)) : 1;
     *bytes = size_t(align256(plan->plan.init_elems * es) +
                     int64_t(G) * (align256(plan->plan.arena_elems * es) + kScratchPerPrime));
+    return TN_OK;
+}
+
+tn_status tn_moduli(const tn_plan* plan, const tn_contract_opts* opts, uint32_t* out, int32_t cap, int32_t* k) {
+    if (!plan || !k) return TN_EINVAL;
+    Resolved R;
+    tn_status st = resolve(plan->plan, opts, R);
+    if (st != TN_OK) return st;
+    *k = R.u64 ? 0 : R.k;
+    if (R.u64) return TN_OK;
+    if (!out || cap < R.k) return TN_EBUFSIZE;
+    std::copy(R.primes.begin(), R.primes.end(), out);
     return TN_OK;
 }
 
@@ -612,7 +695,7 @@ tn_status tn_count(const tn_network* net, const tn_plan* plan, const tn_contract
             L = {uint32_t(v), uint32_t(v >> 32)};
             while (L.size() > 1 && L.back() == 0) L.pop_back();
         } else {
-            crt_limbs(res.data(), R.k, L);
+            crt_limbs(res.data(), R.primes.data(), R.k, L);
         }
     } catch (const std::bad_alloc&) {
         return TN_ENOMEM;
@@ -635,11 +718,16 @@ extern "C" tn_status tn_step(const void* A, int32_t rA, const void* B, int32_t r
     const uint64_t cmask = (uint64_t(1) << rC) - 1;
     if ((maskA & ~cmask) || __builtin_popcountll(maskA) != rA - s) return TN_EINVAL;
     const bool u64 = arith == TN_ARITH_U64;
-    // the residue kernels need 2^16 - 2^11 < p < 65280 (any odd prime there)
-    if (!u64 && (arith != TN_ARITH_RNS || prime <= 65536u - 2048u || prime >= kPrimeBound || prime % 2 == 0))
+    // residues: modulo an odd prime in (2^16 - 2^11, 65280), or modulo a
+    // small modulus 2 <= m <= 255 (held as centred int8 on the device)
+    const bool small = !u64 && prime >= 2 && prime <= kSmallModulusMax;
+    if (!u64 && !small &&
+        (arith != TN_ARITH_RNS || prime <= 65536u - 2048u || prime >= kPrimeBound || prime % 2 == 0))
         return TN_EINVAL;
+    if (small && arith != TN_ARITH_RNS) return TN_EINVAL;
     if (kernel < -1 || kernel > KC_DOT || kernel == KC_BATCH) return TN_EINVAL;
-    const int64_t es = u64 ? 8 : 4;
+    const int el = u64 ? EL_U64 : small ? EL_I8 : EL_U32;
+    const int64_t es = elem_size(el);
     const int64_t nA = align256((int64_t(1) << rA) * es), nB = align256((int64_t(1) << rB) * es),
                   nC = align256((int64_t(1) << rC) * es);
     if (nA + nB + nC + kScratchPerPrime > int64_t(workspace_bytes)) return TN_ETOOBIG;
@@ -655,25 +743,55 @@ extern "C" tn_status tn_step(const void* A, int32_t rA, const void* B, int32_t r
     st.offA = 0;
     st.offB = nA / es;
     st.offC = (nA + nB) / es;
-    if (hipMemcpyAsync(base, A, size_t((int64_t(1) << rA) * es), hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(base + nA, B, size_t((int64_t(1) << rB) * es), hipMemcpyHostToDevice, stream) != hipSuccess) {
+    // small moduli: host residues in [0, m) as u32 <-> centred int8
+    std::vector<int8_t> a8, b8, c8;
+    const void* srcA = A;
+    const void* srcB = B;
+    if (small) {
+        const int32_t m = int32_t(prime);
+        auto centre = [m](const uint32_t* x, int64_t n, std::vector<int8_t>& out) {
+            out.resize(size_t(n));
+            for (int64_t i = 0; i < n; ++i) {
+                const int32_t r = int32_t(x[i] % uint32_t(m));
+                out[size_t(i)] = int8_t(r > m / 2 ? r - m : r);
+            }
+        };
+        centre(static_cast<const uint32_t*>(A), int64_t(1) << rA, a8);
+        centre(static_cast<const uint32_t*>(B), int64_t(1) << rB, b8);
+        c8.resize(size_t(int64_t(1) << rC));
+        srcA = a8.data();
+        srcB = b8.data();
+    }
+    if (hipMemcpyAsync(base, srcA, size_t((int64_t(1) << rA) * es), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(base + nA, srcB, size_t((int64_t(1) << rB) * es), hipMemcpyHostToDevice, stream) !=
+            hipSuccess) {
         (void)hipStreamSynchronize(stream);
         return TN_EHIP;
     }
     KernelClass kc = KC_GENERIC;
-    hipError_t e = launch_step(st, u64, 0, u64 ? nullptr : &prime, 1, base, base, 0, base + nA + nB + nC, stream, &kc,
+    hipError_t e = launch_step(st, el, 0, u64 ? nullptr : &prime, 1, base, base, 0, base + nA + nB + nC, stream, &kc,
                                kernel);
     if (e == hipErrorInvalidValue) {
         (void)hipStreamSynchronize(stream);
         return TN_EUNSUPPORTED;
     }
+    void* dstC = small ? static_cast<void*>(c8.data()) : C;
     if (e != hipSuccess ||
-        hipMemcpyAsync(C, base + nA + nB, size_t((int64_t(1) << rC) * es), hipMemcpyDeviceToHost, stream) !=
+        hipMemcpyAsync(dstC, base + nA + nB, size_t((int64_t(1) << rC) * es), hipMemcpyDeviceToHost, stream) !=
             hipSuccess) {
         (void)hipStreamSynchronize(stream);
         return TN_EHIP;
     }
-    return hipStreamSynchronize(stream) == hipSuccess ? TN_OK : TN_EHIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return TN_EHIP;
+    if (small) {
+        const int32_t m = int32_t(prime);
+        uint32_t* out = static_cast<uint32_t*>(C);
+        for (int64_t i = 0; i < (int64_t(1) << rC); ++i) {
+            const int32_t c = c8[size_t(i)];
+            out[i] = uint32_t(c < 0 ? c + m : c);
+        }
+    }
+    return TN_OK;
 }
 
 namespace tn {

@@ -9,7 +9,15 @@
 // what the matrix-core kernel multiplies, and being above 2^16 - 2^11 they
 // allow the kernels' folding reduction (2^16 = 2^16 - p mod p, below 2^11).
 // primes_needed(n) is the fewest leading primes whose product exceeds 2^n.
+//
+// Counts up to about 2^333 use small moduli instead: pairwise coprime
+// integers of at most 255 (255, 254, 253, 251, 247, ..., taken greedily
+// from the top), whose centred residues (|r| <= 127) are single int8
+// values. A modular multiply-add is then one int8 product rather than four
+// digit products, at the price of about twice as many residue planes.
+// Chinese remaindering needs the moduli pairwise coprime only, not prime.
 #include <cmath>
+#include <numeric>
 #include <mutex>
 
 #include "internal.hpp"
@@ -45,26 +53,53 @@ int32_t primes_needed(int32_t n_vars) {
     return bits > double(n_vars) + 1.0 ? k : TN_MAX_PRIMES + 1;
 }
 
-static uint32_t powmod(uint64_t b, uint64_t e, uint32_t p) {
-    uint64_t r = 1;
-    b %= p;
-    while (e) {
-        if (e & 1) r = r * b % p;
-        b = b * b % p;
-        e >>= 1;
+const std::vector<uint32_t>& small_moduli() {
+    static const std::vector<uint32_t> table = [] {
+        std::vector<uint32_t> t;
+        for (uint32_t m = kSmallModulusMax; m >= 2; --m) {
+            bool coprime = true;
+            for (uint32_t c : t) coprime = coprime && std::gcd(m, c) == 1u;
+            if (coprime) t.push_back(m);
+        }
+        return t;
+    }();
+    return table;
+}
+
+int32_t small_moduli_needed(int32_t n_vars) {
+    const std::vector<uint32_t>& M = small_moduli();
+    double bits = 0.0;
+    int32_t k = 0;
+    while (k < int32_t(M.size()) && bits <= double(n_vars) + 1.0) bits += std::log2(double(M[size_t(k++)]));
+    return bits > double(n_vars) + 1.0 ? k : 0;
+}
+
+// inverse of a modulo m (gcd(a, m) = 1), by the extended Euclidean algorithm
+static uint64_t inverse_mod(uint64_t a, uint64_t m) {
+    int64_t r0 = int64_t(m), r1 = int64_t(a % m), t0 = 0, t1 = 1;
+    while (r1 != 0) {
+        const int64_t q = r0 / r1;
+        const int64_t r2 = r0 - q * r1, t2 = t0 - q * t1;
+        r0 = r1;
+        r1 = r2;
+        t0 = t1;
+        t1 = t2;
     }
-    return uint32_t(r);
+    return uint64_t(t0 < 0 ? t0 + int64_t(m) : t0);
 }
 
 void crt_limbs(const uint32_t* residues, int32_t k, std::vector<uint32_t>& limbs) {
-    const std::vector<uint32_t>& P = prime_table(k);
-    // Garner: x = v0 + v1 p0 + v2 p0 p1 + ... with 0 <= vi < pi
+    crt_limbs(residues, prime_table(k).data(), k, limbs);
+}
+
+void crt_limbs(const uint32_t* residues, const uint32_t* P, int32_t k, std::vector<uint32_t>& limbs) {
+    // Garner: x = v0 + v1 m0 + v2 m0 m1 + ... with 0 <= vi < mi
     std::vector<uint32_t> v(k);
     for (int32_t i = 0; i < k; ++i) {
         uint64_t pi = P[i];
         uint64_t x = residues[i] % pi;
         for (int32_t j = 0; j < i; ++j) {
-            uint64_t inv = powmod(P[j] % pi, pi - 2, uint32_t(pi));
+            uint64_t inv = inverse_mod(P[j] % pi, pi);
             x = (x + pi - v[j] % pi) % pi * inv % pi;
         }
         v[i] = uint32_t(x);

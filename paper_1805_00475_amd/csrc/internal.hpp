@@ -104,8 +104,10 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
 // contract.hip
 struct Resolved {
     bool u64 = false;
-    int32_t k = 0;  // primes
-    std::vector<uint32_t> primes;
+    bool i8 = false;  // small moduli, residues stored as centred int8
+    int32_t k = 0;    // residue planes
+    std::vector<uint32_t> primes;  // their moduli
+    int32_t es() const { return u64 ? 8 : i8 ? 1 : 4; }
 };
 tn_status resolve(const Plan& plan, const tn_contract_opts* o, Resolved& r);
 tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts* o, const Resolved& R,
@@ -116,7 +118,12 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
 constexpr uint32_t kPrimeBound = 65280;
 const std::vector<uint32_t>& prime_table(int32_t k);
 int32_t primes_needed(int32_t n_vars);  // > TN_MAX_PRIMES when n_vars is too large
-void crt_limbs(const uint32_t* residues, int32_t k, std::vector<uint32_t>& limbs);
+void crt_limbs(const uint32_t* residues, int32_t k, std::vector<uint32_t>& limbs);  // first k primes
+void crt_limbs(const uint32_t* residues, const uint32_t* moduli, int32_t k, std::vector<uint32_t>& limbs);
+// small moduli: pairwise coprime, at most kSmallModulusMax, descending
+constexpr uint32_t kSmallModulusMax = 255;
+const std::vector<uint32_t>& small_moduli();
+int32_t small_moduli_needed(int32_t n_vars);  // 0 when they do not suffice
 
 }  // namespace tn
 

@@ -9,17 +9,37 @@
 
 namespace tn {
 
-constexpr int kMaxGroup = 16;  // primes per launch (gridDim.z)
+constexpr int kMaxGroup = 16;  // residue planes per launch (gridDim.z)
+
+// Element kinds of a contraction: residues modulo 16-bit primes (u32),
+// 64-bit wrapping counts, or centred residues modulo small moduli (int8).
+enum ElemKind : int { EL_U32 = 0, EL_U64 = 1, EL_I8 = 2 };
+template <int E>
+struct ElemT;
+template <>
+struct ElemT<EL_U32> {
+    using T = uint32_t;
+};
+template <>
+struct ElemT<EL_U64> {
+    using T = uint64_t;
+};
+template <>
+struct ElemT<EL_I8> {
+    using T = int8_t;
+};
 
 struct StepArgs {
     const void* A;
     const void* B;
     void* C;
-    int64_t strideA, strideB, strideC;  // elements between prime planes (0 = shared)
+    int64_t strideA, strideB, strideC;  // elements between residue planes (0 = shared)
     uint64_t maskA, maskB;              // C bits taken from A / from B
     int32_t rC, s, fA, fB;              // output rank, shared bonds, free bits of A and B
-    uint32_t p[kMaxGroup];              // primes of this launch (RNS)
-    uint32_t r2[kMaxGroup];             // 2^32 mod p (small for p close to 2^31)
+    uint32_t p[kMaxGroup];              // moduli of this launch (RNS)
+    uint32_t r2[kMaxGroup];             // 2^32 mod p
+    uint32_t r16[kMaxGroup];            // 2^16 mod p (small moduli)
+    float pinv[kMaxGroup];              // 1 / p (small moduli)
 };
 
 // Residues modulo primes p in (2^16 - 2^11, 2^16), r = 2^32 mod p < 2^16.
@@ -41,6 +61,36 @@ struct ModP {
         y = (y >> 16) * r16 + (y & 0xffffu);
         y = (y >> 16) * r16 + (y & 0xffffu);
         return y >= p ? y - p : y;
+    }
+};
+
+// Centred residue of a signed sum modulo a small modulus m <= 255, in
+// (-m/2, m/2] (so |r| <= 127, an int8). x = h 2^16 + l with 0 <= l < 2^16 is
+// congruent to h r16 + l (r16 = 2^16 mod m < 256); from |x| < 2^31 one fold
+// gives |y| < 2^24, exact in single precision, where y / m floors to a
+// quotient off by at most one (the product's relative error is below
+// 2^-23 and |y / m| < 2^17), so y - q m lies in [-m, 2m): one conditional
+// add or subtract gives [0, m), one more the centred range. Wider sums
+// first fold at 2^32 (r32 = 2^32 mod m) down to 31 bits.
+struct ModSmall {
+    int32_t m;
+    uint32_t r32, r16;
+    float inv;
+    __device__ __forceinline__ int32_t center32(int32_t x) const {
+        const int32_t y = (x >> 16) * int32_t(r16) + (x & 0xffff);
+        const int32_t q = int32_t(floorf(float(y) * inv));
+        int32_t r = y - q * m;
+        r += r < 0 ? m : 0;
+        r -= r >= m ? m : 0;
+        r -= r > (m >> 1) ? m : 0;
+        return r;
+    }
+    __device__ __forceinline__ int32_t center64(int64_t x) const {
+        // |x| < 2^63: two folds at 2^32 bring it below 2^40.1, then 2^31
+        x = (x >> 32) * int64_t(r32) + int64_t(x & 0xffffffffll);
+        x = (x >> 32) * int64_t(r32) + int64_t(x & 0xffffffffll);
+        const int32_t y = int32_t((x >> 16) * int64_t(r16)) + int32_t(x & 0xffff);
+        return center32(y);
     }
 };
 

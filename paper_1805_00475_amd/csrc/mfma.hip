@@ -26,6 +26,7 @@
 
 #include "kernels.hpp"
 #include "mfma.hpp"
+#include "mfma_common.hpp"
 #include "profile.hpp"
 
 namespace tn {
@@ -125,36 +126,6 @@ __device__ __forceinline__ uint32_t combine_digits(const int32_t (&T)[kShifts], 
 }
 
 
-// Tile traversal. Work-groups are dealt to the 8 XCDs round-robin, so tile
-// t runs on XCD t % 8. Each XCD owns a band of A tiles (or of B tiles when
-// there are fewer than 8 A tiles) and walks it in groups of up to 8 tiles of
-// that side: the group stays in the XCD's L2 while the other operand's tiles
-// stream past it once per group.
-__device__ __forceinline__ void tile_coords(uint64_t tile, uint64_t tilesA, uint64_t tilesB, uint64_t& ta,
-                                            uint64_t& tb) {
-    if (tilesA < 8 && tilesB < 8) {
-        ta = tile % tilesA;
-        tb = tile / tilesA;
-        return;
-    }
-    const uint64_t x = tile & 7, j = tile >> 3;
-    if (tilesA >= 8) {
-        const uint64_t per = tilesA >> 3;
-        const uint64_t gm = per < 8 ? per : 8;
-        const uint64_t span = gm * tilesB;
-        const uint64_t group = j / span, r = j % span;
-        ta = x * per + group * gm + r % gm;
-        tb = r / gm;
-    } else {
-        const uint64_t per = tilesB >> 3;
-        const uint64_t gn = per < 8 ? per : 8;
-        const uint64_t span = gn * tilesA;
-        const uint64_t group = j / span, r = j % span;
-        tb = x * per + group * gn + r % gn;
-        ta = r / gn;
-    }
-}
-
 // Every 2^15 entries of K the exact sums are reduced: T0 takes the residue
 // of X (below p < 2^16) and T1, T2 restart from zero, so the next range adds
 // at most 2^29 to T0 and the bounds above hold again.
@@ -173,27 +144,6 @@ __device__ __forceinline__ void flush(v4i (&acc)[kShifts][RB][CB], uint32_t p, d
 #pragma unroll
                 for (int t = 1; t < kShifts; ++t) acc[t][rb][cb][v] = 0;
             }
-}
-
-typedef __attribute__((address_space(3))) void* lds_ptr_t;
-
-// s_waitcnt immediate: vector memory count <= vm (0..63), LDS count 0
-constexpr int wait_vm_lgkm0(int vm) { return (vm & 15) | ((vm >> 4) << 14) | (7 << 4); }
-
-// Chunk barrier: the waiting wave's loads into LDS, except the newest VM of
-// them, have landed and its LDS reads have returned; then all waves meet.
-// After it, every wave's data of the awaited chunk is in LDS and no wave
-// still reads a buffer that is about to be refilled. The empty asm
-// statements keep the compiler from moving memory accesses across it; the
-// fence of __syncthreads is not used because it would also wait for the
-// loads still in flight.
-template <int VM>
-__device__ __forceinline__ void chunk_barrier() {
-    __asm__ volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(VM));
-    __asm__ volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    __asm__ volatile("" ::: "memory");
 }
 
 // One stage of a tile into LDS buffer `dst` (wave's 1 KiB slice): A rows
@@ -907,6 +857,8 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* p
     prof->after_raw(stream, KC_MFMA, step_bytes, step_macs);
     return hipGetLastError();
 }
+
+bool mfma_eligible(const StepArgs& a, int el) { return el == EL_I8 ? mfma8_eligible(a) : mfma_eligible(a); }
 
 bool mfma_eligible(const StepArgs& a) {
     // 128 x 128 tiles: K up to 2^24 (32-bit load offsets within a tile).

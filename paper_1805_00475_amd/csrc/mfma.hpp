@@ -28,6 +28,9 @@ struct MfmaExtra {
 // operand is a shared initial tensor: both are rewritten in place into digit
 // planes.
 bool mfma_eligible(const StepArgs& a);
+// the same question for an element kind (EL_U32: the digit kernels above;
+// EL_I8: the int8 kernel of mfma8.hip)
+bool mfma_eligible(const StepArgs& a, int el);
 struct Profiler;
 // Digit pass on both operands, then the GEMM; each launch is bracketed by
 // the profiler (no-op unless timing is on) with its algorithmic work.
@@ -36,5 +39,10 @@ struct Profiler;
 // = write C as digit planes
 hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
                        double step_macs, char* scratch, int64_t scratch_per_plane, unsigned dig = 0);
+// Matrix-core step on centred int8 residues modulo small moduli (mfma8.hip):
+// one int8 product per modular multiply-add, no digit pass.
+hipError_t launch_mfma8(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
+                        double step_macs, char* scratch, int64_t scratch_per_plane);
+bool mfma8_eligible(const StepArgs& a);
 
 }  // namespace tn

@@ -1,0 +1,377 @@
+// Dense contraction steps on the matrix cores for residues modulo small
+// moduli (m <= 255), stored as centred int8 values (|r| <= 127).
+//
+// A step C = A B^T (rows of A and B contiguous along the shared bonds, Sec.
+// 2.1 / Eq. 5 in the plan's layout) is an int8 matrix product: every
+// product of two residues is at most 127^2 < 2^14 in magnitude, so
+// v_mfma_i32_16x16x64_i8 sums 2^16 of them exactly in int32 (< 2^30); wider
+// K is reduced to a centred residue every 2^16 entries. The epilogue reduces
+// each sum modulo m (ModSmall) and stores the int8 residue, which the next
+// step reads as it is: no digit pass and one product per multiply-add.
+//
+// Work-group tile WM (xA) x WN (xB) with waves of 16 RA x 16 CB outputs:
+// 8 waves (two per SIMD) on 256 x 256 tiles when both free sides have 8
+// bits, else 256 x 128 or 128 x 128; 4 waves on 256 x 64 or 128 x 64 tiles
+// when B's free side has 6 bits (those steps stream A at the memory rate). K goes in stages of one 64-entry
+// chunk: 64-byte LDS rows, filled straight from global memory
+// (global_load_lds_dwordx4, 16 rows per wave instruction) through four
+// buffers; stage k+4 is requested while stage k is multiplied, and at a
+// tile's last stage (every fragment in registers) the next tile's first
+// four stages. One barrier per stage; after it the wave reads the next
+// stage's fragments while the current stage's MFMAs run.
+//
+// LDS rows: 4 slots of 16 bytes, slot c of row r stored at slot
+// c ^ ((r / 4) % 4). A fragment read has a quarter-wave on 16 consecutive
+// rows at one logical slot; the four rows of each 256-byte bank line land on
+// four distinct slots, so all 64 banks are hit once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "mfma.hpp"
+#include "mfma_common.hpp"
+#include "profile.hpp"
+
+namespace tn {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int k8Row = 64;                  // LDS row bytes: one 64-entry chunk
+constexpr int k8Bufs = 4;
+constexpr int k8Flush = (1 << 16) / 64;    // chunks per exact int32 range
+constexpr int k8MaxRowBytesLog = 25;       // 127 rows of a stage within 32-bit load offsets
+
+// Output addressing of the epilogue, by the host: C offset bits of the
+// tile-local A indices 16 rb (rb < 8) and v (v < 4) and of the B indices
+// 16 cb (cb < 4).
+struct Mfma8Extra {
+    uint64_t dA[8], dV[4], dB[4];
+};
+
+constexpr int lg2(int x) { return x <= 1 ? 0 : 1 + lg2(x / 2); }
+
+// Tile shape: WM x WN outputs, NW waves, each on 16 RA x 16 CB outputs.
+template <int WM_, int WN_, int NW_, int RA_, int CB_>
+struct Cfg {
+    static constexpr int WM = WM_, WN = WN_, NW = NW_, RA = RA_, CB = CB_;
+    static constexpr int THREADS = 64 * NW;
+    static constexpr int ROWS = WM + WN;
+    static constexpr int BUF = ROWS * k8Row;      // one stage
+    static constexpr int GROUP = 16 * NW;         // stage rows per load instruction of all waves
+    static constexpr int LOADS = ROWS / GROUP;    // load instructions per wave and stage
+    static constexpr int WAVES_A = WM / (16 * RA);
+    static constexpr int LGM = lg2(WM), LGN = lg2(WN);
+    static_assert(WM % GROUP == 0 && WN % GROUP == 0, "a load instruction covers A rows or B rows only");
+    static_assert(WAVES_A * (WN / (16 * CB)) == NW, "waves cover the tile");
+};
+using Cfg256x256 = Cfg<256, 256, 8, 8, 4>;
+using Cfg256x128 = Cfg<256, 128, 8, 8, 2>;
+using Cfg128x128 = Cfg<128, 128, 8, 4, 2>;
+using Cfg256x64 = Cfg<256, 64, 4, 4, 4>;
+using Cfg128x64 = Cfg<128, 64, 4, 2, 4>;
+
+// One step on int8 residues: tiles of WM x WN outputs dealt round-robin to
+// the work-groups, K split over blockIdx.y into `splits` ranges (partial
+// residues to `part` when splits > 1), residue planes over blockIdx.z.
+// NK: 1 or 2 stages per tile and block row, or 4 for any power of two >= 4.
+template <class G, int NK>
+__global__ __launch_bounds__(G::THREADS, 1) void k_mfma8(StepArgs a, Mfma8Extra ex, int splits, int8_t* part,
+                                                         int64_t part_stride) {
+    constexpr int RA = G::RA, CB = G::CB;
+    __shared__ __align__(1024) uint8_t lds[k8Bufs * G::BUF + G::THREADS * 8];
+    uint64_t* const lconst = reinterpret_cast<uint64_t*>(lds + k8Bufs * G::BUF);
+
+    const int g = blockIdx.z;
+    const int8_t* A = static_cast<const int8_t*>(a.A) + g * a.strideA;
+    const int8_t* B = static_cast<const int8_t*>(a.B) + g * a.strideB;
+    int8_t* C = static_cast<int8_t*>(a.C) + g * a.strideC;
+    const ModSmall ms{int32_t(a.p[g]), a.r2[g], a.r16[g], a.pinv[g]};
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = (w % G::WAVES_A) * 16 * RA, wc = (w / G::WAVES_A) * 16 * CB;
+    const uint64_t rowBytes = uint64_t(1) << a.s;
+    const int nk = NK >= 4 ? (1 << (a.s - 6)) / splits : NK;  // stages per tile and block row
+    const int kc0 = int(blockIdx.y) * nk;
+    const int lgA = a.fA - G::LGM, lgB = a.fB - G::LGN;
+    const uint32_t T = 1u << (lgA + lgB);
+    if (blockIdx.x >= T) return;
+
+    const int fr = lane & 15, q = lane >> 4;
+    // lane part of the output offset (A index wr + 4 q, B index wc + fr),
+    // kept in LDS: the epilogue reads it once per tile, and in registers
+    // through the K loop it would only add pressure
+    lconst[tid] = pdep64(uint64_t(wr + 4 * q), a.maskA) | pdep64(uint64_t(wc + fr), a.maskB);
+    // loads: lane l of wave w, instruction i fills physical slot l % 4 of
+    // stage row GROUP i + 16 w + l / 4, i.e. logical slot (l % 4) ^ (l / 16):
+    // bytes 16 ((l % 4) ^ (l / 16)).. of that row's chunk
+    const uint32_t voff = uint32_t(16 * w + (lane >> 2)) * uint32_t(rowBytes) + 16u * uint32_t((lane & 3) ^ (lane >> 4));
+    // fragment reads: row wr + fr (A) or WM + wc + fr (B) of a stage, at
+    // logical slot q
+    const int sw = 16 * (q ^ (fr >> 2));
+    const uint32_t rdA = uint32_t((wr + fr) * k8Row + sw), rdB = uint32_t((G::WM + wc + fr) * k8Row + sw);
+    __syncthreads();
+
+    // The per-lane offsets pass through empty asm statements where they are
+    // used, so that addresses are formed there from uniform bases (kept in
+    // scalar registers) instead of being kept per lane across the loop.
+    auto fetch = [&](const int8_t* tA, const int8_t* tB, int chunk, int buf) {
+        uint32_t vo = voff;
+        __asm__ volatile("" : "+v"(vo));
+        const uint64_t co = uint64_t(chunk) * 64;
+#pragma unroll
+        for (int i = 0; i < G::LOADS; ++i) {
+            const int r0 = G::GROUP * i;  // first stage row of instruction i (all A or all B)
+            const int8_t* base = (r0 < G::WM ? tA + uint64_t(r0) * rowBytes : tB + uint64_t(r0 - G::WM) * rowBytes) + co;
+            __builtin_amdgcn_global_load_lds(base + vo, (lds_ptr_t)(lds + buf * G::BUF + w * 1024 + i * (G::NW * 1024)),
+                                             16, 0, 0);
+        }
+    };
+    v4i fa[RA], b0[CB], b1[CB];
+    auto read_stage_b = [&](int buf, v4i(&b)[CB]) {
+        uint32_t o = rdB;
+        __asm__ volatile("" : "+v"(o));
+        const uint8_t* p = lds + o + buf * G::BUF;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) b[cb] = *reinterpret_cast<const v4i*>(p + cb * 16 * k8Row);
+    };
+    auto a_row = [&](int buf) {
+        uint32_t o = rdA;
+        __asm__ volatile("" : "+v"(o));
+        return lds + o + buf * G::BUF;
+    };
+
+    uint32_t tile = blockIdx.x, ta, tb;
+    tile_coords_lg(tile, lgA, lgB, ta, tb);
+    const int8_t* tA = A + uint64_t(ta) * G::WM * rowBytes;
+    const int8_t* tB = B + uint64_t(tb) * G::WN * rowBytes;
+#pragma unroll
+    for (int c = 0; c < (NK < k8Bufs ? NK : k8Bufs); ++c) fetch(tA, tB, kc0 + c, c);
+
+    for (;;) {
+        v4i acc[RA][CB];
+#pragma unroll
+        for (int i = 0; i < RA; ++i)
+#pragma unroll
+            for (int j = 0; j < CB; ++j) acc[i][j] = v4i{0, 0, 0, 0};
+        // every load and store of the wave has completed (loads and stores
+        // share one counter); stage 0 is visible to all waves. A fragments:
+        // one set, each refilled with the next stage's as soon as its last
+        // product of the stage is issued; B fragments: two sets
+        chunk_barrier<0>();
+        {
+            const uint8_t* pa = a_row(0);
+#pragma unroll
+            for (int rb = 0; rb < RA; ++rb) fa[rb] = *reinterpret_cast<const v4i*>(pa + rb * 16 * k8Row);
+        }
+        read_stage_b(0, b0);
+
+        const uint32_t next = tile + gridDim.x;
+        const bool more = next < T;
+        uint32_t nta = 0, ntb = 0;
+        if (more) tile_coords_lg(next, lgA, lgB, nta, ntb);
+        const int8_t* nA = A + uint64_t(nta) * G::WM * rowBytes;
+        const int8_t* nB = B + uint64_t(ntb) * G::WN * rowBytes;
+        // Stage kc from fa and bc. Other than the tile's last stage (LAST),
+        // a step first waits until stage kc + 1 has landed with at most VM
+        // loads (stages kc + 2, kc + 3) still in flight, so that no wave reads
+        // stage kc any more; with FETCH its buffer then takes stage kc + 4;
+        // stage kc + 1 is read into fa and bn.
+        auto step = [&](int kc, v4i(&bc)[CB], v4i(&bn)[CB], auto vm, auto fetch_next, auto last) {
+            constexpr int VM = decltype(vm)::value;
+            constexpr bool FETCH = decltype(fetch_next)::value, LAST = decltype(last)::value;
+            const uint8_t* pa = nullptr;
+            if constexpr (!LAST) {
+                chunk_barrier<VM>();
+                if constexpr (FETCH) fetch(tA, tB, kc0 + kc + 4, kc & 3);
+                // (the compiler would otherwise wait at the MFMAs for the
+                // fragment reads below, to order them after the loads above)
+                __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(63));
+                read_stage_b((kc + 1) & 3, bn);
+                pa = a_row((kc + 1) & 3);
+            } else {
+                // every fragment of the tile is in registers, so the four
+                // buffers take the next tile's first stages
+                chunk_barrier<63>();
+                if (more)
+#pragma unroll
+                    for (int c = 0; c < (NK < k8Bufs ? NK : k8Bufs); ++c) fetch(nA, nB, kc0 + c, c);
+            }
+#pragma unroll
+            for (int rb = 0; rb < RA; ++rb) {
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[rb], bc[cb], acc[rb][cb], 0, 0, 0);
+                if constexpr (!LAST) fa[rb] = *reinterpret_cast<const v4i*>(pa + rb * 16 * k8Row);
+            }
+        };
+        using yes = std::true_type;
+        using no = std::false_type;
+        using vm2 = std::integral_constant<int, 2 * G::LOADS>;
+        using vm1 = std::integral_constant<int, G::LOADS>;
+        using vm0 = std::integral_constant<int, 0>;
+        // Main loop: every step waits for the same count and fetches. The
+        // sums stay exact in int32 for k8Flush stages; after each full range
+        // they are reduced to centred residues (the last range ends in the
+        // epilogue).
+        int kc = 0;
+        while (NK >= 4 && kc + 4 < nk) {
+            const int end = std::min(nk - 4, kc + k8Flush);
+            for (; kc < end; kc += 2) {
+                step(kc, b0, b1, vm2(), yes(), no());
+                step(kc + 1, b1, b0, vm2(), yes(), no());
+            }
+            if (kc < nk - 4) {
+#pragma unroll
+                for (int i = 0; i < RA; ++i)
+#pragma unroll
+                    for (int j = 0; j < CB; ++j)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[i][j][v] = ms.center32(acc[i][j][v]);
+            }
+        }
+        // the last stages
+        if constexpr (NK >= 4) {
+            step(nk - 4, b0, b1, vm2(), no(), no());
+            step(nk - 3, b1, b0, vm1(), no(), no());
+            step(nk - 2, b0, b1, vm0(), no(), no());
+            step(nk - 1, b1, b0, vm0(), no(), yes());
+        } else if constexpr (NK == 2) {
+            step(0, b0, b1, vm0(), no(), no());
+            step(1, b1, b0, vm0(), no(), yes());
+        } else {
+            step(0, b0, b1, vm0(), no(), yes());
+        }
+
+        // epilogue: lane holds A index wr + 16 rb + 4 q + v, B index
+        // wc + 16 cb + fr of each 16x16 block
+        if (splits > 1) {
+            // partial residues of this K range, tile-local order (i, j)
+            int8_t* pt = part + blockIdx.z * part_stride + (uint64_t(blockIdx.y) * T + tile) * (G::WM * G::WN);
+            uint32_t lo = uint32_t((wr + 4 * q) * G::WN + wc + fr);
+            __asm__ volatile("" : "+v"(lo));
+#pragma unroll
+            for (int rb = 0; rb < RA; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        pt[lo + uint32_t((16 * rb + v) * G::WN + 16 * cb)] = int8_t(ms.center32(acc[rb][cb][v]));
+        } else {
+            int ci = tid;
+            __asm__ volatile("" : "+v"(ci));  // read here, per tile
+            const uint64_t baseC =
+                (pdep64(uint64_t(ta) * G::WM, a.maskA) | pdep64(uint64_t(tb) * G::WN, a.maskB)) | lconst[ci];
+#pragma unroll
+            for (int rb = 0; rb < RA; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        C[baseC | ex.dA[rb] | ex.dV[v] | ex.dB[cb]] = int8_t(ms.center32(acc[rb][cb][v]));
+        }
+        if (!more) break;
+        tile = next;
+        ta = nta;
+        tb = ntb;
+        tA = nA;
+        tB = nB;
+    }
+}
+
+// split-K: sum the partial residues of every K range and scatter into C
+template <class G>
+__global__ __launch_bounds__(256) void k_mfma8_reduce(StepArgs a, const int8_t* part, int64_t part_stride,
+                                                      int splits) {
+    const int g = blockIdx.z;
+    const ModSmall ms{int32_t(a.p[g]), a.r2[g], a.r16[g], a.pinv[g]};
+    int8_t* C = static_cast<int8_t*>(a.C) + g * a.strideC;
+    const int lgA = a.fA - G::LGM, lgB = a.fB - G::LGN;
+    const uint64_t T = uint64_t(1) << (lgA + lgB);
+    const uint64_t n = T * (G::WM * G::WN);
+    const int8_t* pg = part + g * part_stride;
+    for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t tile = e / (G::WM * G::WN), loc = e % (G::WM * G::WN);
+        int32_t sum = 0;  // at most 1024 residues of magnitude 127
+        for (int y = 0; y < splits; ++y) sum += pg[(uint64_t(y) * T + tile) * (G::WM * G::WN) + loc];
+        uint32_t ta, tb;
+        tile_coords_lg(uint32_t(tile), lgA, lgB, ta, tb);
+        const uint64_t i = loc / G::WN, j = loc % G::WN;
+        C[pdep64(uint64_t(ta) * G::WM + i, a.maskA) | pdep64(uint64_t(tb) * G::WN + j, a.maskB)] =
+            int8_t(ms.center32(sum));
+    }
+}
+
+uint64_t pdep_host(uint64_t x, uint64_t m) {
+    uint64_t r = 0;
+    for (; m; m &= m - 1, x >>= 1)
+        if (x & 1) r |= m & (~m + 1);
+    return r;
+}
+
+template <class Gm>
+hipError_t launch_cfg(const StepArgs& a, int G, hipStream_t stream, char* scratch, int64_t scratch_per_plane) {
+    Mfma8Extra ex{};
+    for (int rb = 0; rb < 8; ++rb) ex.dA[rb] = pdep_host(uint64_t(16 * rb), a.maskA);
+    for (int v = 0; v < 4; ++v) ex.dV[v] = pdep_host(uint64_t(v), a.maskA);
+    for (int cb = 0; cb < 4; ++cb) ex.dB[cb] = pdep_host(uint64_t(16 * cb), a.maskB);
+    const uint64_t T = (uint64_t(1) << (a.fA - Gm::LGM)) * (uint64_t(1) << (a.fB - Gm::LGN));
+    // too few output tiles to fill the GPU: split K over block rows (powers
+    // of two, as many partial tiles per plane as the scratch area holds, at
+    // least 8 stages each so that reading operands outweighs writing the
+    // partial tile)
+    const int nk = 1 << (a.s - 6);
+    const uint64_t cap_tiles = uint64_t(scratch_per_plane) / uint64_t(Gm::WM * Gm::WN);
+    int splits = 1;
+    while (T * G * splits * 2 <= 1024 && splits * 16 <= nk && T * splits * 2 <= cap_tiles) splits *= 2;
+    int8_t* part = reinterpret_cast<int8_t*>(scratch);
+    dim3 grid(uint32_t(std::min<uint64_t>(T, 1024)), uint32_t(splits), G);
+    const int per = nk / splits;
+    if (per >= 4)
+        hipLaunchKernelGGL((k_mfma8<Gm, 4>), grid, dim3(Gm::THREADS), 0, stream, a, ex, splits, part,
+                           scratch_per_plane);
+    else if (per == 2)
+        hipLaunchKernelGGL((k_mfma8<Gm, 2>), grid, dim3(Gm::THREADS), 0, stream, a, ex, splits, part,
+                           scratch_per_plane);
+    else
+        hipLaunchKernelGGL((k_mfma8<Gm, 1>), grid, dim3(Gm::THREADS), 0, stream, a, ex, splits, part,
+                           scratch_per_plane);
+    if (splits > 1) {
+        const uint64_t n = T * uint64_t(Gm::WM * Gm::WN);
+        dim3 gr(uint32_t(std::min<uint64_t>((n + 255) / 256, 4096)), 1, G);
+        hipLaunchKernelGGL((k_mfma8_reduce<Gm>), gr, dim3(256), 0, stream, a, part, scratch_per_plane, splits);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool mfma8_eligible(const StepArgs& a) {
+    // at least one 128 x 64 tile, K of at least one 64-entry chunk, a
+    // stage's rows within 32-bit load offsets and the tile count in 32 bits
+    return a.s >= 6 && a.s <= k8MaxRowBytesLog && a.fA >= 7 && a.fB >= 6 && a.fA + a.fB <= 45;
+}
+
+hipError_t launch_mfma8(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
+                        double step_macs, char* scratch, int64_t scratch_per_plane) {
+    if (!mfma8_eligible(a)) return hipErrorInvalidValue;
+    prof->before(stream);
+    hipError_t e;
+    if (a.fB >= 8)
+        e = launch_cfg<Cfg256x256>(a, G, stream, scratch, scratch_per_plane);
+    else if (a.fB == 7)
+        e = a.fA >= 8 ? launch_cfg<Cfg256x128>(a, G, stream, scratch, scratch_per_plane)
+                      : launch_cfg<Cfg128x128>(a, G, stream, scratch, scratch_per_plane);
+    else
+        e = a.fA >= 8 ? launch_cfg<Cfg256x64>(a, G, stream, scratch, scratch_per_plane)
+                      : launch_cfg<Cfg128x64>(a, G, stream, scratch, scratch_per_plane);
+    prof->after_raw(stream, KC_MFMA, step_bytes, step_macs);
+    return e;
+}
+
+}  // namespace tn

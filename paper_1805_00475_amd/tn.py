@@ -24,6 +24,7 @@ FLAG_GENERIC_ONLY = 1
 FLAG_NO_MFMA = 2
 FLAG_TIMING = 4
 FLAG_NO_GRAPH = 8
+FLAG_WIDE_RNS = 16
 KERNEL_CLASSES = ["generic", "stream", "rowdot", "mfma", "batch", "dot", "digits"]
 MAX_RANK = 34
 MAX_PRIMES = 128
@@ -86,6 +87,8 @@ _SIGS = {
                         _P(ctypes.c_uint32), ctypes.c_size_t, _P(ctypes.c_size_t), _P(PlanStats_c)], ctypes.c_int),
     "tn_primes": ([ctypes.c_int32, _P(ctypes.c_uint32)], ctypes.c_int),
     "tn_primes_for": ([ctypes.c_int32, _P(ctypes.c_int32)], ctypes.c_int),
+    "tn_moduli": ([ctypes.c_void_p, _P(ContractOpts_c), _P(ctypes.c_uint32), ctypes.c_int32, _P(ctypes.c_int32)],
+                  ctypes.c_int),
     "tn_crt": ([_P(ctypes.c_uint32), ctypes.c_int32, _P(ctypes.c_uint32), ctypes.c_size_t, _P(ctypes.c_size_t)],
                ctypes.c_int),
     "tn_profile_get": ([_P(KernelProfile_c)], ctypes.c_int),
@@ -248,8 +251,8 @@ def _opts(arith="auto", n_primes=0, ptr=None, nbytes=0, stream=None, prime_group
     return ContractOpts_c(ARITH[arith], n_primes, ptr, nbytes, stream, prime_group, flags)
 
 
-def workspace_bytes(net: Network, plan: Plan, arith="auto", n_primes=0, prime_group=0) -> int:
-    o = _opts(arith, n_primes, prime_group=prime_group)
+def workspace_bytes(net: Network, plan: Plan, arith="auto", n_primes=0, prime_group=0, flags=0) -> int:
+    o = _opts(arith, n_primes, prime_group=prime_group, flags=flags)
     b = ctypes.c_size_t()
     _check(load().tn_workspace_bytes(net.h, plan.h, ctypes.byref(o), ctypes.byref(b)), "tn_workspace_bytes")
     return b.value
@@ -267,17 +270,16 @@ def contract(net: Network, plan: Plan, arith="auto", n_primes=0, workspace: Work
     """Run a plan; returns the residues list (RNS) or the exact int (U64)."""
     lib = load()
     ws = workspace or default_workspace()
-    need = workspace_bytes(net, plan, arith, n_primes, prime_group)
+    need = workspace_bytes(net, plan, arith, n_primes, prime_group, flags)
     ptr, nb = ws.get(max(need, max_bytes))
     o = _opts(arith, n_primes, ptr, nb, current_stream_handle(), prime_group, flags)
     res = (ctypes.c_uint32 * MAX_PRIMES)()
     u = ctypes.c_uint64()
     _check(lib.tn_contract(net.h, plan.h, ctypes.byref(o), res, MAX_PRIMES, ctypes.byref(u)), "tn_contract")
-    n_vars = net.formula.n_vars
-    if arith == "u64" or (arith == "auto" and n_vars <= 63):
+    mods = moduli(plan, arith, n_primes, flags)
+    if not mods:
         return int(u.value)
-    k = n_primes if n_primes > 0 else primes_for(n_vars)
-    return [int(res[i]) for i in range(k)]
+    return [int(res[i]) for i in range(len(mods))]
 
 
 def count_plan(net: Network, plan: Plan, arith="auto", n_primes=0, workspace: Workspace = None,
@@ -285,7 +287,7 @@ def count_plan(net: Network, plan: Plan, arith="auto", n_primes=0, workspace: Wo
     """Exact count (tn_count) of a built network under a plan."""
     lib = load()
     ws = workspace or default_workspace()
-    need = workspace_bytes(net, plan, arith, n_primes, prime_group)
+    need = workspace_bytes(net, plan, arith, n_primes, prime_group, flags)
     ptr, nb = ws.get(max(need, max_bytes))
     o = _opts(arith, n_primes, ptr, nb, current_stream_handle(), prime_group, flags)
     cap = 80
@@ -328,7 +330,8 @@ def count_batch(formulas: Sequence, order: str = "greedy", seed: int = 0, arith=
 def step(A, rA: int, B, rB: int, s: int, maskA: int, prime: int = None, kernel: str = "auto",
          workspace: Workspace = None):
     """One contraction step on the GPU (tn_step). A, B: numpy uint32 (RNS,
-    with ``prime``) or uint64 arrays of 2^rA / 2^rB entries. Returns C."""
+    with ``prime``: a prime of tn_primes or a small modulus <= 255) or uint64
+    arrays of 2^rA / 2^rB entries. Returns C."""
     import numpy as np
     u64 = prime is None
     dt = np.uint64 if u64 else np.uint32
@@ -433,6 +436,15 @@ def primes(k: int) -> List[int]:
     buf = (ctypes.c_uint32 * max(1, k))()
     _check(load().tn_primes(k, buf), "tn_primes")
     return [int(buf[i]) for i in range(k)]
+
+
+def moduli(plan: Plan, arith="auto", n_primes=0, flags=0) -> List[int]:
+    """Residue moduli of a contraction (tn_moduli); [] for 64-bit arithmetic."""
+    o = _opts(arith, n_primes, flags=flags)
+    buf = (ctypes.c_uint32 * MAX_PRIMES)()
+    k = ctypes.c_int32()
+    _check(load().tn_moduli(plan.h, ctypes.byref(o), buf, MAX_PRIMES, ctypes.byref(k)), "tn_moduli")
+    return [int(buf[i]) for i in range(k.value)]
 
 
 def primes_for(n_vars: int) -> int:

@@ -1,0 +1,187 @@
+"""Small-modulus residues (moduli of at most 255, held on the device as
+centred int8): every contraction kernel against the oracle's entry-by-entry
+definition of a step, the int8 matrix-core kernel in each of its tile shapes
+and K schedules, extreme residues, and whole counts in both residue modes."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import instances as I
+from oracle import contract
+from paper_1805_00475_amd import tn
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+MODULI = (255, 251, 254)
+
+
+def _say(*a):
+    print("[gpu case]", *a, flush=True)
+
+
+def _mask(rC, fA, rng):
+    m = 0
+    for q in rng.choice(rC, size=fA, replace=False):
+        m |= 1 << int(q)
+    return m
+
+
+def _inputs(rA, rB, m, rng, kind):
+    if kind == "plus":  # centred +m//2 (+127 for 255): the largest positive products
+        return np.full(1 << rA, m // 2, np.uint32), np.full(1 << rB, m // 2, np.uint32)
+    if kind == "mixed":  # centred values of the largest magnitude, both signs
+        hi = (m + 1) // 2
+        A = np.where(rng.integers(0, 2, size=1 << rA) == 1, m // 2, hi).astype(np.uint32)
+        B = np.where(rng.integers(0, 2, size=1 << rB) == 1, m // 2, hi).astype(np.uint32)
+        return A, B
+    if kind == "raw":  # values not yet reduced: the library takes them modulo m
+        return (rng.integers(0, 1 << 32, size=1 << rA, dtype=np.uint64).astype(np.uint32),
+                rng.integers(0, 1 << 32, size=1 << rB, dtype=np.uint64).astype(np.uint32))
+    return (rng.integers(0, m, size=1 << rA).astype(np.uint32), rng.integers(0, m, size=1 << rB).astype(np.uint32))
+
+
+def _check(rA, rB, s, kernel, m, seed, kind="uniform", samples=None):
+    rng = np.random.default_rng(seed)
+    rC = rA + rB - 2 * s
+    maskA = _mask(rC, rA - s, rng)
+    A, B = _inputs(rA, rB, m, rng, kind)
+    _say(f"kernel={kernel} rA={rA} rB={rB} s={s} m={m} kind={kind} mask={maskA:#x}")
+    C = tn.step(A.copy(), rA, B.copy(), rB, s, maskA, prime=m, kernel=kernel)
+    if samples is None and rC + s > 21:
+        samples = max(24, min(4096, (1 << 21) >> s))
+    if samples is None:
+        cs = range(1 << rC)
+    else:
+        cs = sorted(set(rng.integers(0, 1 << rC, size=samples).tolist()) | {0, (1 << rC) - 1})
+    want = contract.step_entries(A % m, B % m, s, maskA, rC, cs, m)
+    got = [int(C[c]) for c in cs]
+    assert got == want
+
+
+ELEMENT = [
+    ("generic", 5, 4, 2), ("generic", 9, 7, 3), ("generic", 6, 0, 0),
+    ("stream", 14, 5, 3), ("stream", 12, 3, 1), ("stream", 10, 2, 0),
+    ("rowdot", 12, 10, 8), ("rowdot", 9, 9, 9), ("rowdot", 14, 8, 7),
+    ("dot", 14, 14, 14), ("dot", 16, 15, 13),
+    ("auto", 16, 15, 9), ("auto", 12, 3, 1), ("auto", 18, 18, 16),
+]
+
+# int8 matrix-core shapes (free sides fA >= 7, fB >= 6 after the role swap):
+# 128x128 tiles with 1, 2 and 4+ stages per tile, 256x128 and 256x256 tiles,
+# the 4-wave 256x64 and 128x64 tiles of B free sides of 6 bits, K split over
+# block rows, more tiles than work-groups (tile loop), the roles swapped
+MFMA8 = [
+    ("mfma", 13, 13, 6), ("mfma", 14, 14, 7), ("mfma", 15, 15, 8), ("mfma", 16, 15, 8),
+    ("mfma", 17, 17, 9), ("mfma", 18, 17, 10), ("mfma", 22, 21, 12), ("mfma", 20, 19, 8),
+    ("mfma", 23, 20, 13), ("mfma", 19, 21, 11), ("mfma", 18, 17, 8), ("mfma", 23, 23, 16),
+    ("mfma", 14, 14, 6), ("mfma", 16, 16, 7),
+    ("mfma", 14, 12, 6), ("mfma", 16, 13, 7), ("mfma", 18, 16, 10), ("mfma", 19, 15, 9), ("mfma", 13, 12, 6),
+    ("mfma", 17, 16, 10), ("mfma", 21, 20, 14), ("mfma", 15, 16, 9),
+]
+
+
+@pytest.mark.parametrize("kernel,rA,rB,s", ELEMENT + MFMA8)
+def test_kernel_small_modulus(kernel, rA, rB, s):
+    for i, m in enumerate(MODULI[:2]):
+        _check(rA, rB, s, kernel, m, seed=rA * 100 + rB * 10 + s + i)
+
+
+@pytest.mark.parametrize("kernel,rA,rB,s", [("mfma", 15, 15, 8), ("mfma", 17, 17, 9), ("generic", 9, 7, 3),
+                                            ("stream", 14, 5, 3), ("rowdot", 12, 10, 8)])
+def test_even_modulus(kernel, rA, rB, s):
+    # 254: the centred range is (-127, 127], one sided at 127
+    _check(rA, rB, s, kernel, 254, seed=3)
+
+
+@pytest.mark.parametrize("kind", ["plus", "mixed", "raw"])
+@pytest.mark.parametrize("kernel,rA,rB,s", [("mfma", 17, 17, 9), ("mfma", 22, 21, 12), ("mfma", 23, 23, 16),
+                                            ("stream", 13, 7, 5), ("rowdot", 12, 10, 8), ("dot", 16, 15, 13),
+                                            ("generic", 9, 7, 3)])
+def test_small_modulus_extreme_residues(kernel, rA, rB, s, kind):
+    _check(rA, rB, s, kernel, 255, seed=7, kind=kind, samples=1500)
+
+
+def test_tiny_moduli():
+    for m in (2, 3, 7):
+        _check(15, 15, 8, "mfma", m, seed=m)
+        _check(12, 10, 8, "rowdot", m, seed=m)
+
+
+def test_mfma8_refuses_narrow():
+    # a free side of 5 bits has no int8 matrix-core tile
+    rng = np.random.default_rng(0)
+    A = rng.integers(0, 255, size=1 << 16).astype(np.uint32)
+    B = rng.integers(0, 255, size=1 << 14).astype(np.uint32)
+    with pytest.raises(tn.TNError):
+        tn.step(A, 16, B, 14, 9, (1 << 7) - 1, prime=255, kernel="mfma")
+
+
+def test_mfma8_full_size_sampled():
+    # 2^11 output tiles of 256 x 256: more than the 1024 work-groups
+    _check(24, 23, 10, "mfma", 255, seed=11, samples=300)
+    # the largest narrow step of the n=200 cubic vertex-cover plans: 2^13
+    # tiles of 256 x 64 with one stage each
+    _check(27, 12, 6, "mfma", 253, seed=12, samples=300)
+    # B free side of 6 bits, K = 2^17 split over block rows
+    _check(24, 23, 17, "mfma", 251, seed=15, samples=24)
+
+
+def test_mfma8_exact_range_flush():
+    # 2^6 tiles of 256 x 256 with K = 2^17 in one block row: the int32 sums
+    # are reduced after 2^16 entries, at the largest products
+    _check(28, 28, 17, "mfma", 255, seed=13, kind="plus", samples=24)
+    _check(28, 28, 17, "mfma", 251, seed=14, samples=24)
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as fh:
+        return json.load(fh)
+
+
+def test_moduli_choice():
+    f = I.cvc(200, 0)
+    plan = tn.Network(f).order("community")
+    small = tn.moduli(plan)
+    assert max(small) <= 255 and len(small) >= 25
+    wide = tn.moduli(plan, flags=tn.FLAG_WIDE_RNS)
+    assert wide == tn.primes(tn.primes_for(200))
+    assert tn.moduli(plan, n_primes=9) == tn.primes(9)
+    assert tn.moduli(tn.Network(I.cvc(40, 0)).order("community")) == []
+
+
+def test_wide_and_small_counts_agree():
+    for it in _gold("cvc_counts.json")["items"]:
+        if it["n"] not in (120, 200) or it["seed"] > 1:
+            continue
+        f = I.cvc(it["n"], it["seed"])
+        _say(f"cvc n={it['n']} seed={it['seed']} both residue modes")
+        want = int(it["count"])
+        assert tn.count(f, "community", seed=it["seed"]) == want
+        assert tn.count(f, "community", seed=it["seed"], flags=tn.FLAG_WIDE_RNS) == want
+        assert tn.count(f, "community", seed=it["seed"], flags=tn.FLAG_WIDE_RNS | tn.FLAG_NO_MFMA) == want
+        assert tn.count(f, "community", seed=it["seed"], flags=tn.FLAG_NO_MFMA) == want
+    # n = 200 (27 small moduli, 13 primes): the two modes agree
+    f = I.cvc(200, 3)
+    _say("cvc n=200 seed=3 both residue modes")
+    assert tn.count(f, "community", seed=3) == tn.count(f, "community", seed=3, flags=tn.FLAG_WIDE_RNS)
+
+
+def test_contract_residues_small_moduli():
+    f = I.cvc(120, 0)
+    net = tn.Network(f)
+    plan = net.order("community")
+    want = tn.count_plan(net, plan, flags=tn.FLAG_WIDE_RNS)
+    mods = tn.moduli(plan)
+    res = tn.contract(net, plan)
+    assert res == [want % m for m in mods]
+
+
+def test_batch_wide_rns():
+    with open(os.path.join(GOLD, "batch_counts.json")) as fh:
+        g = {it["index"]: int(it["count"]) for it in json.load(fh)["items"]}
+    fs = [I.batch_instance(i) for i in sorted(g)][:24]
+    _say("batch of 24 with 16-bit primes")
+    got = tn.count_batch(fs, "best", seed=0, flags=tn.FLAG_WIDE_RNS, workspace_bytes_=8 << 30)
+    assert got == [g[i] for i in sorted(g)][:24]
