@@ -48,10 +48,93 @@ constexpr int k8MaxRowBytesLog = 25;       // 127 rows of a stage within 32-bit 
 
 // Output addressing of the epilogue, by the host: C offset bits of the
 // tile-local A indices 16 rb (rb < 8) and v (v < 4) and of the B indices
-// 16 cb (cb < 4).
+// 16 cb (cb < 4). A lane holds four outputs, A indices v = 0..3 (A's two
+// lowest bits) at one B index. mode 0: those are C's two lowest bits, so
+// the four are consecutive bytes; mode 1: C's two lowest bits are A's
+// lowest and B's lowest (either order), so a lane and its neighbour (B
+// indices differing in the lowest bit) swap halves and each stores 4
+// consecutive bytes, the even lane those of v < 2 and the odd lane those of
+// v >= 2; sel are the byte selectors of that swap (even, odd lane); mode 2:
+// single bytes.
 struct Mfma8Extra {
     uint64_t dA[8], dV[4], dB[4];
+    uint32_t sel[2];
+    int32_t mode;
 };
+
+// Centred residue of an exact int32 sum modulo m <= 255, returned as the low
+// byte of a float's bit pattern. With FOLD, x = h 2^16 + l becomes
+// y = h (2^16 mod m) + l; else |x| < 2^21 already (K <= 128). Then
+// |y| < 2^15 (m - 1) + 2^16, exact in single precision, q = rint(y / m) with
+// the quotient's rounding error below 2^-23 |y|, and y - q m, exact by one
+// fma, lies within m/2 + 1 of zero: |r| <= 127 for every m <= 255. Adding
+// 1.5 2^23 leaves r in the low mantissa bits in two's complement.
+template <bool FOLD>
+__device__ __forceinline__ uint32_t res8(int32_t x, int32_t r16, float mf, float inv) {
+    const int32_t y = FOLD ? (x >> 16) * r16 + (x & 0xffff) : x;
+    const float f = float(y);
+    const float q = __builtin_rintf(f * inv);
+    const float r = __builtin_fmaf(-q, mf, f);
+    return __float_as_uint(r + 12582912.0f);
+}
+
+// The low bytes of four words, packed (word 0 in byte 0).
+__device__ __forceinline__ uint32_t pack4(uint32_t t0, uint32_t t1, uint32_t t2, uint32_t t3) {
+    const uint32_t lo = __builtin_amdgcn_perm(t1, t0, 0x0c0c0400u), hi = __builtin_amdgcn_perm(t3, t2, 0x0c0c0400u);
+    return __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+}
+
+// Store a wave's outputs of one tile: lane (fr, q) holds acc[rb][cb][v] for
+// A index 16 rb + 4 q + v and B index 16 cb + fr (plus the wave's offsets);
+// baseC is the C offset of the lane's first stored byte (tile, wave and lane
+// parts, see Mfma8Extra for the modes).
+template <int RA, int CB, bool FOLD>
+__device__ __forceinline__ void store_tile8(const v4i (&acc)[RA][CB], int8_t* C, uint64_t baseC, const Mfma8Extra& ex,
+                                            const ModSmall& ms, int lane) {
+    const float mf = float(ms.m);
+    const int32_t r16 = int32_t(ms.r16);
+    // (the row offset passes through an empty asm statement so that the
+    // compiler does not precompute all RA x CB table combinations in
+    // scalar registers, which would spill)
+    if (ex.mode != 2) {
+        const uint32_t sel = ex.sel[lane & 1];
+#pragma unroll
+        for (int rb = 0; rb < RA; ++rb) {
+            uint64_t row = baseC | ex.dA[rb];
+            __asm__ volatile("" : "+v"(row));
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const uint32_t x =
+                    pack4(res8<FOLD>(acc[rb][cb][0], r16, mf, ms.inv), res8<FOLD>(acc[rb][cb][1], r16, mf, ms.inv),
+                          res8<FOLD>(acc[rb][cb][2], r16, mf, ms.inv), res8<FOLD>(acc[rb][cb][3], r16, mf, ms.inv));
+                // the neighbour lane's word (quad permutation 1, 0, 3, 2)
+                const uint32_t y = uint32_t(__builtin_amdgcn_mov_dpp(int(x), 0xb1, 0xf, 0xf, false));
+                *reinterpret_cast<uint32_t*>(C + (row | ex.dB[cb])) = __builtin_amdgcn_perm(x, y, sel);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int rb = 0; rb < RA; ++rb) {
+            uint64_t row = baseC | ex.dA[rb];
+            __asm__ volatile("" : "+v"(row));
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    C[row | ex.dV[v] | ex.dB[cb]] = int8_t(res8<FOLD>(acc[rb][cb][v], r16, mf, ms.inv));
+        }
+    }
+}
+
+// Lane part of the C offset of the lane's first stored byte (see Mfma8Extra):
+// A index wr + 4 q, B index wc + fr; in mode 1 the lane stores the outputs of
+// B index wc + (fr & ~1) and A indices wr + 4 q + 2 (fr & 1) + {0, 1}.
+__device__ __forceinline__ uint64_t lane_offset8(const StepArgs& a, const Mfma8Extra& ex, int wr, int wc, int fr,
+                                                 int q) {
+    if (ex.mode == 1)
+        return pdep64(uint64_t(wr + 4 * q + 2 * (fr & 1)), a.maskA) | pdep64(uint64_t(wc + (fr & ~1)), a.maskB);
+    return pdep64(uint64_t(wr + 4 * q), a.maskA) | pdep64(uint64_t(wc + fr), a.maskB);
+}
 
 constexpr int lg2(int x) { return x <= 1 ? 0 : 1 + lg2(x / 2); }
 
@@ -103,10 +186,10 @@ __global__ __launch_bounds__(G::THREADS, 1) void k_mfma8(StepArgs a, Mfma8Extra 
     if (blockIdx.x >= T) return;
 
     const int fr = lane & 15, q = lane >> 4;
-    // lane part of the output offset (A index wr + 4 q, B index wc + fr),
-    // kept in LDS: the epilogue reads it once per tile, and in registers
-    // through the K loop it would only add pressure
-    lconst[tid] = pdep64(uint64_t(wr + 4 * q), a.maskA) | pdep64(uint64_t(wc + fr), a.maskB);
+    // lane part of the output offset, kept in LDS: the epilogue reads it
+    // once per tile, and in registers through the K loop it would only add
+    // pressure
+    lconst[tid] = lane_offset8(a, ex, wr, wc, fr, q);
     // loads: lane l of wave w, instruction i fills physical slot l % 4 of
     // stage row GROUP i + 16 w + l / 4, i.e. logical slot (l % 4) ^ (l / 16):
     // bytes 16 ((l % 4) ^ (l / 16)).. of that row's chunk
@@ -250,30 +333,30 @@ __global__ __launch_bounds__(G::THREADS, 1) void k_mfma8(StepArgs a, Mfma8Extra 
 
         // epilogue: lane holds A index wr + 16 rb + 4 q + v, B index
         // wc + 16 cb + fr of each 16x16 block
+        constexpr bool FOLD = NK >= 4;
+        const float mf = float(ms.m);
+        const int32_t r16 = int32_t(ms.r16);
+        auto packed = [&](int rb, int cb) {
+            return pack4(res8<FOLD>(acc[rb][cb][0], r16, mf, ms.inv), res8<FOLD>(acc[rb][cb][1], r16, mf, ms.inv),
+                         res8<FOLD>(acc[rb][cb][2], r16, mf, ms.inv), res8<FOLD>(acc[rb][cb][3], r16, mf, ms.inv));
+        };
         if (splits > 1) {
-            // partial residues of this K range, tile-local order (i, j)
+            // partial residues of this K range, tile-local order (j, i): the
+            // lane's four A indices are consecutive bytes
             int8_t* pt = part + blockIdx.z * part_stride + (uint64_t(blockIdx.y) * T + tile) * (G::WM * G::WN);
-            uint32_t lo = uint32_t((wr + 4 * q) * G::WN + wc + fr);
+            uint32_t lo = uint32_t((wc + fr) * G::WM + wr + 4 * q);
             __asm__ volatile("" : "+v"(lo));
 #pragma unroll
             for (int rb = 0; rb < RA; ++rb)
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        pt[lo + uint32_t((16 * rb + v) * G::WN + 16 * cb)] = int8_t(ms.center32(acc[rb][cb][v]));
+                    *reinterpret_cast<uint32_t*>(pt + lo + uint32_t(16 * cb * G::WM + 16 * rb)) = packed(rb, cb);
         } else {
             int ci = tid;
             __asm__ volatile("" : "+v"(ci));  // read here, per tile
             const uint64_t baseC =
                 (pdep64(uint64_t(ta) * G::WM, a.maskA) | pdep64(uint64_t(tb) * G::WN, a.maskB)) | lconst[ci];
-#pragma unroll
-            for (int rb = 0; rb < RA; ++rb)
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        C[baseC | ex.dA[rb] | ex.dV[v] | ex.dB[cb]] = int8_t(ms.center32(acc[rb][cb][v]));
+            store_tile8<RA, CB, FOLD>(acc, C, baseC, ex, ms, lane);
         }
         if (!more) break;
         tile = next;
@@ -296,14 +379,83 @@ __global__ __launch_bounds__(256) void k_mfma8_reduce(StepArgs a, const int8_t* 
     const uint64_t n = T * (G::WM * G::WN);
     const int8_t* pg = part + g * part_stride;
     for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += uint64_t(gridDim.x) * blockDim.x) {
-        const uint64_t tile = e / (G::WM * G::WN), loc = e % (G::WM * G::WN);
+        const uint64_t tile = e / (G::WM * G::WN), loc = e % (G::WM * G::WN);  // loc = j WM + i
         int32_t sum = 0;  // at most 1024 residues of magnitude 127
         for (int y = 0; y < splits; ++y) sum += pg[(uint64_t(y) * T + tile) * (G::WM * G::WN) + loc];
         uint32_t ta, tb;
         tile_coords_lg(uint32_t(tile), lgA, lgB, ta, tb);
-        const uint64_t i = loc / G::WN, j = loc % G::WN;
+        const uint64_t j = loc / G::WM, i = loc % G::WM;
         C[pdep64(uint64_t(ta) * G::WM + i, a.maskA) | pdep64(uint64_t(tb) * G::WN + j, a.maskB)] =
             int8_t(ms.center32(sum));
+    }
+}
+
+// Short shared dimension, K = 2^S <= 32: no staging. Each lane reads its
+// fragments straight from A's and B's rows (K consecutive bytes, the tile's
+// rows consecutive in memory, so a wave's fragment load covers 16 whole rows)
+// -- 8 bytes at K offset 8 q, zero where 8 q >= K -- and one
+// v_mfma_i32_16x16x32_i8 per 16x16 block gives the exact sums (at most
+// 32 127^2 < 2^21). The next tile's fragments are loaded before the current
+// tile's outputs are stored.
+template <class G, int S>
+__global__ __launch_bounds__(G::THREADS) void k_mfma8_short(StepArgs a, Mfma8Extra ex) {
+    constexpr int RA = G::RA, CB = G::CB, K = 1 << S;
+    const int g = blockIdx.z;
+    const int8_t* A = static_cast<const int8_t*>(a.A) + g * a.strideA;
+    const int8_t* B = static_cast<const int8_t*>(a.B) + g * a.strideB;
+    int8_t* C = static_cast<int8_t*>(a.C) + g * a.strideC;
+    const ModSmall ms{int32_t(a.p[g]), a.r2[g], a.r16[g], a.pinv[g]};
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = (w % G::WAVES_A) * 16 * RA, wc = (w / G::WAVES_A) * 16 * CB;
+    const int lgA = a.fA - G::LGM, lgB = a.fB - G::LGN;
+    const uint32_t T = 1u << (lgA + lgB);
+    const int fr = lane & 15, q = lane >> 4;
+    const uint64_t lc = lane_offset8(a, ex, wr, wc, fr, q);
+    // lane's fragment offset within a tile's rows: row wr + fr (A) or
+    // wc + fr (B), K offset 8 q
+    const uint32_t offA = uint32_t((wr + fr) * K + 8 * q), offB = uint32_t((wc + fr) * K + 8 * q);
+    typedef long frag_t;
+    auto load = [&](const int8_t* p) -> frag_t {
+        if constexpr (S >= 3) {
+            if (8 * q >= K) return 0;
+            return *reinterpret_cast<const frag_t*>(p);
+        } else {
+            if (q != 0) return 0;
+            if constexpr (S == 2) return frag_t(*reinterpret_cast<const uint32_t*>(p));
+            if constexpr (S == 1) return frag_t(*reinterpret_cast<const uint16_t*>(p));
+            return frag_t(*reinterpret_cast<const uint8_t*>(p));
+        }
+    };
+    frag_t fa[RA], fb[CB];
+    auto fetch = [&](uint32_t tile) {
+        uint32_t ta, tb;
+        tile_coords_lg(tile, lgA, lgB, ta, tb);
+        const int8_t* pA = A + uint64_t(ta) * G::WM * K + offA;
+        const int8_t* pB = B + uint64_t(tb) * G::WN * K + offB;
+#pragma unroll
+        for (int rb = 0; rb < RA; ++rb) fa[rb] = load(pA + 16 * K * rb);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) fb[cb] = load(pB + 16 * K * cb);
+    };
+    uint32_t tile = blockIdx.x;
+    if (tile >= T) return;
+    fetch(tile);
+    for (;;) {
+        v4i acc[RA][CB];
+#pragma unroll
+        for (int rb = 0; rb < RA; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+                acc[rb][cb] = __builtin_amdgcn_mfma_i32_16x16x32_i8(fa[rb], fb[cb], v4i{0, 0, 0, 0}, 0, 0, 0);
+        const uint32_t next = tile + gridDim.x;
+        uint32_t ta, tb;
+        tile_coords_lg(tile, lgA, lgB, ta, tb);
+        if (next < T) fetch(next);
+        const uint64_t baseC = (pdep64(uint64_t(ta) * G::WM, a.maskA) | pdep64(uint64_t(tb) * G::WN, a.maskB)) | lc;
+        store_tile8<RA, CB, false>(acc, C, baseC, ex, ms, lane);
+        if (next >= T) break;
+        tile = next;
     }
 }
 
@@ -314,12 +466,33 @@ uint64_t pdep_host(uint64_t x, uint64_t m) {
     return r;
 }
 
-template <class Gm>
-hipError_t launch_cfg(const StepArgs& a, int G, hipStream_t stream, char* scratch, int64_t scratch_per_plane) {
+Mfma8Extra extra_of(const StepArgs& a) {
     Mfma8Extra ex{};
     for (int rb = 0; rb < 8; ++rb) ex.dA[rb] = pdep_host(uint64_t(16 * rb), a.maskA);
     for (int v = 0; v < 4; ++v) ex.dV[v] = pdep_host(uint64_t(v), a.maskA);
     for (int cb = 0; cb < 4; ++cb) ex.dB[cb] = pdep_host(uint64_t(16 * cb), a.maskB);
+    // v_perm selectors: bytes 0..3 of the neighbour's word are 0..3, the
+    // lane's own are 4..7
+    if ((a.maskA & 3) == 3) {
+        ex.mode = 0;
+        ex.sel[0] = ex.sel[1] = 0x07060504u;
+    } else if ((a.maskB & 1) && (a.maskA & 2)) {  // C bit 0 from B, bit 1 from A
+        ex.mode = 1;
+        ex.sel[0] = 0x01050004u;  // own v0, neighbour v0, own v1, neighbour v1
+        ex.sel[1] = 0x07030602u;  // neighbour v2, own v2, neighbour v3, own v3
+    } else if ((a.maskA & 1) && (a.maskB & 2)) {  // C bit 0 from A, bit 1 from B
+        ex.mode = 1;
+        ex.sel[0] = 0x01000504u;  // own v0, own v1, neighbour v0, neighbour v1
+        ex.sel[1] = 0x07060302u;  // neighbour v2, neighbour v3, own v2, own v3
+    } else {
+        ex.mode = 2;
+    }
+    return ex;
+}
+
+template <class Gm>
+hipError_t launch_cfg(const StepArgs& a, int G, hipStream_t stream, char* scratch, int64_t scratch_per_plane) {
+    const Mfma8Extra ex = extra_of(a);
     const uint64_t T = (uint64_t(1) << (a.fA - Gm::LGM)) * (uint64_t(1) << (a.fB - Gm::LGN));
     // too few output tiles to fill the GPU: split K over block rows (powers
     // of two, as many partial tiles per plane as the scratch area holds, at
@@ -349,12 +522,33 @@ hipError_t launch_cfg(const StepArgs& a, int G, hipStream_t stream, char* scratc
     return hipGetLastError();
 }
 
+template <class Gm, int S>
+hipError_t launch_short(const StepArgs& a, int G, hipStream_t stream) {
+    const uint64_t T = (uint64_t(1) << (a.fA - Gm::LGM)) * (uint64_t(1) << (a.fB - Gm::LGN));
+    dim3 grid(uint32_t(std::min<uint64_t>(T, 2048)), 1, G);
+    hipLaunchKernelGGL((k_mfma8_short<Gm, S>), grid, dim3(Gm::THREADS), 0, stream, a, extra_of(a));
+    return hipGetLastError();
+}
+
+template <class Gm>
+hipError_t launch_short_s(const StepArgs& a, int G, hipStream_t stream) {
+    switch (a.s) {
+        case 0: return launch_short<Gm, 0>(a, G, stream);
+        case 1: return launch_short<Gm, 1>(a, G, stream);
+        case 2: return launch_short<Gm, 2>(a, G, stream);
+        case 3: return launch_short<Gm, 3>(a, G, stream);
+        case 4: return launch_short<Gm, 4>(a, G, stream);
+        default: return launch_short<Gm, 5>(a, G, stream);
+    }
+}
+
 }  // namespace
 
 bool mfma8_eligible(const StepArgs& a) {
     // at least one 128 x 64 tile, K of at least one 64-entry chunk, a
     // stage's rows within 32-bit load offsets and the tile count in 32 bits
-    return a.s >= 6 && a.s <= k8MaxRowBytesLog && a.fA >= 7 && a.fB >= 6 && a.fA + a.fB <= 45;
+    // (K below 64: the unstaged kernel, 128 x 128 or 128 x 64 tiles)
+    return a.s >= 0 && a.s <= k8MaxRowBytesLog && a.fA >= 7 && a.fB >= 6 && a.fA + a.fB <= 45;
 }
 
 hipError_t launch_mfma8(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
@@ -362,7 +556,9 @@ hipError_t launch_mfma8(const StepArgs& a, int G, hipStream_t stream, Profiler* 
     if (!mfma8_eligible(a)) return hipErrorInvalidValue;
     prof->before(stream);
     hipError_t e;
-    if (a.fB >= 8)
+    if (a.s < 6)
+        e = a.fB >= 7 ? launch_short_s<Cfg128x128>(a, G, stream) : launch_short_s<Cfg128x64>(a, G, stream);
+    else if (a.fB >= 8)
         e = launch_cfg<Cfg256x256>(a, G, stream, scratch, scratch_per_plane);
     else if (a.fB == 7)
         e = a.fA >= 8 ? launch_cfg<Cfg256x128>(a, G, stream, scratch, scratch_per_plane)

@@ -79,6 +79,10 @@ MFMA8 = [
     ("mfma", 14, 14, 6), ("mfma", 16, 16, 7),
     ("mfma", 14, 12, 6), ("mfma", 16, 13, 7), ("mfma", 18, 16, 10), ("mfma", 19, 15, 9), ("mfma", 13, 12, 6),
     ("mfma", 17, 16, 10), ("mfma", 21, 20, 14), ("mfma", 15, 16, 9),
+    # K = 2^s <= 32: fragments straight from A's and B's rows, 128x128 and
+    # 128x64 tiles, s = 0..5
+    ("mfma", 12, 12, 5), ("mfma", 13, 12, 4), ("mfma", 14, 13, 3), ("mfma", 10, 9, 2), ("mfma", 9, 8, 1),
+    ("mfma", 8, 7, 0), ("mfma", 12, 11, 5), ("mfma", 11, 9, 3), ("mfma", 9, 7, 1),
 ]
 
 
@@ -126,6 +130,8 @@ def test_mfma8_full_size_sampled():
     _check(27, 12, 6, "mfma", 253, seed=12, samples=300)
     # B free side of 6 bits, K = 2^17 split over block rows
     _check(24, 23, 17, "mfma", 251, seed=15, samples=24)
+    # K = 32 with 2^12 tiles of 128 x 128: more than the 2048 work-groups
+    _check(20, 16, 5, "mfma", 255, seed=16, samples=2000)
 
 
 def test_mfma8_exact_range_flush():
