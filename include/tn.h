@@ -89,13 +89,17 @@ typedef enum {
 } tn_order_kind;
 
 /* Predicted cost of a plan, known before any tensor entry is touched (the
- * "lazy" evaluation of Sec. 4). Entries count 32-bit words per prime. */
+ * "lazy" evaluation of Sec. 4). Entries and multiply-adds are per residue
+ * plane; log2_cost is the log2 of the predicted device time in microseconds
+ * of the whole contraction in the default residue arithmetic (64-bit counts
+ * for n_vars <= 63, else small moduli when they hold the count, else 16-bit
+ * primes; all planes and launches). */
 typedef struct {
     int32_t n_steps;
     int32_t max_rank;              /* largest rank of any tensor in the plan */
     double entries;                /* sum over steps of 2^rA + 2^rB + 2^rC */
     double macs;                   /* sum over steps of 2^(rA + rB - s) */
-    double log2_cost;              /* log2 of the cost model used to judge orders */
+    double log2_cost;              /* log2 of the predicted device time (us) used to judge orders */
     uint64_t peak_elems;           /* arena high-water mark in entries, one prime */
     int32_t chosen;                /* tn_order_kind that produced the plan */
     int32_t fallback;              /* 1 when the learned order lost to the judge */

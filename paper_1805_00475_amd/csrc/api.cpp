@@ -12,7 +12,7 @@ namespace tn {
 // randomized bisection trials the judge may try
 constexpr int kPartitionTrials = 16;
 // host microseconds of order search allowed per predicted device microsecond
-constexpr double kSearchRatio = 1.0;
+constexpr double kSearchRatio = 2.0;
 // most host time spent reconfiguring one plan
 constexpr double kRefineCapUs = 400000.0;
 
@@ -58,15 +58,14 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         // far (all residue planes). The device cannot start before the first
         // plan of a batch is ready, so search time beyond the device time it
         // saves is a loss; measured on batches of n = 200 cubic vertex-cover
-        // instances, one host microsecond per predicted device microsecond
-        // gives the shortest batch (a quarter of that gives much worse plans,
-        // four times that no better ones).
+        // instances (small-modulus residues), two host microseconds per
+        // predicted device microsecond give the shortest batch (one gives
+        // worse plans, four and eight a longer wait for the first plan).
         const auto t0 = std::chrono::steady_clock::now();
-        const double planes = N.n_vars <= 63 ? 1.0 : double(primes_needed(N.n_vars));
         auto over_budget = [&]() {
             const double spent_us =
                 std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
-            return have && spent_us > kSearchRatio * planes * plan_cost(out);
+            return have && spent_us > kSearchRatio * plan_cost(out);
         };
         auto partition_trial = [&](int t) {
             Plan p;
@@ -88,7 +87,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         for (int t = 4; t < kPartitionTrials && !over_budget(); ++t) partition_trial(t);
         // local reconfiguration of the winner's contraction tree
         if (have && out.merges.size() > 2) {
-            const double budget = std::min(kRefineCapUs, kSearchRatio * planes * plan_cost(out));
+            const double budget = std::min(kRefineCapUs, kSearchRatio * plan_cost(out));
             Plan p;
             const int32_t chosen = out.stats.chosen;
             if (make_plan(N, refine_order(N, out.merges, budget), chosen, p) == TN_OK &&

@@ -89,8 +89,17 @@ Reduced absorb_small(const Network& net);
 // plan.cpp
 tn_status make_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>> merges,
                     int32_t chosen, Plan& plan);
+// Residue arithmetic a contraction uses by default for n_vars variables:
+// 64-bit wrapping counts (n_vars <= 63), small moduli (int8 residues) when
+// their product holds the count, else 16-bit primes; and its plane count.
+enum ResidueMode : int { RM_U64 = 0, RM_WIDE = 1, RM_SMALL = 2 };
+int default_residue_mode(int32_t n_vars);
+int32_t default_planes(int32_t n_vars);
+// Predicted device time in microseconds: of a whole plan under its default
+// residue mode (all planes, launches included), and of one step for one
+// residue plane (launch excluded).
 double plan_cost(const Plan& plan);
-double step_cost_model(int rA, int rB, int s, int rC);  // microseconds, one prime
+double step_cost_model(int rA, int rB, int s, int rC, int mode);
 // order_refine.cpp: exact re-optimization of subtrees with up to 8 frontier
 // nodes, sweeping the largest tensors first, within budget_us
 std::vector<std::pair<int32_t, int32_t>> refine_order(const Network& net,

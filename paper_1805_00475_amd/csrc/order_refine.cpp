@@ -20,8 +20,6 @@
 
 namespace tn {
 
-double step_cost_model(int rA, int rB, int s, int rC);
-
 namespace {
 
 struct Tree {
@@ -40,11 +38,13 @@ struct Tree {
 constexpr int kMaxFrontier = 8;
 
 // set per refinement (per thread: orders are searched on worker threads):
-// no intermediate may exceed the plan's largest rank
+// no intermediate may exceed the plan's largest rank; steps are priced in
+// the network's default residue arithmetic
 thread_local int g_rank_cap = 64;
+thread_local int g_mode = RM_SMALL;
 
 double merge_cost(int ra, int rb, int rc) {
-    const double c = step_cost_model(ra, rb, (ra + rb - rc) / 2, rc);
+    const double c = step_cost_model(ra, rb, (ra + rb - rc) / 2, rc, g_mode);
     return rc > g_rank_cap ? c + 1e15 : c;
 }
 
@@ -187,6 +187,7 @@ std::vector<std::pair<int32_t, int32_t>> refine_order(const Network& net,
     int maxr = 0;
     for (int32_t v = 0; v < n; ++v) maxr = std::max(maxr, t.rank(v));
     g_rank_cap = maxr;  // keep peak memory: never raise the largest rank
+    g_mode = default_residue_mode(net.n_vars);
     std::vector<char> is_frontier(n, 0);
     for (int sweep = 0; sweep < 4; ++sweep) {
         bool any = false;

@@ -76,39 +76,70 @@ struct Arena {
 
 }  // namespace
 
-// Predicted device time in microseconds of one step for one prime, from
-// the kernels' measured behaviour on MI355X. Dense steps (the int8-limb
-// MFMA path: s >= 6, larger free side >= 7 bits, smaller >= 6) run at the
-// int8 peak (5e15 ops/s, 8 ops per modular multiply-add: four digit-pair
-// products) times an efficiency that grows with K = 2^s (the per-tile
-// epilogue is amortized over K; table below for s = 6..13 and beyond),
-// plus a digit pass over both operands (4 bytes read, 2 written per entry)
-// at ~5e12 B/s and the output write. Other wide steps (s >= 6) run on vector units at ~2.3e11
-// B/s of algorithmic traffic (wave per output); streaming steps move
-// 4 (2^rA + 2^rB + 2^rC) bytes at ~1e12 B/s; every launch costs ~3 us.
-double step_cost_model(int rA, int rB, int s, int rC) {
-    static const double eff[] = {0.042, 0.087, 0.12, 0.22, 0.31, 0.39, 0.45, 0.45};
-    const double bytes = 4.0 * (std::ldexp(1.0, rA) + std::ldexp(1.0, rB) + std::ldexp(1.0, rC));
+int default_residue_mode(int32_t n_vars) {
+    if (n_vars <= 63) return RM_U64;
+    return small_moduli_needed(n_vars) > 0 ? RM_SMALL : RM_WIDE;
+}
+
+int32_t default_planes(int32_t n_vars) {
+    switch (default_residue_mode(n_vars)) {
+        case RM_U64: return 1;
+        case RM_SMALL: return small_moduli_needed(n_vars);
+        default: return primes_needed(n_vars);
+    }
+}
+
+// Predicted device time in microseconds of one step for one residue plane,
+// launch excluded, from the kernels' measured behaviour on MI355X
+// (single-instance contractions of cubic vertex-cover and 1-in-3 formulas,
+// n = 80..225, fitted per kernel class).
+//  - small moduli (1-byte entries): the int8 matrix-core kernels (larger free
+//    side >= 7 bits, smaller >= 6, any K) take 1 / 1.5e15 s per multiply-add
+//    plus the entries read and written at 2e12 B/s (within 15 % from K = 2^5
+//    to 2^13: small K is bound by the output write, large K by the matrix
+//    cores at about 60 % of the int8 peak); the split-K dot (rC <= 6,
+//    s >= 10) moves its bytes at 1.8e12 B/s, the wave-per-output kernel
+//    (other s >= 6) at 4e10 B/s, streaming steps (s <= 5) at 7e11 B/s.
+//  - 64-bit counts (8-byte entries, no matrix cores): the same non-matrix
+//    classes.
+//  - 16-bit primes (4-byte entries): the int8-limb matrix-core kernel at the
+//    int8 peak (8 ops per modular multiply-add: four digit-pair products)
+//    times an efficiency that grows with K (the per-tile epilogue is
+//    amortized; table for s = 6..13 and beyond) plus a digit pass over both
+//    operands (4 bytes read, 2 written per entry) and the output write;
+//    other steps as above with 4-byte entries.
+double step_cost_model(int rA, int rB, int s, int rC, int mode) {
+    const double ea = std::ldexp(1.0, rA), eb = std::ldexp(1.0, rB), ec = std::ldexp(1.0, rC);
     const double macs = std::ldexp(1.0, rA + rB - s);
     const int fa = std::max(rA, rB) - s, fb = std::min(rA, rB) - s;
+    const double es = mode == RM_U64 ? 8.0 : mode == RM_WIDE ? 4.0 : 1.0;
+    const double bytes = es * (ea + eb + ec);
     double t;
-    if (s >= 6 && fa >= 7 && fb >= 6) {
+    if (mode == RM_SMALL && fa >= 7 && fb >= 6) {
+        t = macs / 1.5e15 + bytes / 2e12;
+    } else if (mode == RM_WIDE && s >= 6 && fa >= 7 && fb >= 6) {
+        static const double eff[] = {0.042, 0.087, 0.12, 0.22, 0.31, 0.39, 0.45, 0.45};
         const double e = eff[std::min(s, 13) - 6];
-        t = macs * 8.0 / (5e15 * e) + 6.0 * (std::ldexp(1.0, rA) + std::ldexp(1.0, rB)) / 5e12 +
-            4.0 * std::ldexp(1.0, rC) / 2.5e12;
-    } else if (s >= 6 && rC <= 6 && s >= 10) {
-        t = bytes / 5e12;  // split-K dot
+        t = macs * 8.0 / (5e15 * e) + 6.0 * (ea + eb) / 5e12 + 4.0 * ec / 2.5e12;
+    } else if (s >= 10 && rC <= 6) {
+        t = bytes / 1.8e12;  // split-K dot
     } else if (s >= 6) {
-        t = bytes / 2.3e11;
+        t = bytes / 4e10;
     } else {
-        t = bytes / 1e12;
+        t = bytes / 7e11;
     }
-    return 1e6 * t + 3.0;
+    return 1e6 * t;
 }
 
 double plan_cost(const Plan& plan) {
+    constexpr int kPlanesPerLaunch = 16;  // residue planes of one launch
+    constexpr double kLaunchUs = 5.0;
+    const int mode = default_residue_mode(plan.n_vars);
+    const int32_t planes = default_planes(plan.n_vars);
+    const double launches = double((planes + kPlanesPerLaunch - 1) / kPlanesPerLaunch);
     double t = 0;
-    for (const Step& st : plan.steps) t += step_cost_model(st.rA, st.rB, st.s, st.rC);
+    for (const Step& st : plan.steps)
+        t += planes * step_cost_model(st.rA, st.rB, st.s, st.rC, mode) + launches * kLaunchUs;
     return t;
 }
 
