@@ -27,10 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the matrix-core kernel from rocprofv3 byte counters
-# (FETCH_SIZE and WRITE_SIZE runs of this benchmark, scaled by a plain copy
-# of known size); used only while the kernel source is the one measured
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mfma_cvc200_batch16_traffic.txt")
+# HBM bytes per launch of the matrix-core kernels (small-modulus residues)
+# from rocprofv3 byte counters (FETCH_SIZE and WRITE_SIZE runs of this
+# benchmark, scaled by a plain copy of known size); used only while the kernel
+# source is the one measured
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mfma8_cvc200_batch16_traffic.txt")
 INT8_PEAK_TOPS = 5000.0   # dense int8 MFMA, MI355X
 # int8 products per multiply-add modulo one modulus: 4 digit pairs for the
 # 16-bit primes, 1 for small moduli (centred int8 residues); an int8 op is a
@@ -69,7 +70,8 @@ def roofline_of(name, d, mode="small"):
     if name == "mfma":
         tops = d["macs"] * 2 * INT8_PRODUCTS_PER_MODMAC[mode] / sec / 1e12 if sec > 0 else 0.0
         per.update({"bound": "mfma", "achieved": round(tops, 2), "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                    "frac": round(tops / INT8_PEAK_TOPS, 4), "traffic": measured_traffic(),
+                    "frac": round(tops / INT8_PEAK_TOPS, 4),
+                    "traffic": measured_traffic() if mode == "small" else None,
                     "algorithmic_modmacs_per_launch": d["macs"] / max(1, d["launches"]),
                     "achieved_modmacs_per_s": d["macs"] / sec if sec > 0 else 0.0})
     else:
