@@ -55,11 +55,16 @@ constexpr int k8MaxRowBytesLog = 25;       // 127 rows of a stage within 32-bit 
 // indices differing in the lowest bit) swap halves and each stores 4
 // consecutive bytes, the even lane those of v < 2 and the odd lane those of
 // v >= 2; sel are the byte selectors of that swap (even, odd lane); mode 2:
-// single bytes.
+// single bytes. In modes 0 and 1, C's bits 2 and 3 then belong to lane bits
+// x2 and x3 (B indices' four lowest bits are lane bits 0..3, A indices'
+// bits 2 and 3 lane bits 4 and 5, and in mode 1 lane bit 0 stands for A's
+// bit 1): exchanging those with two bits of the block index leaves 16
+// consecutive bytes of C in each lane (x2 = -1: 4-byte stores).
 struct Mfma8Extra {
     uint64_t dA[8], dV[4], dB[4];
     uint32_t sel[2];
-    int32_t mode;
+    int32_t mode, x2, x3;
+    int32_t form;  // 16-byte store variant (store_tile8), 0: none
 };
 
 // Centred residue of an exact int32 sum modulo m <= 255, returned as the low
@@ -84,35 +89,98 @@ __device__ __forceinline__ uint32_t pack4(uint32_t t0, uint32_t t1, uint32_t t2,
     return __builtin_amdgcn_perm(hi, lo, 0x05040100u);
 }
 
+// Exchange lane bit k with the index of a pair of words: afterwards the lane
+// with bit k = t holds in x (y) the word the lane with bit k = 0 (1) held in
+// its word t. P = 4 or 5: lane bit 4 or 5, one permlane swap; P = 0: lane
+// bit k < 4 (run-time), a cross-lane read (ds_bpermute) and selects.
+template <int P>
+__device__ __forceinline__ void lane_swap(uint32_t& x, uint32_t& y, int k, int lane) {
+    if constexpr (P == 4 || P == 5) {
+        const auto r = P == 4 ? __builtin_amdgcn_permlane16_swap(x, y, false, false)
+                              : __builtin_amdgcn_permlane32_swap(x, y, false, false);
+        x = r[0];
+        y = r[1];
+    } else {
+        const bool hi = (lane >> k) & 1;
+        const int send = int(hi ? x : y);
+        const int recv = __builtin_amdgcn_ds_bpermute((lane ^ (1 << k)) << 2, send);
+        x = hi ? uint32_t(recv) : x;
+        y = hi ? y : uint32_t(recv);
+    }
+}
+
+// The lane's word of block (rb, cb) (see Mfma8Extra): four reduced outputs
+// packed; with PAIR, half exchanged with the neighbour lane.
+template <int RA, int CB, bool FOLD, bool PAIR>
+__device__ __forceinline__ uint32_t out_word(const v4i (&acc)[RA][CB], int rb, int cb, const ModSmall& ms,
+                                             uint32_t sel) {
+    const float mf = float(ms.m);
+    const int32_t r16 = int32_t(ms.r16);
+    const uint32_t x =
+        pack4(res8<FOLD>(acc[rb][cb][0], r16, mf, ms.inv), res8<FOLD>(acc[rb][cb][1], r16, mf, ms.inv),
+              res8<FOLD>(acc[rb][cb][2], r16, mf, ms.inv), res8<FOLD>(acc[rb][cb][3], r16, mf, ms.inv));
+    if constexpr (!PAIR) return x;
+    // the neighbour lane's word (quad permutation 1, 0, 3, 2)
+    const uint32_t y = uint32_t(__builtin_amdgcn_mov_dpp(int(x), 0xb1, 0xf, 0xf, false));
+    return __builtin_amdgcn_perm(x, y, sel);
+}
+
+// 16-byte stores: blocks b = rb + RA cb in groups of four (block bits 0 and
+// 1) exchange those bits with lane bits x2 and x3 (forms P2, P3 of
+// lane_swap); afterwards word t of a group is C's bytes 4t..4t+3 of the
+// lane's 16.
+template <int RA, int CB, bool FOLD, bool PAIR, int P2, int P3>
+__device__ __forceinline__ void store16(const v4i (&acc)[RA][CB], int8_t* C, uint64_t baseC, const Mfma8Extra& ex,
+                                        const ModSmall& ms, int lane) {
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    const uint32_t sel = ex.sel[lane & 1];
+#pragma unroll
+    for (int g = 0; g < RA * CB; g += 4) {
+        uint32_t w[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) w[t] = out_word<RA, CB, FOLD, PAIR>(acc, (g + t) % RA, (g + t) / RA, ms, sel);
+        lane_swap<P2>(w[0], w[1], ex.x2, lane);
+        lane_swap<P2>(w[2], w[3], ex.x2, lane);
+        lane_swap<P3>(w[0], w[2], ex.x3, lane);
+        lane_swap<P3>(w[1], w[3], ex.x3, lane);
+        uint64_t row = baseC | ex.dA[g % RA];
+        __asm__ volatile("" : "+v"(row));
+        *reinterpret_cast<u4*>(C + (row | ex.dB[g / RA])) = u4{w[0], w[1], w[2], w[3]};
+    }
+}
+
 // Store a wave's outputs of one tile: lane (fr, q) holds acc[rb][cb][v] for
 // A index 16 rb + 4 q + v and B index 16 cb + fr (plus the wave's offsets);
 // baseC is the C offset of the lane's first stored byte (tile, wave and lane
-// parts, see Mfma8Extra for the modes).
+// parts, see Mfma8Extra for the modes; form selects the 16-byte variant).
+// (Row offsets pass through an empty asm statement so that the compiler does
+// not precompute all RA x CB table combinations in scalar registers, which
+// would spill.)
 template <int RA, int CB, bool FOLD>
 __device__ __forceinline__ void store_tile8(const v4i (&acc)[RA][CB], int8_t* C, uint64_t baseC, const Mfma8Extra& ex,
                                             const ModSmall& ms, int lane) {
-    const float mf = float(ms.m);
-    const int32_t r16 = int32_t(ms.r16);
-    // (the row offset passes through an empty asm statement so that the
-    // compiler does not precompute all RA x CB table combinations in
-    // scalar registers, which would spill)
+    switch (ex.form) {
+        case 1: return store16<RA, CB, FOLD, false, 4, 5>(acc, C, baseC, ex, ms, lane);
+        case 2: return store16<RA, CB, FOLD, false, 4, 0>(acc, C, baseC, ex, ms, lane);
+        case 3: return store16<RA, CB, FOLD, false, 0, 4>(acc, C, baseC, ex, ms, lane);
+        case 4: return store16<RA, CB, FOLD, false, 0, 0>(acc, C, baseC, ex, ms, lane);
+        case 5: return store16<RA, CB, FOLD, true, 0, 4>(acc, C, baseC, ex, ms, lane);
+        case 6: return store16<RA, CB, FOLD, true, 0, 0>(acc, C, baseC, ex, ms, lane);
+        default: break;
+    }
+    const uint32_t sel = ex.sel[lane & 1];
     if (ex.mode != 2) {
-        const uint32_t sel = ex.sel[lane & 1];
 #pragma unroll
         for (int rb = 0; rb < RA; ++rb) {
             uint64_t row = baseC | ex.dA[rb];
             __asm__ volatile("" : "+v"(row));
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                const uint32_t x =
-                    pack4(res8<FOLD>(acc[rb][cb][0], r16, mf, ms.inv), res8<FOLD>(acc[rb][cb][1], r16, mf, ms.inv),
-                          res8<FOLD>(acc[rb][cb][2], r16, mf, ms.inv), res8<FOLD>(acc[rb][cb][3], r16, mf, ms.inv));
-                // the neighbour lane's word (quad permutation 1, 0, 3, 2)
-                const uint32_t y = uint32_t(__builtin_amdgcn_mov_dpp(int(x), 0xb1, 0xf, 0xf, false));
-                *reinterpret_cast<uint32_t*>(C + (row | ex.dB[cb])) = __builtin_amdgcn_perm(x, y, sel);
-            }
+            for (int cb = 0; cb < CB; ++cb)
+                *reinterpret_cast<uint32_t*>(C + (row | ex.dB[cb])) = out_word<RA, CB, FOLD, true>(acc, rb, cb, ms, sel);
         }
     } else {
+        const float mf = float(ms.m);
+        const int32_t r16 = int32_t(ms.r16);
 #pragma unroll
         for (int rb = 0; rb < RA; ++rb) {
             uint64_t row = baseC | ex.dA[rb];
@@ -128,12 +196,26 @@ __device__ __forceinline__ void store_tile8(const v4i (&acc)[RA][CB], int8_t* C,
 
 // Lane part of the C offset of the lane's first stored byte (see Mfma8Extra):
 // A index wr + 4 q, B index wc + fr; in mode 1 the lane stores the outputs of
-// B index wc + (fr & ~1) and A indices wr + 4 q + 2 (fr & 1) + {0, 1}.
-__device__ __forceinline__ uint64_t lane_offset8(const StepArgs& a, const Mfma8Extra& ex, int wr, int wc, int fr,
-                                                 int q) {
-    if (ex.mode == 1)
-        return pdep64(uint64_t(wr + 4 * q + 2 * (fr & 1)), a.maskA) | pdep64(uint64_t(wc + (fr & ~1)), a.maskB);
-    return pdep64(uint64_t(wr + 4 * q), a.maskA) | pdep64(uint64_t(wc + fr), a.maskB);
+// B index wc + (fr & ~1) and A indices wr + 4 q + 2 (fr & 1) + {0, 1}; with
+// 16-byte stores lane bits x2 and x3 stand for block bits 0 and 1 instead
+// (rb's bit 0, and rb's bit 1 or, with RA = 2, cb's bit 0).
+template <int RA>
+__device__ __forceinline__ uint64_t lane_offset8(const StepArgs& a, const Mfma8Extra& ex, int wr, int wc, int lane) {
+    uint32_t ai = uint32_t(wr), bi = uint32_t(wc);
+    for (int k = 0; k < 6; ++k) {
+        if (!((lane >> k) & 1)) continue;
+        if (ex.mode != 2 && k == ex.x2)
+            ai += 16;
+        else if (ex.mode != 2 && k == ex.x3)
+            (RA >= 4 ? ai : bi) += RA >= 4 ? 32 : 16;
+        else if (k >= 4)
+            ai += 4u << (k - 4);
+        else if (k == 0 && ex.mode == 1)
+            ai += 2;
+        else
+            bi += 1u << k;
+    }
+    return pdep64(ai, a.maskA) | pdep64(bi, a.maskB);
 }
 
 constexpr int lg2(int x) { return x <= 1 ? 0 : 1 + lg2(x / 2); }
@@ -189,7 +271,7 @@ __global__ __launch_bounds__(G::THREADS, 1) void k_mfma8(StepArgs a, Mfma8Extra 
     // lane part of the output offset, kept in LDS: the epilogue reads it
     // once per tile, and in registers through the K loop it would only add
     // pressure
-    lconst[tid] = lane_offset8(a, ex, wr, wc, fr, q);
+    lconst[tid] = lane_offset8<RA>(a, ex, wr, wc, lane);
     // loads: lane l of wave w, instruction i fills physical slot l % 4 of
     // stage row GROUP i + 16 w + l / 4, i.e. logical slot (l % 4) ^ (l / 16):
     // bytes 16 ((l % 4) ^ (l / 16)).. of that row's chunk
@@ -411,7 +493,7 @@ __global__ __launch_bounds__(G::THREADS) void k_mfma8_short(StepArgs a, Mfma8Ext
     const int lgA = a.fA - G::LGM, lgB = a.fB - G::LGN;
     const uint32_t T = 1u << (lgA + lgB);
     const int fr = lane & 15, q = lane >> 4;
-    const uint64_t lc = lane_offset8(a, ex, wr, wc, fr, q);
+    const uint64_t lc = lane_offset8<RA>(a, ex, wr, wc, lane);
     // lane's fragment offset within a tile's rows: row wr + fr (A) or
     // wc + fr (B), K offset 8 q
     const uint32_t offA = uint32_t((wr + fr) * K + 8 * q), offB = uint32_t((wc + fr) * K + 8 * q);
@@ -487,6 +569,38 @@ Mfma8Extra extra_of(const StepArgs& a) {
     } else {
         ex.mode = 2;
     }
+    // lane bit holding C bit pos (modes 0 and 1), -1 if none
+    auto lane_bit_of = [&](int pos) -> int {
+        const bool fromA = (a.maskA >> pos) & 1;
+        const int idx = __builtin_popcountll((fromA ? a.maskA : a.maskB) & ((uint64_t(1) << pos) - 1));
+        if (fromA) {
+            if (idx == 2 || idx == 3) return 4 + (idx - 2);
+            return idx == 1 && ex.mode == 1 ? 0 : -1;
+        }
+        if (idx >= 1 && idx <= 3) return idx;
+        return idx == 0 && ex.mode == 0 ? 0 : -1;
+    };
+    ex.x2 = ex.x3 = -1;
+    if (ex.mode != 2) {
+        const int b2 = lane_bit_of(2), b3 = lane_bit_of(3);
+        if (b2 >= 0 && b3 >= 0 && b2 != b3) {
+            ex.x2 = b2;
+            ex.x3 = b3;
+        }
+    }
+    // the compiled 16-byte variants: (pair exchange, lane bit of C bit 2, of
+    // C bit 3) with bits 4 and 5 by permlane swaps and 0..3 at run time
+    const int c2 = ex.x2 >= 4 ? ex.x2 : 0, c3 = ex.x3 >= 4 ? ex.x3 : 0;
+    ex.form = 0;
+    if (ex.x2 >= 0) {
+        if (ex.mode == 0 && c2 == 4 && c3 == 5) ex.form = 1;
+        else if (ex.mode == 0 && c2 == 4 && c3 == 0) ex.form = 2;
+        else if (ex.mode == 0 && c2 == 0 && c3 == 4) ex.form = 3;
+        else if (ex.mode == 0 && c2 == 0 && c3 == 0) ex.form = 4;
+        else if (ex.mode == 1 && c2 == 0 && c3 == 4) ex.form = 5;
+        else if (ex.mode == 1 && c2 == 0 && c3 == 0) ex.form = 6;
+    }
+    if (ex.form == 0) ex.x2 = ex.x3 = -1;  // the lane offsets of 4-byte stores
     return ex;
 }
 

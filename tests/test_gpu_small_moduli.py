@@ -191,3 +191,36 @@ def test_batch_wide_rns():
     _say("batch of 24 with 16-bit primes")
     got = tn.count_batch(fs, "best", seed=0, flags=tn.FLAG_WIDE_RNS, workspace_bytes_=8 << 30)
     assert got == [g[i] for i in sorted(g)][:24]
+
+
+def _layout_mask(rC, fA, layout, rng):
+    # C's lowest bits owned as in layout ("A"/"B" per bit), the rest random
+    low = [q for q, c in enumerate(layout) if c == "A"]
+    rest = [q for q in range(len(layout), rC)]
+    nA = fA - len(low)
+    pick = rng.choice(len(rest), size=nA, replace=False)
+    m = 0
+    for q in low + [rest[int(i)] for i in pick]:
+        m |= 1 << q
+    return m
+
+
+# Owners of C's four lowest bits select the epilogue's store form: 16-byte
+# stores after exchanging lane bits 0, 1, 2, 4 or 5 with block bits, 4-byte
+# words, or bytes (B owns C's two lowest bits).
+LAYOUTS = ["AAAA", "BAAB", "BAAA", "AABB", "BBAA", "AAAB", "ABAA", "BABA", "ABAB", "ABBA", "BABB", "ABBB", "BBBB"]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("rA,rB,s", [(14, 14, 7), (14, 14, 6), (14, 12, 6), (13, 12, 5)])
+def test_mfma8_output_layouts(layout, rA, rB, s):
+    rng = np.random.default_rng(sum(ord(c) << (2 * i) for i, c in enumerate(layout)) * 1000 + rA * 100 + rB * 10 + s)
+    rC = rA + rB - 2 * s
+    maskA = _layout_mask(rC, rA - s, layout, rng)
+    m = 251
+    A = rng.integers(0, m, size=1 << rA).astype(np.uint32)
+    B = rng.integers(0, m, size=1 << rB).astype(np.uint32)
+    _say(f"layout={layout} rA={rA} rB={rB} s={s} mask={maskA:#x}")
+    C = tn.step(A.copy(), rA, B.copy(), rB, s, maskA, prime=m, kernel="mfma")
+    cs = sorted(set(rng.integers(0, 1 << rC, size=3000).tolist()) | set(range(64)) | {(1 << rC) - 1})
+    assert [int(C[c]) for c in cs] == contract.step_entries(A, B, s, maskA, rC, cs, m)
