@@ -172,7 +172,24 @@ __global__ __launch_bounds__(256) void k_rowdot(StepArgs a) {
             if (lane == 0) C[c] = acc;
         } else if constexpr (E == EL_I8) {
             int64_t acc = 0;
-            for (uint64_t z = lane; z < K; z += 64) acc += int32_t(ra[z]) * int32_t(rb[z]);
+            if (K >= 1024) {
+                // 16 bytes per lane and iteration (rows start 64-byte
+                // aligned), four 4-way int8 dot products; a chunk's sum is at
+                // most 16 127^2 < 2^18, widened once per chunk
+                typedef int v4i_t __attribute__((ext_vector_type(4)));
+                const v4i_t* va = reinterpret_cast<const v4i_t*>(ra);
+                const v4i_t* vb = reinterpret_cast<const v4i_t*>(rb);
+                for (uint64_t z = lane; z < K / 16; z += 64) {
+                    const v4i_t x = va[z], y = vb[z];
+                    int d = __builtin_amdgcn_sdot4(x[0], y[0], 0, false);
+                    d = __builtin_amdgcn_sdot4(x[1], y[1], d, false);
+                    d = __builtin_amdgcn_sdot4(x[2], y[2], d, false);
+                    d = __builtin_amdgcn_sdot4(x[3], y[3], d, false);
+                    acc += d;
+                }
+            } else {
+                for (uint64_t z = lane; z < K; z += 64) acc += int32_t(ra[z]) * int32_t(rb[z]);
+            }
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
             if (lane == 0) C[c] = T(ms.center64(acc));
         } else {

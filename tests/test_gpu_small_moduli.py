@@ -64,6 +64,8 @@ ELEMENT = [
     ("generic", 5, 4, 2), ("generic", 9, 7, 3), ("generic", 6, 0, 0),
     ("stream", 14, 5, 3), ("stream", 12, 3, 1), ("stream", 10, 2, 0),
     ("rowdot", 12, 10, 8), ("rowdot", 9, 9, 9), ("rowdot", 14, 8, 7),
+    # K >= 2^10: 16 bytes per lane and 4-way int8 dot products
+    ("rowdot", 14, 12, 10), ("rowdot", 16, 13, 12), ("rowdot", 19, 14, 14), ("rowdot", 22, 15, 12),
     ("dot", 14, 14, 14), ("dot", 16, 15, 13),
     ("auto", 16, 15, 9), ("auto", 12, 3, 1), ("auto", 18, 18, 16),
 ]
@@ -101,7 +103,8 @@ def test_even_modulus(kernel, rA, rB, s):
 
 @pytest.mark.parametrize("kind", ["plus", "mixed", "raw"])
 @pytest.mark.parametrize("kernel,rA,rB,s", [("mfma", 17, 17, 9), ("mfma", 22, 21, 12), ("mfma", 23, 23, 16),
-                                            ("stream", 13, 7, 5), ("rowdot", 12, 10, 8), ("dot", 16, 15, 13),
+                                            ("stream", 13, 7, 5), ("rowdot", 12, 10, 8), ("rowdot", 16, 13, 12),
+                                            ("dot", 16, 15, 13),
                                             ("generic", 9, 7, 3)])
 def test_small_modulus_extreme_residues(kernel, rA, rB, s, kind):
     _check(rA, rB, s, kernel, 255, seed=7, kind=kind, samples=1500)
