@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <unordered_map>
 
 #include "graph.hpp"
 #include "internal.hpp"
@@ -23,19 +24,44 @@
 
 namespace tn {
 
-void pair_features(const LiveGraph& g, int32_t u, int32_t v, float* f) {
-    int32_t ru = g.rank[u], rv = g.rank[v];
-    int32_t du = int32_t(g.nb[u].size()), dv = int32_t(g.nb[v].size());
-    if (rv > ru || (rv == ru && dv > du)) {
-        std::swap(ru, rv);
-        std::swap(du, dv);
+namespace {
+
+// The integers the features are made of (the larger tensor first).
+struct PairInts {
+    int32_t ru, rv, s, du, dv, common;
+};
+
+// Common neighbours are counted against a stamp array (one entry per
+// tensor id, epoch-marked) when one is given, else by search.
+struct Stamps {
+    std::vector<uint32_t> mark;
+    uint32_t epoch = 0;
+};
+
+PairInts pair_ints(const LiveGraph& g, int32_t u, int32_t v, Stamps* st = nullptr) {
+    PairInts p{g.rank[u], g.rank[v], 0, int32_t(g.nb[u].size()), int32_t(g.nb[v].size()), 0};
+    if (p.rv > p.ru || (p.rv == p.ru && p.dv > p.du)) {
+        std::swap(p.ru, p.rv);
+        std::swap(p.du, p.dv);
         std::swap(u, v);
     }
-    const int32_t s = g.shared(u, v);
+    p.s = g.shared(u, v);
+    if (st) {
+        if (st->mark.size() < g.nb.size()) st->mark.resize(g.nb.size(), 0);
+        const uint32_t e = ++st->epoch;
+        for (const auto& b : g.nb[v]) st->mark[size_t(b.first)] = e;
+        for (const auto& a : g.nb[u])
+            if (a.first != v && st->mark[size_t(a.first)] == e) ++p.common;
+    } else {
+        for (const auto& a : g.nb[u])
+            if (a.first != v && g.shared(v, a.first) > 0) ++p.common;
+    }
+    return p;
+}
+
+void features_of(const PairInts& p, float* f) {
+    const int32_t ru = p.ru, rv = p.rv, s = p.s, du = p.du, dv = p.dv, common = p.common;
     const int32_t rc = ru + rv - 2 * s;
-    int32_t common = 0;
-    for (const auto& a : g.nb[u])
-        if (a.first != v && g.shared(v, a.first) > 0) ++common;
     f[0] = ru / 32.0f;
     f[1] = rv / 32.0f;
     f[2] = s / 32.0f;
@@ -47,6 +73,21 @@ void pair_features(const LiveGraph& g, int32_t u, int32_t v, float* f) {
     f[8] = (ru + rv - s) / 48.0f;
     f[9] = (s == rv) ? 1.0f : 0.0f;
 }
+
+// The six integers in 10 bits each, or ~0 when one does not fit.
+uint64_t pair_key(const PairInts& p) {
+    const int32_t v[6] = {p.ru, p.rv, p.s, p.du, p.dv, p.common};
+    uint64_t k = 0;
+    for (int i = 0; i < 6; ++i) {
+        if (v[i] < 0 || v[i] > 1023) return ~uint64_t(0);
+        k = (k << 10) | uint64_t(v[i]);
+    }
+    return k;
+}
+
+}  // namespace
+
+void pair_features(const LiveGraph& g, int32_t u, int32_t v, float* f) { features_of(pair_ints(g, u, v), f); }
 
 // Host forward pass, float32, the same arithmetic as the GPU kernels:
 // h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = w3 . h2 + b3. The
@@ -96,20 +137,35 @@ std::vector<std::pair<int32_t, int32_t>> order_learned(const Network& net, const
     transpose_params(P, w1t, w2t);
     LiveGraph g;
     g.init(net);
-    // scores of live candidate pairs, keyed by (lo, hi)
+    // The score is a function of six small integers, and the same local
+    // configurations recur throughout a network: scores are kept by those
+    // integers (the same floats as computing them again).
+    std::unordered_map<uint64_t, float> memo;
+    memo.reserve(4096);
+    Stamps stamps;
+    float f[kFeatures];
+    auto score_pair = [&](int32_t u, int32_t v) {
+        const PairInts p = pair_ints(g, u, v, &stamps);
+        const uint64_t key = pair_key(p);
+        if (key != ~uint64_t(0)) {
+            const auto it = memo.find(key);
+            if (it != memo.end()) return it->second;
+        }
+        features_of(p, f);
+        const float y = mlp_score_t(P, w1t.data(), w2t.data(), f);
+        if (key != ~uint64_t(0)) memo.emplace(key, y);
+        return y;
+    };
+    // scores of live candidate pairs
     struct Cand {
         int32_t u, v;
         float score;
     };
-    std::vector<Cand> cands;
-    float f[kFeatures];
-    auto score_pair = [&](int32_t u, int32_t v) {
-        pair_features(g, u, v, f);
-        return mlp_score_t(P, w1t.data(), w2t.data(), f);
-    };
+    std::vector<Cand> cands, keep;
     for (int32_t u = 0; u < int32_t(g.nb.size()); ++u)
         for (const auto& pr : g.nb[u])
             if (u < pr.first) cands.push_back({u, pr.first, score_pair(u, pr.first)});
+    std::vector<char> touched;
     while (!cands.empty()) {
         size_t best = 0;
         for (size_t i = 1; i < cands.size(); ++i) {
@@ -121,26 +177,27 @@ std::vector<std::pair<int32_t, int32_t>> order_learned(const Network& net, const
         const int32_t c = g.merge(u, v);
         merges.push_back({u, v});
         // drop pairs touching u or v; re-score pairs touching c's neighbourhood
-        std::vector<char> touched(g.alive.size(), 0);
-        touched[c] = 1;
-        for (const auto& pr : g.nb[c]) touched[pr.first] = 1;
-        std::vector<Cand> keep;
-        keep.reserve(cands.size());
+        touched.assign(g.alive.size(), 0);
+        touched[size_t(c)] = 1;
+        for (const auto& pr : g.nb[size_t(c)]) touched[size_t(pr.first)] = 1;
+        keep.clear();
         for (const Cand& x : cands) {
             if (x.u == u || x.v == u || x.u == v || x.v == v) continue;
-            if (touched[x.u] || touched[x.v]) continue;  // re-scored below
+            if (touched[size_t(x.u)] || touched[size_t(x.v)]) continue;  // re-scored below
             keep.push_back(x);
         }
         cands.swap(keep);
         // every live pair with an endpoint in N(c) u {c}
-        for (int32_t x = 0; x < int32_t(g.alive.size()); ++x) {
-            if (!touched[x] || !g.alive[x]) continue;
-            for (const auto& pr : g.nb[x]) {
+        auto rescore_from = [&](int32_t x) {
+            for (const auto& pr : g.nb[size_t(x)]) {
                 const int32_t y = pr.first;
-                if (touched[y] && y < x) continue;  // counted from y's side
+                if (touched[size_t(y)] && y < x) continue;  // counted from y's side
                 cands.push_back({std::min(x, y), std::max(x, y), score_pair(x, y)});
             }
-        }
+        };
+        rescore_from(c);
+        for (const auto& pr : g.nb[size_t(c)])
+            if (g.alive[size_t(pr.first)]) rescore_from(pr.first);
     }
     g.close_scalars(merges);
     *ok = true;
