@@ -68,19 +68,20 @@ struct Mfma8Extra {
 };
 
 // Centred residue of an exact int32 sum modulo m <= 255, returned as the low
-// byte of a float's bit pattern. With FOLD, x = h 2^16 + l becomes
-// y = h (2^16 mod m) + l; else |x| < 2^21 already (K <= 128). Then
-// |y| < 2^15 (m - 1) + 2^16, exact in single precision, q = rint(y / m) with
-// the quotient's rounding error below 2^-23 |y|, and y - q m, exact by one
-// fma, lies within m/2 + 1 of zero: |r| <= 127 for every m <= 255. Adding
-// 1.5 2^23 leaves r in the low mantissa bits in two's complement.
+// byte of a word. With FOLD, x = h 2^16 + l becomes y = h (2^16 mod m) + l;
+// else |x| < 2^21 already (K <= 128). Then |y| < 2^15 (m - 1) + 2^16 < 2^23,
+// exact in single precision, and one fma adds f / m to 1.5 2^23, which rounds
+// the exact product to the nearest integer q (ties to even) into the low
+// mantissa bits: the word's low 24 bits read as a signed 24-bit integer are
+// 2^22 + q. One 24-bit multiply-add gives y - m (2^22 + q) = r - 2^22 m with
+// r = y - q m, whose low byte is r's since 256 divides 2^22 m; |r| <= 127 for
+// every m <= 255 (checked exhaustively over the range of y), so that byte is
+// r in two's complement.
 template <bool FOLD>
-__device__ __forceinline__ uint32_t res8(int32_t x, int32_t r16, float mf, float inv) {
+__device__ __forceinline__ uint32_t res8(int32_t x, int32_t r16, int32_t negm, float inv) {
     const int32_t y = FOLD ? (x >> 16) * r16 + (x & 0xffff) : x;
-    const float f = float(y);
-    const float q = __builtin_rintf(f * inv);
-    const float r = __builtin_fmaf(-q, mf, f);
-    return __float_as_uint(r + 12582912.0f);
+    const float u = __builtin_fmaf(float(y), inv, 12582912.0f);
+    return uint32_t(__mul24(int32_t(__float_as_uint(u)), negm) + y);
 }
 
 // The low bytes of four words, packed (word 0 in byte 0).
@@ -114,11 +115,11 @@ __device__ __forceinline__ void lane_swap(uint32_t& x, uint32_t& y, int k, int l
 template <int RA, int CB, bool FOLD, bool PAIR>
 __device__ __forceinline__ uint32_t out_word(const v4i (&acc)[RA][CB], int rb, int cb, const ModSmall& ms,
                                              uint32_t sel) {
-    const float mf = float(ms.m);
+    const int32_t negm = -int32_t(ms.m);
     const int32_t r16 = int32_t(ms.r16);
     const uint32_t x =
-        pack4(res8<FOLD>(acc[rb][cb][0], r16, mf, ms.inv), res8<FOLD>(acc[rb][cb][1], r16, mf, ms.inv),
-              res8<FOLD>(acc[rb][cb][2], r16, mf, ms.inv), res8<FOLD>(acc[rb][cb][3], r16, mf, ms.inv));
+        pack4(res8<FOLD>(acc[rb][cb][0], r16, negm, ms.inv), res8<FOLD>(acc[rb][cb][1], r16, negm, ms.inv),
+              res8<FOLD>(acc[rb][cb][2], r16, negm, ms.inv), res8<FOLD>(acc[rb][cb][3], r16, negm, ms.inv));
     if constexpr (!PAIR) return x;
     // the neighbour lane's word (quad permutation 1, 0, 3, 2)
     const uint32_t y = uint32_t(__builtin_amdgcn_mov_dpp(int(x), 0xb1, 0xf, 0xf, false));
@@ -179,7 +180,7 @@ __device__ __forceinline__ void store_tile8(const v4i (&acc)[RA][CB], int8_t* C,
                 *reinterpret_cast<uint32_t*>(C + (row | ex.dB[cb])) = out_word<RA, CB, FOLD, true>(acc, rb, cb, ms, sel);
         }
     } else {
-        const float mf = float(ms.m);
+        const int32_t negm = -int32_t(ms.m);
         const int32_t r16 = int32_t(ms.r16);
 #pragma unroll
         for (int rb = 0; rb < RA; ++rb) {
@@ -189,7 +190,7 @@ __device__ __forceinline__ void store_tile8(const v4i (&acc)[RA][CB], int8_t* C,
             for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    C[row | ex.dV[v] | ex.dB[cb]] = int8_t(res8<FOLD>(acc[rb][cb][v], r16, mf, ms.inv));
+                    C[row | ex.dV[v] | ex.dB[cb]] = int8_t(res8<FOLD>(acc[rb][cb][v], r16, negm, ms.inv));
         }
     }
 }
@@ -416,11 +417,11 @@ __global__ __launch_bounds__(G::THREADS, 1) void k_mfma8(StepArgs a, Mfma8Extra 
         // epilogue: lane holds A index wr + 16 rb + 4 q + v, B index
         // wc + 16 cb + fr of each 16x16 block
         constexpr bool FOLD = NK >= 4;
-        const float mf = float(ms.m);
+        const int32_t negm = -int32_t(ms.m);
         const int32_t r16 = int32_t(ms.r16);
         auto packed = [&](int rb, int cb) {
-            return pack4(res8<FOLD>(acc[rb][cb][0], r16, mf, ms.inv), res8<FOLD>(acc[rb][cb][1], r16, mf, ms.inv),
-                         res8<FOLD>(acc[rb][cb][2], r16, mf, ms.inv), res8<FOLD>(acc[rb][cb][3], r16, mf, ms.inv));
+            return pack4(res8<FOLD>(acc[rb][cb][0], r16, negm, ms.inv), res8<FOLD>(acc[rb][cb][1], r16, negm, ms.inv),
+                         res8<FOLD>(acc[rb][cb][2], r16, negm, ms.inv), res8<FOLD>(acc[rb][cb][3], r16, negm, ms.inv));
         };
         if (splits > 1) {
             // partial residues of this K range, tile-local order (j, i): the
