@@ -68,8 +68,9 @@ struct Mfma8Extra {
 };
 
 // Centred residue of an exact int32 sum modulo m <= 255, returned as the low
-// byte of a word. With FOLD, x = h 2^16 + l becomes y = h (2^16 mod m) + l;
-// else |x| < 2^21 already (K <= 128). Then |y| < 2^15 (m - 1) + 2^16 < 2^23,
+// byte of a word. With FOLD, x = h 2^16 + l becomes y = h (2^16 mod m) + l,
+// |y| < 2^15 (m - 1) + 2^16; else K <= 512 and |y| = |x| <= 512 127^2. Either
+// way |y| < 2^23,
 // exact in single precision, and one fma adds f / m to 1.5 2^23, which rounds
 // the exact product to the nearest integer q (ties to even) into the low
 // mantissa bits: the word's low 24 bits read as a signed 24-bit integer are
@@ -245,7 +246,8 @@ using Cfg128x64 = Cfg<128, 64, 4, 2, 4>;
 // the work-groups, K split over blockIdx.y into `splits` ranges (partial
 // residues to `part` when splits > 1), residue planes over blockIdx.z.
 // NK: 1 or 2 stages per tile and block row, or 4 for any power of two >= 4.
-template <class G, int NK>
+// FOLD: the sums exceed 8 stages, so the epilogue folds them at 2^16 first.
+template <class G, int NK, bool FOLD>
 __global__ __launch_bounds__(G::THREADS, 1) void k_mfma8(StepArgs a, Mfma8Extra ex, int splits, int8_t* part,
                                                          int64_t part_stride) {
     constexpr int RA = G::RA, CB = G::CB;
@@ -416,7 +418,6 @@ __global__ __launch_bounds__(G::THREADS, 1) void k_mfma8(StepArgs a, Mfma8Extra 
 
         // epilogue: lane holds A index wr + 16 rb + 4 q + v, B index
         // wc + 16 cb + fr of each 16x16 block
-        constexpr bool FOLD = NK >= 4;
         const int32_t negm = -int32_t(ms.m);
         const int32_t r16 = int32_t(ms.r16);
         auto packed = [&](int rb, int cb) {
@@ -620,14 +621,18 @@ hipError_t launch_cfg(const StepArgs& a, int G, hipStream_t stream, char* scratc
     int8_t* part = reinterpret_cast<int8_t*>(scratch);
     dim3 grid(uint32_t(std::min<uint64_t>(T, 1024)), uint32_t(splits), G);
     const int per = nk / splits;
-    if (per >= 4)
-        hipLaunchKernelGGL((k_mfma8<Gm, 4>), grid, dim3(Gm::THREADS), 0, stream, a, ex, splits, part,
+    // sums of at most 8 stages stay below 8 64 127^2 < 2^23: no fold
+    if (per > 8)
+        hipLaunchKernelGGL((k_mfma8<Gm, 4, true>), grid, dim3(Gm::THREADS), 0, stream, a, ex, splits, part,
+                           scratch_per_plane);
+    else if (per >= 4)
+        hipLaunchKernelGGL((k_mfma8<Gm, 4, false>), grid, dim3(Gm::THREADS), 0, stream, a, ex, splits, part,
                            scratch_per_plane);
     else if (per == 2)
-        hipLaunchKernelGGL((k_mfma8<Gm, 2>), grid, dim3(Gm::THREADS), 0, stream, a, ex, splits, part,
+        hipLaunchKernelGGL((k_mfma8<Gm, 2, false>), grid, dim3(Gm::THREADS), 0, stream, a, ex, splits, part,
                            scratch_per_plane);
     else
-        hipLaunchKernelGGL((k_mfma8<Gm, 1>), grid, dim3(Gm::THREADS), 0, stream, a, ex, splits, part,
+        hipLaunchKernelGGL((k_mfma8<Gm, 1, false>), grid, dim3(Gm::THREADS), 0, stream, a, ex, splits, part,
                            scratch_per_plane);
     if (splits > 1) {
         const uint64_t n = T * uint64_t(Gm::WM * Gm::WN);

@@ -1,8 +1,8 @@
 """The matrix-core epilogue's residue reduction, emulated on the CPU.
 
 The int8 kernels reduce an exact int32 sum x modulo m <= 255 to a centred
-residue in three vector instructions (after an optional fold of x at 2^16):
-u = fma(float(y), fl(1/m), 1.5 2^23), then a signed 24-bit multiply-add of u's
+residue in three vector instructions (after a fold of x at 2^16 when x sums
+more than 8 stages of 64 products): u = fma(float(y), fl(1/m), 1.5 2^23), then a signed 24-bit multiply-add of u's
 low 24 bits with -m, plus y. The stored byte is the low byte of that word.
 This checks, for every m in 2..255, that the byte is the two's complement of
 a residue r of y with |r| <= 127, on every y where the quotient's rounding can
@@ -33,9 +33,10 @@ def reduce_byte(y, m):
 
 
 def ranges(m):
-    """The ranges of y: no fold (K <= 128) and after the fold at 2^16."""
+    """The ranges of y: no fold (sums of at most 8 stages of 64, K <= 512)
+    and after the fold at 2^16."""
     r16 = 65536 % m
-    return [(-128 * 127 * 127, 128 * 127 * 127), (-(2**15) * r16, (2**15 - 1) * r16 + 65535)]
+    return [(-512 * 127 * 127, 512 * 127 * 127), (-(2**15) * r16, (2**15 - 1) * r16 + 65535)]
 
 
 @pytest.mark.parametrize("m", range(2, 256))
