@@ -251,8 +251,11 @@ template <class G, int NK, bool FOLD>
 __global__ __launch_bounds__(G::THREADS, 1) void k_mfma8(StepArgs a, Mfma8Extra ex, int splits, int8_t* part,
                                                          int64_t part_stride) {
     constexpr int RA = G::RA, CB = G::CB;
-    __shared__ __align__(1024) uint8_t lds[k8Bufs * G::BUF + G::THREADS * 8];
-    uint64_t* const lconst = reinterpret_cast<uint64_t*>(lds + k8Bufs * G::BUF);
+    // one LDS buffer per stage in flight: tiles of one or two stages leave
+    // room for more work-groups per CU
+    constexpr int NBUF = NK < k8Bufs ? NK : k8Bufs;
+    __shared__ __align__(1024) uint8_t lds[NBUF * G::BUF + G::THREADS * 8];
+    uint64_t* const lconst = reinterpret_cast<uint64_t*>(lds + NBUF * G::BUF);
 
     const int g = blockIdx.z;
     const int8_t* A = static_cast<const int8_t*>(a.A) + g * a.strideA;
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(G::THREADS, 1) void k_mfma8(StepArgs a, Mfma8Extra 
     const int8_t* tA = A + uint64_t(ta) * G::WM * rowBytes;
     const int8_t* tB = B + uint64_t(tb) * G::WN * rowBytes;
 #pragma unroll
-    for (int c = 0; c < (NK < k8Bufs ? NK : k8Bufs); ++c) fetch(tA, tB, kc0 + c, c);
+    for (int c = 0; c < NBUF; ++c) fetch(tA, tB, kc0 + c, c);
 
     for (;;) {
         v4i acc[RA][CB];
@@ -368,7 +371,7 @@ __global__ __launch_bounds__(G::THREADS, 1) void k_mfma8(StepArgs a, Mfma8Extra 
                 chunk_barrier<63>();
                 if (more)
 #pragma unroll
-                    for (int c = 0; c < (NK < k8Bufs ? NK : k8Bufs); ++c) fetch(nA, nB, kc0 + c, c);
+                    for (int c = 0; c < NBUF; ++c) fetch(nA, nB, kc0 + c, c);
             }
 #pragma unroll
             for (int rb = 0; rb < RA; ++rb) {
