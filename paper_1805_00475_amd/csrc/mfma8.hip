@@ -69,15 +69,15 @@ struct Mfma8Extra {
 
 // Centred residue of an exact int32 sum modulo m <= 255, returned as the low
 // byte of a word. With FOLD, x = h 2^16 + l becomes y = h (2^16 mod m) + l,
-// |y| < 2^15 (m - 1) + 2^16; else K <= 512 and |y| = |x| <= 512 127^2. Either
-// way |y| < 2^23,
-// exact in single precision, and one fma adds f / m to 1.5 2^23, which rounds
-// the exact product to the nearest integer q (ties to even) into the low
-// mantissa bits: the word's low 24 bits read as a signed 24-bit integer are
-// 2^22 + q. One 24-bit multiply-add gives y - m (2^22 + q) = r - 2^22 m with
-// r = y - q m, whose low byte is r's since 256 divides 2^22 m; |r| <= 127 for
-// every m <= 255 (checked exhaustively over the range of y), so that byte is
-// r in two's complement.
+// |y| < 2^15 (m - 1) + 2^16; else the sum covers K <= 512 and
+// |y| = |x| <= 512 127^2. Either way |y| < 2^23 is exact in single precision.
+// One fma adds y fl(1/m) to 1.5 2^23 and rounds the exact sum once: with
+// |y fl(1/m)| < 2^22 the result lies where floats are spaced 1 apart, so its
+// low 24 bits, read as a signed 24-bit integer, are 2^22 + q, q the nearest
+// integer to y fl(1/m) (ties to even). One 24-bit multiply-add gives
+// y - m (2^22 + q) = r - 2^22 m with r = y - q m, whose low byte is r's since
+// 256 divides 2^22 m. |r| <= 127 for every m in 2..255 (checked over every
+// reachable y), so that byte is r in two's complement.
 template <bool FOLD>
 __device__ __forceinline__ uint32_t res8(int32_t x, int32_t r16, int32_t negm, float inv) {
     const int32_t y = FOLD ? (x >> 16) * r16 + (x & 0xffff) : x;
