@@ -11,10 +11,14 @@
  * satisfying assignments. A host-side order (Sec. 3.1.1: tensor-greedy,
  * tensor-METIS style recursive bisection, tensor-GN community detection, or
  * a learned scorer) fixes the sequence of pairwise contractions; HIP kernels
- * run them on the GPU. Counts are exact: 64-bit unsigned arithmetic while the
- * formula has at most 63 variables, otherwise residues modulo 16-bit primes
- * combined on the host by the Chinese remainder theorem (the exact-precision
- * remark of Sec. 3.2, at a cost linear in the number of primes).
+ * run them on the GPU. Counts are exact (the paper's floating-point counts
+ * lose precision from about 100 vertices, Sec. 3.2): 64-bit unsigned
+ * arithmetic while the count is below 2^64 (at most 63 boolean variables);
+ * otherwise residues modulo the fewest small pairwise coprime moduli
+ * (<= 255, one signed byte per residue) whose product exceeds twice the
+ * largest possible count, or, beyond about 332 bits, modulo 16-bit primes;
+ * the residues are combined on the host by the Chinese remainder theorem at
+ * a cost linear in the number of moduli.
  *
  * Conventions for every call:
  *  - Plain C ABI, no exceptions cross it; every call returns a tn_status.
@@ -160,7 +164,10 @@ tn_status tn_plan_verify(const tn_plan* plan);
 tn_status tn_workspace_bytes(const tn_network* net, const tn_plan* plan,
                              const tn_contract_opts* opts, size_t* bytes);
 
-/* Runs the plan on the GPU. RNS: writes the count modulo each modulus that
+/* Runs the plan on the GPU: the ordered pairwise contractions of Sec. 2.1
+ * (each step sums over every bond its two tensors share, Eq. 5 form; all
+ * parallel bonds at once, Sec. 2.2) until the network is one scalar, the
+ * full trace of Eq. 2 at zero temperature. RNS: writes the count modulo each modulus that
  * tn_moduli lists for the same plan and opts, in that order, to
  * residues[0..k-1]. U64: writes the exact count to *u64. Either output
  * pointer may be NULL when unused. Returns TN_ETOOBIG before any device work
@@ -168,8 +175,11 @@ tn_status tn_workspace_bytes(const tn_network* net, const tn_plan* plan,
 tn_status tn_contract(const tn_network* net, const tn_plan* plan, const tn_contract_opts* opts,
                       uint32_t* residues, int32_t residues_cap, uint64_t* u64);
 
-/* Exact count as little-endian base-2^32 limbs (CRT of the residues or the
- * 64-bit value). TN_EBUFSIZE with *n_limbs set when cap is too small. */
+/* Exact count (Sec. 2.1: the full contraction of the network is the number
+ * of satisfying assignments; exact integers instead of the floating-point
+ * counts of Sec. 3.2) as little-endian base-2^32 limbs: the CRT of
+ * tn_contract's residues, or its 64-bit value. limbs is a host buffer of cap
+ * entries; TN_EBUFSIZE with *n_limbs set when cap is too small. */
 tn_status tn_count(const tn_network* net, const tn_plan* plan, const tn_contract_opts* opts,
                    uint32_t* limbs, size_t cap, size_t* n_limbs);
 
@@ -287,7 +297,50 @@ tn_status tn_moduli(const tn_plan* plan, const tn_contract_opts* opts, uint32_t*
 /* Chinese remaindering of residues modulo the first k primes of tn_primes
  * into little-endian base-2^32 limbs. */
 tn_status tn_crt(const uint32_t* residues, int32_t k, uint32_t* limbs, size_t cap, size_t* n_limbs);
+/* Chinese remaindering of residues[i] modulo moduli[i] (i < k; any pairwise
+ * coprime moduli >= 2, such as those tn_moduli returns for a plan, so that
+ * tn_contract's residues recombine into the count) into the unique integer
+ * below their product, as little-endian base-2^32 limbs (host buffers).
+ * TN_EINVAL if a residue is not below its modulus or two moduli share a
+ * factor; TN_EBUFSIZE with *n_limbs set when cap is too small. */
+tn_status tn_crt_moduli(const uint32_t* residues, const uint32_t* moduli, int32_t k, uint32_t* limbs, size_t cap,
+                        size_t* n_limbs);
 const char* tn_status_str(tn_status s);
+
+/* ------------------------------------------------------------- generators
+ * Seeded synthetic instances shaped like the paper's workloads (Sec. 3.2):
+ * random cubic graphs, #Cubic-Vertex-Cover as 2-variable OR clauses (one
+ * variable per vertex, one clause per edge), monotone 1-in-3 with uniform
+ * clauses, and the paper's own 1-in-3 family on cubic graphs (one variable
+ * per edge, one exactly-one clause per vertex: every variable occurs in two
+ * clauses, the solutions are the perfect matchings). Random numbers:
+ * SplitMix64 seeding xoshiro256**, bounded draws by rejection; cubic graphs by
+ * the configuration model, the whole draw rejected on a loop or repeated
+ * edge (uniform over simple cubic graphs; the paper samples the same
+ * distribution with the Viger-Latapy method). Outputs are caller-owned host
+ * arrays in the tn_formula layout; a formula's sizes are fixed by its
+ * arguments, as stated per call. TN_EINVAL on a bad size or NULL output,
+ * TN_EUNSUPPORTED if no simple graph was drawn in 100000 tries. */
+/* Seed of instance ``index`` of workload ``family`` under ``master``
+ * (SplitMix64 of master ^ family << 40 ^ index). */
+uint64_t tn_instance_seed(int32_t family, uint64_t index, uint64_t master);
+/* Simple cubic graph on n (even, >= 4) vertices 0..n-1: edges[2i], edges[2i+1]
+ * for i < 3n/2, each pair (smaller, larger). */
+tn_status tn_gen_cubic_graph(int32_t n, uint64_t seed, int32_t* edges);
+/* Monotone 1-in-3: n variables, m clauses of 3 distinct variables drawn
+ * uniformly. clause_ptr: m + 1, lits: 3m, kinds: m entries. */
+tn_status tn_gen_exactly_one_3(int32_t n, int32_t m, uint64_t seed, int32_t* clause_ptr, int32_t* lits,
+                               uint8_t* kinds);
+/* Vertex cover of a random cubic graph on n vertices (OR clause per edge,
+ * in tn_gen_cubic_graph's edge order). clause_ptr: 3n/2 + 1, lits: 3n,
+ * kinds: 3n/2 entries. */
+tn_status tn_gen_cubic_vc(int32_t n, uint64_t seed, int32_t* clause_ptr, int32_t* lits, uint8_t* kinds);
+/* The paper's 1-in-3 family on a random cubic graph with n_vertices vertices:
+ * 3 n_vertices / 2 variables (variable i + 1 = edge i), one exactly-one clause
+ * per vertex over its three edges in increasing order. clause_ptr:
+ * n_vertices + 1, lits: 3 n_vertices, kinds: n_vertices entries. */
+tn_status tn_gen_cubic_1in3(int32_t n_vertices, uint64_t seed, int32_t* clause_ptr, int32_t* lits, uint8_t* kinds);
+
 /* Library version string. */
 const char* tn_version(void);
 

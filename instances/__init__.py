@@ -27,6 +27,13 @@ from .gen import (  # noqa: F401
     cvc,
     large_1in3,
     learned_instance,
+    cubic_1in3,
+    FAMILY_SMALL_1IN3,
+    FAMILY_CVC,
+    FAMILY_LARGE_1IN3,
+    FAMILY_BATCH,
+    FAMILY_LEARNED,
+    FAMILY_CUBIC_1IN3,
     OR,
     EXACTLY_ONE,
 )

@@ -291,6 +291,7 @@ FAMILY_CVC = 1            # vertex cover of random cubic graphs
 FAMILY_LARGE_1IN3 = 2     # monotone 1-in-3, n=150..300, alpha 0.62..0.70
 FAMILY_BATCH = 3          # mixed batch, n in [30, 120]
 FAMILY_LEARNED = 4        # training / held-out 1-in-3, n in [100, 250]
+FAMILY_CUBIC_1IN3 = 5     # the paper's 1-in-3 family: one variable per edge of a cubic graph
 
 
 def small_1in3(index: int) -> Formula:
@@ -328,3 +329,13 @@ def learned_instance(index: int, split: str = "train", n: int = None) -> Formula
     if n is None:
         n = rng.uniform_int(100, 250)
     return exactly_one_3(n, int(round(0.66 * n)), rng, name=f"learn-{split}{index}-n{n}")
+
+
+def cubic_1in3(n_vertices: int, index: int) -> Formula:
+    """The paper's 1-in-3 workload (Sec. 3.2): a uniform random cubic graph on
+    ``n_vertices`` vertices, one variable per edge (3 n_vertices / 2 of them,
+    each in exactly two clauses, clause density 2/3) and one exactly-one
+    clause per vertex over its three edges."""
+    rng = Rng(instance_seed(FAMILY_CUBIC_1IN3, (n_vertices << 20) | index))
+    return perfect_matching_formula(cubic_graph(n_vertices, rng), n_vertices,
+                                    name=f"cubic1in3-N{3 * n_vertices // 2}-s{index}")

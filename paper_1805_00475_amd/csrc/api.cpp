@@ -210,6 +210,33 @@ tn_status tn_crt(const uint32_t* residues, int32_t k, uint32_t* limbs, size_t ca
     return TN_OK;
 }
 
+tn_status tn_crt_moduli(const uint32_t* residues, const uint32_t* moduli, int32_t k, uint32_t* limbs, size_t cap,
+                        size_t* n_limbs) {
+    if (k <= 0 || k > 4096 || !residues || !moduli || !n_limbs) return TN_EINVAL;
+    for (int32_t i = 0; i < k; ++i) {
+        if (moduli[i] < 2 || residues[i] >= moduli[i]) return TN_EINVAL;
+        for (int32_t j = 0; j < i; ++j) {
+            uint32_t a = moduli[i], b = moduli[j];
+            while (b) {
+                const uint32_t t = a % b;
+                a = b;
+                b = t;
+            }
+            if (a != 1) return TN_EINVAL;  // not coprime: no unique recombination
+        }
+    }
+    std::vector<uint32_t> L;
+    try {
+        crt_limbs(residues, moduli, k, L);
+    } catch (const std::bad_alloc&) {
+        return TN_ENOMEM;
+    }
+    *n_limbs = L.size();
+    if (!limbs || cap < L.size()) return TN_EBUFSIZE;
+    std::copy(L.begin(), L.end(), limbs);
+    return TN_OK;
+}
+
 const char* tn_status_str(tn_status s) {
     switch (s) {
         case TN_OK: return "ok";

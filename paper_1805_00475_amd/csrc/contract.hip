@@ -5,8 +5,10 @@
 // Step semantics (Sec. 2.1, Eq. 5; all shared bonds at once, Sec. 2.2):
 //     C[c] = sum over z in {0,1}^s of A[z | xA << s] * B[z | xB << s]
 // with xA = the C bits selected by maskA and xB those selected by maskB, in
-// order. Arithmetic is modulo a 31-bit prime (one prime per blockIdx.z) or
-// wrapping 64-bit, which is exact while the count fits (n <= 63).
+// order. Arithmetic is per residue plane (one plane per blockIdx.z): centred
+// int8 residues modulo a small modulus (<= 255), u32 residues modulo a 16-bit
+// prime, or wrapping 64-bit counts, which are exact while the count fits
+// (n <= 63).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -109,6 +109,16 @@ _SIGS = {
     "tn_step": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                  ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                  ctypes.c_void_p], ctypes.c_int),
+    "tn_crt_moduli": ([_P(ctypes.c_uint32), _P(ctypes.c_uint32), ctypes.c_int32, _P(ctypes.c_uint32),
+                       ctypes.c_size_t, _P(ctypes.c_size_t)], ctypes.c_int),
+    "tn_instance_seed": ([ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_uint64),
+    "tn_gen_cubic_graph": ([ctypes.c_int32, ctypes.c_uint64, _P(ctypes.c_int32)], ctypes.c_int),
+    "tn_gen_exactly_one_3": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, _P(ctypes.c_int32),
+                              _P(ctypes.c_int32), _P(ctypes.c_uint8)], ctypes.c_int),
+    "tn_gen_cubic_vc": ([ctypes.c_int32, ctypes.c_uint64, _P(ctypes.c_int32), _P(ctypes.c_int32),
+                         _P(ctypes.c_uint8)], ctypes.c_int),
+    "tn_gen_cubic_1in3": ([ctypes.c_int32, ctypes.c_uint64, _P(ctypes.c_int32), _P(ctypes.c_int32),
+                           _P(ctypes.c_uint8)], ctypes.c_int),
     "tn_status_str": ([ctypes.c_int], ctypes.c_char_p),
     "tn_version": ([], ctypes.c_char_p),
 }
@@ -462,6 +472,72 @@ def crt(residues: Sequence[int]) -> int:
     n = ctypes.c_size_t()
     _check(load().tn_crt(r, k, limbs, cap, ctypes.byref(n)), "tn_crt")
     return _limbs_to_int(limbs, n.value)
+
+
+def crt_moduli(residues: Sequence[int], mods: Sequence[int]) -> int:
+    """Recombine residues modulo pairwise coprime moduli (tn_crt_moduli)."""
+    k = len(residues)
+    r = (ctypes.c_uint32 * max(1, k))(*residues)
+    m = (ctypes.c_uint32 * max(1, k))(*mods)
+    n = ctypes.c_size_t()
+    st = load().tn_crt_moduli(r, m, k, None, 0, ctypes.byref(n))
+    if st not in (TN_OK, -6):
+        _check(st, "tn_crt_moduli")
+    limbs = (ctypes.c_uint32 * max(1, n.value))()
+    _check(load().tn_crt_moduli(r, m, k, limbs, n.value, ctypes.byref(n)), "tn_crt_moduli")
+    return _limbs_to_int(limbs, n.value)
+
+
+# -------------------------------------------------------------- generators
+class GenFormula:
+    """A generated formula in the C-ABI layout (n_vars, clause_ptr, lits, kinds),
+    usable wherever a formula is expected."""
+
+    def __init__(self, n_vars, ptr, lits, kinds, name=""):
+        self.n_vars = n_vars
+        self._ptr, self._lits, self._kinds = list(ptr), list(lits), list(kinds)
+        self.name = name
+
+    @property
+    def n_clauses(self):
+        return len(self._kinds)
+
+    def arrays(self):
+        return self._ptr, self._lits, self._kinds
+
+    @property
+    def clauses(self):
+        return [(self._kinds[c], self._lits[self._ptr[c]:self._ptr[c + 1]]) for c in range(self.n_clauses)]
+
+
+def instance_seed(family: int, index: int, master: int = 0) -> int:
+    return int(load().tn_instance_seed(family, index, master))
+
+
+def _gen(fn, args, n_vars, m, lits_per):
+    ptr = (ctypes.c_int32 * (m + 1))()
+    lits = (ctypes.c_int32 * max(1, lits_per * m))()
+    kinds = (ctypes.c_uint8 * max(1, m))()
+    _check(getattr(load(), fn)(*args, ptr, lits, kinds), fn)
+    return GenFormula(n_vars, ptr[:m + 1], lits[:lits_per * m], kinds[:m])
+
+
+def gen_cubic_graph(n: int, seed: int):
+    e = (ctypes.c_int32 * (3 * n))()
+    _check(load().tn_gen_cubic_graph(n, seed, e), "tn_gen_cubic_graph")
+    return [(e[2 * i], e[2 * i + 1]) for i in range(3 * n // 2)]
+
+
+def gen_exactly_one_3(n: int, m: int, seed: int):
+    return _gen("tn_gen_exactly_one_3", (n, m, seed), n, m, 3)
+
+
+def gen_cubic_vc(n: int, seed: int):
+    return _gen("tn_gen_cubic_vc", (n, seed), n, 3 * n // 2, 2)
+
+
+def gen_cubic_1in3(n_vertices: int, seed: int):
+    return _gen("tn_gen_cubic_1in3", (n_vertices, seed), 3 * n_vertices // 2, n_vertices, 3)
 
 
 def profile() -> dict:

@@ -203,3 +203,17 @@ def test_repeat_is_deterministic():
     r1 = tn.contract(net, plan, arith="rns")
     r2 = tn.contract(net, plan, arith="rns")
     assert r1 == r2
+
+
+@pytest.mark.gpu
+def test_contract_residues_recombine_through_crt_moduli():
+    # tn_contract's default residues (small moduli) recombined by the C ABI's
+    # own CRT entry point, against the closed form of prism vertex covers
+    _say("[gpu] tn_contract residues -> tn_crt_moduli, prism n=200")
+    f = I.vertex_cover_formula(I.prism_graph(100))
+    net = tn.Network(f)
+    plan = net.order("best", seed=0)
+    res = tn.contract(net, plan)
+    mods = tn.moduli(plan)
+    assert len(res) == len(mods) and max(mods) <= 255
+    assert tn.crt_moduli(res, mods) == closed.prism_vertex_covers(100)

@@ -214,3 +214,31 @@ def test_workspace_query_small_moduli_bytes():
     wide = tn.workspace_bytes(net, plan, flags=tn.FLAG_WIDE_RNS)
     assert small < wide
     assert small >= plan.stats["peak_elems"] * 0.5
+
+
+def test_crt_moduli_round_trip():
+    from oracle import rns as R
+    mods = [255, 254, 253, 251, 247, 241, 239]
+    rnd = random.Random(5)
+    prod = 1
+    for m in mods:
+        prod *= m
+    for _ in range(50):
+        x = rnd.randrange(prod)
+        assert tn.crt_moduli([x % m for m in mods], mods) == x
+    # the library's own moduli and a count known in closed form
+    x = 2 ** 200 - 12345
+    ms = [255, 254, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199, 197, 193, 191, 181, 179, 173,
+          167, 163, 157, 151, 149, 139, 137]
+    assert tn.crt_moduli([x % m for m in ms], ms) == x
+    assert R.crt([x % m for m in ms], ms) == x
+
+
+def test_crt_moduli_rejects_bad_input():
+    lib = tn.load()
+    import ctypes
+    n = ctypes.c_size_t()
+    r = (ctypes.c_uint32 * 2)(1, 2)
+    for mods in ((6, 9), (5, 1), (3, 2)):   # shared factor, modulus 1, residue >= modulus
+        m = (ctypes.c_uint32 * 2)(*mods)
+        assert lib.tn_crt_moduli(r, m, 2, None, 0, ctypes.byref(n)) == -1
