@@ -175,6 +175,24 @@ tn_status tn_workspace_bytes(const tn_network* net, const tn_plan* plan,
 tn_status tn_contract(const tn_network* net, const tn_plan* plan, const tn_contract_opts* opts,
                       uint32_t* residues, int32_t residues_cap, uint64_t* u64);
 
+/* tn_contract without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the workspace is a file-scope device array of
+ * tn_noalloc_max_bytes() bytes (64 MiB) that the library holds on every GPU
+ * it runs on until the process ends; opts->workspace and
+ * opts->workspace_bytes are ignored, every other field is used as by
+ * tn_contract, and the outputs are tn_contract's. Returns TN_ETOOBIG before
+ * any device work when the plan's initial tensors, one residue plane's
+ * arena and its scratch do not fit the array (tn_workspace_bytes with
+ * prime_group = 0 gives the need), TN_EUNSUPPORTED with TN_FLAG_TIMING.
+ * Every call on one GPU uses that GPU's one array and leaves its contents
+ * behind (nothing in it needs to start at zero): calls that overlap on one
+ * GPU, from two threads or on two streams, race and must not be made. */
+tn_status tn_contract_noalloc(const tn_network* net, const tn_plan* plan, const tn_contract_opts* opts,
+                              uint32_t* residues, int32_t residues_cap, uint64_t* u64);
+/* Size in bytes of tn_contract_noalloc's device array. */
+size_t tn_noalloc_max_bytes(void);
+
 /* Exact count (Sec. 2.1: the full contraction of the network is the number
  * of satisfying assignments; exact integers instead of the floating-point
  * counts of Sec. 3.2) as little-endian base-2^32 limbs: the CRT of

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -726,6 +727,52 @@ tn_status tn_count(const tn_network* net, const tn_plan* plan, const tn_contract
 }
 
 }  // extern "C"
+
+// ------------------------------------------------- allocation-free variant
+// Device memory for tn_contract_noalloc: one file-scope array per GPU (each
+// device that loads the library holds its own copy until the process ends).
+// Host code never passes the array's name to a kernel or a copy: it looks up
+// the array's device address once per device (hipGetSymbolAddress, with that
+// device current) and uses that address as the workspace.
+static constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+tn_status noalloc_workspace(void** ptr) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return TN_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TN_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return TN_OK;
+}
+}  // namespace
+
+extern "C" tn_status tn_contract_noalloc(const tn_network* net, const tn_plan* plan, const tn_contract_opts* opts,
+                                         uint32_t* residues, int32_t residues_cap, uint64_t* u64) {
+    if (!net || !plan || !opts) return TN_EINVAL;
+    // per-launch timing creates events: not available without allocation
+    if (opts->flags & TN_FLAG_TIMING) return TN_EUNSUPPORTED;
+    tn_contract_opts o = *opts;
+    void* ws = nullptr;
+    const tn_status st = noalloc_workspace(&ws);
+    if (st != TN_OK) return st;
+    o.workspace = ws;
+    o.workspace_bytes = kNoAllocBytes;
+    // the plan's init region, arena and scratch must fit the array; run_plan
+    // returns TN_ETOOBIG before any device work otherwise
+    return tn_contract(net, plan, &o, residues, residues_cap, u64);
+}
+
+extern "C" size_t tn_noalloc_max_bytes(void) { return kNoAllocBytes; }
 
 extern "C" tn_status tn_step(const void* A, int32_t rA, const void* B, int32_t rB, int32_t s, uint64_t maskA,
                              int32_t arith, uint32_t prime, int32_t kernel, void* C, void* workspace,

@@ -81,6 +81,9 @@ _SIGS = {
                            ctypes.c_int),
     "tn_contract": ([ctypes.c_void_p, ctypes.c_void_p, _P(ContractOpts_c), _P(ctypes.c_uint32), ctypes.c_int32,
                      _P(ctypes.c_uint64)], ctypes.c_int),
+    "tn_contract_noalloc": ([ctypes.c_void_p, ctypes.c_void_p, _P(ContractOpts_c), _P(ctypes.c_uint32),
+                             ctypes.c_int32, _P(ctypes.c_uint64)], ctypes.c_int),
+    "tn_noalloc_max_bytes": ([], ctypes.c_size_t),
     "tn_count": ([ctypes.c_void_p, ctypes.c_void_p, _P(ContractOpts_c), _P(ctypes.c_uint32), ctypes.c_size_t,
                   _P(ctypes.c_size_t)], ctypes.c_int),
     "tn_count_batch": ([_P(Formula_c), ctypes.c_int32, ctypes.c_int, ctypes.c_uint64, _P(ContractOpts_c),
@@ -290,6 +293,24 @@ def contract(net: Network, plan: Plan, arith="auto", n_primes=0, workspace: Work
     if not mods:
         return int(u.value)
     return [int(res[i]) for i in range(len(mods))]
+
+
+def contract_noalloc(net: Network, plan: Plan, arith="auto", n_primes=0, prime_group=0, flags=0):
+    """tn_contract_noalloc: the library's own device array as workspace;
+    returns the residues list (RNS) or the exact int (U64)."""
+    o = _opts(arith, n_primes, None, 0, current_stream_handle(), prime_group, flags)
+    res = (ctypes.c_uint32 * MAX_PRIMES)()
+    u = ctypes.c_uint64()
+    _check(load().tn_contract_noalloc(net.h, plan.h, ctypes.byref(o), res, MAX_PRIMES, ctypes.byref(u)),
+           "tn_contract_noalloc")
+    mods = moduli(plan, arith, n_primes, flags)
+    if not mods:
+        return int(u.value)
+    return [int(res[i]) for i in range(len(mods))]
+
+
+def noalloc_max_bytes() -> int:
+    return int(load().tn_noalloc_max_bytes())
 
 
 def count_plan(net: Network, plan: Plan, arith="auto", n_primes=0, workspace: Workspace = None,
