@@ -31,24 +31,56 @@ Tensor = Tuple[np.ndarray, Tuple[int, ...]]
 
 
 def _mod_tensordot(A: np.ndarray, B: np.ndarray, axes, p: int) -> np.ndarray:
-    """tensordot of residue arrays modulo p, exact in int64.
+    """tensordot of residue arrays modulo p < 2^31, exact.
 
-    Entries are below p < 2^31. Both operands are split into 16-bit halves
-    so every partial product is below 2^32 and every sum of at most 2^30 of
-    them fits in int64; the four partial results are recombined mod p.
+    Both operands are split into 16-bit halves, a = a0 + 2^16 a1. A product of
+    two halves is below 2^32 and a sum of at most 2^21 such products is below
+    2^53, so each of the four half-products over a chunk of at most 2^21
+    shared entries is an exact float64 matrix product (numpy's BLAS; the
+    summation order does not matter for exact integers). The half-products
+    are recombined modulo p in int64,
+        A.B = s00 + 2^16 (s01 + s10) + 2^32 s11   (mod p),
+    and the chunks are added modulo p. The result has A's free axes, then
+    B's, as numpy's tensordot.
     """
-    A = A.astype(np.int64)
-    B = B.astype(np.int64)
-    a0, a1 = A & 0xFFFF, A >> 16
-    b0, b1 = B & 0xFFFF, B >> 16
-    s00 = np.tensordot(a0, b0, axes=axes) % p
-    s01 = np.tensordot(a0, b1, axes=axes) % p
-    s10 = np.tensordot(a1, b0, axes=axes) % p
-    s11 = np.tensordot(a1, b1, axes=axes) % p
-    two16 = (1 << 16) % p
-    two32 = (1 << 32) % p
-    mid = (s01 + s10) % p
-    return ((s11 * two32) % p + (mid * two16) % p + s00) % p
+    ia, ib = list(axes[0]), list(axes[1])
+    fa = [d for d in range(A.ndim) if d not in ia]
+    fb = [d for d in range(B.ndim) if d not in ib]
+    out_shape = tuple(A.shape[d] for d in fa) + tuple(B.shape[d] for d in fb)
+    K = 1
+    for d in ia:
+        K *= A.shape[d]
+    A2 = np.transpose(np.asarray(A, dtype=np.int64), fa + ia).reshape(-1, K)
+    B2 = np.transpose(np.asarray(B, dtype=np.int64), ib + fb).reshape(K, -1)
+    chunk = 1 << 21
+    acc = None
+    for k0 in range(0, K, chunk):
+        a, b = A2[:, k0:k0 + chunk], B2[k0:k0 + chunk, :]
+        a0, a1 = (a & 0xFFFF).astype(np.float64), (a >> 16).astype(np.float64)
+        b0, b1 = (b & 0xFFFF).astype(np.float64), (b >> 16).astype(np.float64)
+
+        def part(x, y):
+            t = x @ y
+            np.fmod(t, p, out=t)
+            return t.astype(np.int64)
+
+        r = part(a1, b1)
+        r *= (1 << 32) % p          # < 2^62
+        r %= p
+        mid = part(a0, b1)
+        mid += part(a1, b0)         # < 2p
+        mid %= p
+        mid *= (1 << 16) % p        # < 2^47
+        r += mid
+        del mid
+        r += part(a0, b0)
+        r %= p
+        if acc is None:
+            acc = r
+        else:
+            acc += r
+            acc %= p
+    return acc.reshape(out_shape)
 
 
 def contract_pair(A: Tensor, B: Tensor, p: Optional[int] = None) -> Tensor:

@@ -1,6 +1,13 @@
 """Writes the stored expected counts under tests/golden from the oracle only.
 
     python tests/golden/make_golden.py [--large]
+    python tests/golden/make_golden.py --cvc200 [seeds...]
+
+cvc200_counts.json        vertex cover of random cubic graphs, n=200: the
+                          pairwise contractor O-B (exact float64 limb products
+                          per 31-bit prime, CRT) along the oracle's own order
+                          (oracle.order: the cheaper of its Girvan-Newman and
+                          bisection orders), checked against one extra prime
 
 small_1in3_counts.json    monotone 1-in-3, n=20, m=14, seeds 0..999 (O-A brute force)
 batch_small_counts.json   the first instances of the mixed batch with n <= 30 (O-A)
@@ -20,7 +27,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import instances as I  # noqa: E402
-from oracle import brute, contract, elim  # noqa: E402
+from oracle import brute, contract, elim, order, rns, tensors  # noqa: E402
 
 
 def dump(name, obj):
@@ -87,5 +94,86 @@ def main(large=False):
         "oracle": "oracle.elim.count_rns (O-D)", "items": l13})
 
 
+def count_ob(f, log=print):
+    """O-B along the oracle's cheapest own order, one 31-bit prime at a time,
+    with the CRT result checked modulo one more prime."""
+    nets, _ = tensors.network_of_formula(f)
+    labels = [ls for _, ls in nets]
+    t = time.time()
+    merges, which = order.cheapest_order(labels)
+    mr = order_max_rank(labels, merges)
+    log(f"  {f.name}: {which} order, max rank {mr} ({time.time() - t:.1f}s)")
+    primes = rns.primes_for(f.n_vars)
+    extra = rns.largest_primes_below(1 << 31, len(primes) + 1)[-1]
+    res = []
+    for p in primes + [extra]:
+        t = time.time()
+        res.append(contract.count_mod(f, p, merges))
+        log(f"    mod {p}: {res[-1]} ({time.time() - t:.1f}s)")
+    c = rns.crt(res[:-1], primes)
+    assert c % extra == res[-1], "extra-prime check failed"
+    return c, which, mr
+
+
+def order_max_rank(labels, merges):
+    return contract.max_rank_of_order(labels, merges)
+
+
+def cvc200(seeds):
+    path = os.path.join(HERE, "cvc200_counts.json")
+    items = json.load(open(path))["items"] if os.path.exists(path) else []
+    have = {it["seed"] for it in items}
+    for s in seeds:
+        if s in have:
+            continue
+        f = I.cvc(200, s)
+        c, which, mr = count_ob(f)
+        items.append({"n": 200, "seed": s, "count": str(c), "order": which, "max_rank": mr})
+        items.sort(key=lambda it: it["seed"])
+        dump("cvc200_counts.json", {
+            "workload": "instances.cvc(200, seed): vertex covers of a uniform random cubic graph, n=200",
+            "oracle": "oracle.contract.count_mod (O-B) per prime of oracle.rns.primes_for(200) along "
+                      "oracle.order.cheapest_order, oracle.rns.crt; checked modulo one extra prime",
+            "items": items})
+
+
+# uniform 1-in-3 instances of the large workload (n = 150-300, alpha
+# 0.62-0.70) small enough for a CPU oracle: O-B along the oracle's own order
+# where that order stays at rank <= 28, O-D where its elimination width does
+C3_CASES = [(200, 0.66, 0, "ob"), (200, 0.66, 1, "od"), (200, 0.66, 3, "ob"), (200, 0.70, 3, "ob"),
+            (250, 0.62, 1, "ob")]
+
+
+def c3():
+    path = os.path.join(HERE, "c3_1in3_counts.json")
+    items = json.load(open(path))["items"] if os.path.exists(path) else []
+    have = {(it["n"], it["alpha"], it["seed"]) for it in items}
+    for n, a, s, how in C3_CASES:
+        if (n, a, s) in have:
+            continue
+        f = I.large_1in3(n, a, s)
+        t = time.time()
+        if how == "ob":
+            c, which, mr = count_ob(f)
+            it = {"n": n, "alpha": a, "seed": s, "count": str(c), "oracle": "O-B", "order": which, "max_rank": mr}
+        else:
+            c = elim.count_rns(f)
+            it = {"n": n, "alpha": a, "seed": s, "count": str(c), "oracle": "O-D", "width": elim.width(f)}
+        print(f"  1in3 n={n} a={a} s={s}: {c} ({time.time() - t:.1f}s)", flush=True)
+        items.append(it)
+        items.sort(key=lambda x: (x["n"], x["alpha"], x["seed"]))
+        dump("c3_1in3_counts.json", {
+            "workload": "instances.large_1in3(n, alpha, seed): monotone 1-in-3, clauses of 3 distinct uniform "
+                        "variables, m = round(alpha n)",
+            "oracle": "O-B: oracle.contract.count_mod per 31-bit prime along oracle.order.cheapest_order + "
+                      "oracle.rns.crt, checked modulo one extra prime; O-D: oracle.elim.count_rns",
+            "items": items})
+
+
 if __name__ == "__main__":
-    main(large="--large" in sys.argv)
+    if "--c3" in sys.argv:
+        c3()
+    elif "--cvc200" in sys.argv:
+        cvc200([int(x) for x in sys.argv[sys.argv.index("--cvc200") + 1:]] or [0, 1])
+    else:
+        main(large="--large" in sys.argv)

@@ -361,3 +361,41 @@ def test_step_definition_matches_pairwise_contraction():
         Cf = np.transpose(Ct, [lc.index(l) for l in reversed(cl)]).reshape(-1) if rC else Ct.reshape(-1)
         want = contract.step_entries(A, B, s, maskA, rC, range(1 << rC), p)
         assert [int(x) for x in Cf] == want
+
+
+def test_mod_tensordot_chunked_shared_dimension_exact():
+    # a shared dimension of 2^22 (two float64 chunks of 2^21) against exact
+    # Python integers, entries uniform below the largest 31-bit prime
+    import numpy as np
+    from oracle import contract as C
+    r = np.random.default_rng(1)
+    p = 2147483647
+    A = r.integers(0, p, size=(2,) * 23, dtype=np.int64)
+    B = r.integers(0, p, size=(2,) * 23, dtype=np.int64)
+    got = C._mod_tensordot(A, B, (list(range(1, 23)), list(range(1, 23))), p)
+    a, b = A.reshape(2, -1).tolist(), B.reshape(2, -1).tolist()
+    want = [[sum(x * y for x, y in zip(a[i], b[j])) % p for j in range(2)] for i in range(2)]
+    assert got.tolist() == want
+
+
+def test_oracle_orders_valid_and_count_exact():
+    # the oracle's own bisection and Girvan-Newman orders merge every tensor
+    # exactly once, and O-B along them gives the brute-force count
+    from oracle import contract as C, order as O, tensors as T, brute as Bf, cost
+    rng = I.Rng(4242)
+    forms = [I.random_mixed_formula(9, 8, rng) for _ in range(6)] + \
+        [I.vertex_cover_formula(I.petersen_graph()), I.perfect_matching_formula(I.prism_graph(5)),
+         I.small_1in3(3), I.Formula(3)]
+    for f in forms:
+        nets, _ = T.network_of_formula(f)
+        labels = [ls for _, ls in nets]
+        for merges in (O.partition_order(labels, 1, tries=3), O.community_order(labels),
+                       O.cheapest_order(labels, tries=2)[0]):
+            used = set()
+            for k, (a, b) in enumerate(merges):
+                assert a != b and a not in used and b not in used and max(a, b) < len(labels) + k
+                used.update((a, b))
+            if labels:
+                assert len(merges) == len(labels) - 1
+                assert cost.replay(labels, merges)["remaining"] == [[]]
+            assert C.count_exact(f, merges) == Bf.count(f)
