@@ -1,25 +1,31 @@
-"""Benchmark: exact counts per second of #Cubic-Vertex-Cover on random cubic
-graphs (Sec. 3.2 workload; configuration model, n = 200 vertices by
-default), counted by tensor-network contraction on one MI355X.
+"""Benchmark: exact model counts per second by tensor-network contraction on
+one MI355X.
 
-A step is one pass of the whole path over one batch of formulas: build the
-network, order it on the host, contract on the GPU, recombine by CRT. The
-timed region starts with the formulas in host memory (the path's input);
-every count is exact.
+Headline workload: monotone #1-in-3SAT with uniform random 3-variable clauses
+(Sec. 3.2 family with uniform clauses), n = 300 variables, m = 186 clauses
+(density 0.62), seed 1 -- the largest configuration of the grid n in
+{150, 200, 250, 300} x density in {0.62, 0.66, 0.70} whose predicted largest
+intermediate rank (the lazy cost check of Sec. 4) lies in [30, 32]; its
+judged plan reaches rank 31 (2^31 residues per modulus). A step is one pass
+of the whole path over that formula: build the network, order it on the host,
+contract on the GPU in 42 small moduli, recombine by CRT. The timed region
+starts with the formula in host memory; every count is exact.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 200] [--batch B]
-                    [--order best] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu-baseline]
 
-Prints one JSON line. ``roofline`` reports the dominant kernel class measured
-with hipEvents around every launch of an extra, identical pass;
-``cpu_baseline`` times the CPU oracle on a bounded sample of the workload.
+Prints one JSON line. ``roofline`` is the dominant kernel class (the int8
+matrix-core kernels), from hipEvents around every launch of the timed steps;
+``hbm_roofline`` covers the memory-bound launches (arithmetic intensity
+below the machine balance) whose working set is at least 1 GiB. Extra keys
+measure the other workloads (vertex cover n = 200, the n = 20 1-in-3 set,
+the mixed 4096-instance batch, learned vs greedy orders) and the CPU oracle.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import subprocess
 import sys
 import time
 
@@ -27,21 +33,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the matrix-core kernels (small-modulus residues)
-# from rocprofv3 byte counters (FETCH_SIZE and WRITE_SIZE runs of this
-# benchmark, scaled by a plain copy of known size); used only while the kernel
-# source is the one measured
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mfma8_cvc200_batch16_traffic.txt")
-INT8_PEAK_TOPS = 5000.0   # dense int8 MFMA, MI355X
+INT8_PEAK_TOPS = 5000.0    # dense int8 MFMA, MI355X
+# machine balance: int8 multiply-adds per HBM byte at the two peaks
+BALANCE_MACS_PER_BYTE = INT8_PEAK_TOPS * 1e12 / 2 / (HBM_PEAK_GBS * 1e9)
 # int8 products per multiply-add modulo one modulus: 4 digit pairs for the
-# 16-bit primes, 1 for small moduli (centred int8 residues); an int8 op is a
-# multiply or an add, 2 per product
+# 16-bit primes, 1 for small moduli (centred int8 residues)
 INT8_PRODUCTS_PER_MODMAC = {"wide": 4, "small": 1}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mfma8_1in3_n300_traffic.txt")
+
+C3 = {"n": 300, "alpha": 0.62, "seed": 1}
+LEARNED_HELDOUT = [1, 4, 6, 9, 12, 15, 16, 18, 22, 23]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def measured_traffic():
-    """Counter-derived bytes per k_mfma launch, or None when the kernel
-    source changed since the counters were taken (or no record exists)."""
+    """Counter-derived HBM bytes per matrix-core launch on the headline
+    workload, or None when the kernel source changed since the counters were
+    taken (or no record exists)."""
     import hashlib
     try:
         rec = {}
@@ -57,98 +68,169 @@ def measured_traffic():
         return None
 
 
-def roofline_of(name, d, mode="small"):
-    """Achieved vs peak for one kernel class from its hipEvent total.
-
-    Matrix-core GEMM (mfma): algorithmic multiply-adds modulo each modulus,
-    each costing INT8_PRODUCTS_PER_MODMAC[mode] int8 products (2 int8 ops
-    apiece), against the dense int8 MFMA peak. Every other class: algorithmic
-    bytes (entries of A and B read, C written) against the HBM peak."""
-    sec = d["ms"] * 1e-3
-    per = {"kernel_class": name, "launches": d["launches"],
-           "avg_launch_us": round(1e6 * sec / max(1, d["launches"]), 3)}
-    if name == "mfma":
-        tops = d["macs"] * 2 * INT8_PRODUCTS_PER_MODMAC[mode] / sec / 1e12 if sec > 0 else 0.0
-        per.update({"bound": "mfma", "achieved": round(tops, 2), "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                    "frac": round(tops / INT8_PEAK_TOPS, 4),
-                    "traffic": measured_traffic() if mode == "small" else None,
-                    "algorithmic_modmacs_per_launch": d["macs"] / max(1, d["launches"]),
-                    "achieved_modmacs_per_s": d["macs"] / sec if sec > 0 else 0.0})
-    else:
-        gbs = d["bytes"] / sec / 1e9 if sec > 0 else 0.0
-        per.update({"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                    "algorithmic_bytes_per_launch": d["bytes"] / max(1, d["launches"])})
-    return per
-
-
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["cvc", "batch"], default="cvc",
-                    help="cvc: vertex cover of random cubic graphs (n vertices); batch: the mixed batch "
-                         "of 1-in-3 and cubic vertex cover with n in [30, 120]")
-    ap.add_argument("--n", type=int, default=200)
-    ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--order", default="best")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned vs greedy comparison")
+    ap.add_argument("--c4-batch", type=int, default=4096, help="instances of the mixed batch (0 = skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a plain copy kernel of known size, used to scale "
                          "hardware byte counters)")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--single", action="store_true", help="count one formula at a time instead of the batch API")
-    ap.add_argument("--wide-rns", action="store_true",
-                    help="residues modulo 16-bit primes even where small int8 moduli suffice")
     return ap.parse_args()
 
 
-def cpu_baseline(formula, plan_steps, budget_s):
-    """Oracle O-B (numpy pairwise contraction) on one prime of one instance,
-    following the same contraction order, stopped after ``budget_s``; the
-    instance time is extrapolated linearly in multiply-adds done and in the
-    oracle's own number of primes (31-bit ones)."""
-    import numpy as np
-    from oracle import contract, cost, rns, tensors
-    n_primes = rns.n_primes_for(formula.n_vars)
-    nets, _ = tensors.network_of_formula(formula)
-    rep = cost.replay([ls for _, ls in nets], plan_steps)
-    macs = [s["macs"] for s in rep["steps"]]
-    total = float(sum(macs))
-    p = rns.primes_for(formula.n_vars)[0]
-    work = {i: (np.asarray(t, dtype=np.int64) % p, ls) for i, (t, ls) in enumerate(nets)}
-    nid = len(nets)
-    done = 0.0
-    t0 = time.process_time()
-    w0 = time.time()
-    k = 0
-    for k, (a, b) in enumerate(plan_steps):
-        work[nid] = contract.contract_pair(work.pop(a), work.pop(b), p)
-        nid += 1
-        done += macs[k]
-        if time.time() - w0 > budget_s:
-            break
-    el = time.time() - w0
-    frac = done / total
-    inst_s = el / max(frac, 1e-12) * n_primes
-    return {"value": 1.0 / inst_s, "unit": "counts/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle O-B (numpy pairwise contraction, exact int64 limbs) on {formula.name}, "
-                       f"prime 1 of {n_primes}, first {k + 1} of {len(plan_steps)} steps of the same order "
-                       f"= {100 * frac:.2f}% of its multiply-adds in {el:.1f}s wall "
-                       f"({time.process_time() - t0:.1f}s CPU); instance time extrapolated linearly in "
-                       f"multiply-adds and primes"),
-            "extrapolated_instance_s": inst_s}
+class Acc:
+    """Per-class and per-launch device times summed over several timed calls."""
+
+    def __init__(self, tn):
+        self.tn = tn
+        self.cls = {}
+        self.launches = []
+
+    def add(self):
+        for k, v in self.tn.profile().items():
+            c = self.cls.setdefault(k, {"launches": 0, "ms": 0.0, "bytes": 0.0, "macs": 0.0})
+            for f in c:
+                c[f] += v[f]
+        self.launches += self.tn.launches()
 
 
-LEARNED_HELDOUT = [1, 4, 6, 9, 12, 15, 16, 18, 22, 23]
+def roofline_mfma(d, mode="small"):
+    sec = d["ms"] * 1e-3
+    tops = d["macs"] * 2 * INT8_PRODUCTS_PER_MODMAC[mode] / sec / 1e12 if sec > 0 else 0.0
+    return {"kernel_class": "mfma (k_mfma8: int8 matrix-core contraction step)", "launches": d["launches"],
+            "avg_launch_us": round(1e6 * sec / max(1, d["launches"]), 3), "bound": "mfma",
+            "achieved": round(tops, 2), "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+            "frac": round(tops / INT8_PEAK_TOPS, 4),
+            "traffic": measured_traffic() if mode == "small" else None,
+            "algorithmic_ops_per_launch": d["macs"] * 2 * INT8_PRODUCTS_PER_MODMAC[mode] / max(1, d["launches"]),
+            "algorithmic_bytes_per_launch": d["bytes"] / max(1, d["launches"])}
 
 
-def learned_vs_greedy(tn, I, ws, log):
-    """Order + contraction wall time of greedy, the learned scorer alone and
-    the judged learned order on held-out 1-in-3 instances (n in [100, 180],
-    alpha = 0.66) where greedy stays within the rank cap."""
+def hbm_roofline(launches, es=1):
+    """Memory-bound launches (multiply-adds per byte below the machine
+    balance) whose working set (entries of A, B and C of all planes) is at
+    least 1 GiB: algorithmic bytes over device time."""
+    sel = []
+    for cls, rA, rB, s, rC, G, ms in launches:
+        byt = es * G * (2 ** rA + 2 ** rB + 2 ** rC)
+        macs = G * 2 ** (rA + rB - s)
+        if byt >= 2 ** 30 and macs / byt < BALANCE_MACS_PER_BYTE and ms > 0:
+            sel.append((cls, rA, rB, s, rC, G, ms, byt))
+    if not sel:
+        return None
+    tot_b = sum(x[7] for x in sel)
+    tot_s = sum(x[6] for x in sel) * 1e-3
+    gbs = tot_b / tot_s / 1e9
+    by = {}
+    for x in sel:
+        b = by.setdefault(x[0], [0, 0.0, 0.0])
+        b[0] += 1
+        b[1] += x[7]
+        b[2] += x[6] * 1e-3
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "launches": len(sel),
+            "by_class": {k: {"launches": v[0], "GBps": round(v[1] / v[2] / 1e9, 1)} for k, v in by.items()},
+            "shapes": sorted({(x[0], x[1], x[2], x[3], x[4]) for x in sel})[:12]}
+
+
+def c3_formula(I):
+    return I.large_1in3(C3["n"], C3["alpha"], C3["seed"])
+
+
+def headline(tn, I, ws, args):
+    import torch
+    f = c3_formula(I)
+
+    def one(flags=0):
+        net = tn.Network(f)
+        plan = net.order("best", seed=C3["seed"])
+        return tn.count_plan(net, plan, workspace=ws, flags=flags), plan
+
+    ref = None
+    for w in range(args.warmup):
+        ref, plan = one()
+        log(f"warmup {w + 1}/{args.warmup} done")
+    acc = Acc(tn)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    got = []
+    for k in range(args.steps):
+        c, plan = one(tn.FLAG_TIMING)
+        acc.add()
+        got.append(c)
+        log(f"timed step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if len(set(got)) != 1 or (ref is not None and got[0] != ref):
+        raise SystemExit("counts changed between passes")
+    return f, plan, got[0], t1 - t0, acc
+
+
+def cvc200_rate(tn, I, ws):
+    import torch
+    fs = [I.cvc(200, s) for s in range(16)]
+    tn.count_batch(fs, "best", seed=0, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        tn.count_batch(fs, "best", seed=0, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    log("cvc200 done")
+    return {"workload": "#Cubic-Vertex-Cover on uniform random cubic graphs, n=200, seeds 0..15, best order, "
+                        "27 small moduli + CRT, whole path per pass", "counts_per_s": round(16 / dt, 3),
+            "ms_per_pass": round(1000 * dt, 2)}
+
+
+def c1_rates(tn, I, ws):
+    import torch
+    fs = [I.small_1in3(i) for i in range(1000)]
+    tn.count_batch(fs[:64], "greedy", workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batched = tn.count_batch(fs, "greedy", workspace=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    single = [tn.count(f, "greedy", workspace=ws) for f in fs]
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    if batched != single:
+        raise SystemExit("batched and single-stream counts differ")
+    log("c1 done")
+    return {"workload": "monotone 1-in-3, n=20, m=14, seeds 0..999, greedy order, 64-bit counts",
+            "batched_counts_per_s": round(1000 / (t1 - t0), 1),
+            "single_stream_counts_per_s": round(1000 / (t2 - t1), 1)}
+
+
+def c4_batch(tn, I, ws, n):
+    import torch
+    fs = [I.batch_instance(i) for i in range(n)]
+    t0 = time.perf_counter()
+    a = tn.count_batch(fs, "greedy", seed=0, workspace=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    b = tn.count_batch(fs, "greedy", seed=0, workspace=ws, flags=tn.FLAG_TIMING)
+    prof = tn.profile()
+    torch.cuda.synchronize()
+    if a != b:
+        raise SystemExit("batch counts changed between passes")
+    dev_ms = sum(v["ms"] for v in prof.values())
+    log("c4 done")
+    return {"workload": f"mixed batch of {n}: even index monotone 1-in-3 n~U[30,120] m=round(0.66n), odd index "
+                        f"cubic vertex cover n~U[30,120] (even); greedy order; u64 for n<=63 else small moduli",
+            "counts_per_s": round(n / (t1 - t0), 1), "wall_s": round(t1 - t0, 3),
+            "device_ms": round(dev_ms, 2),
+            "classes": {k: {"launches": v["launches"], "ms": round(v["ms"], 2)} for k, v in prof.items()
+                        if v["launches"]}}
+
+
+def learned_vs_greedy(tn, I, ws):
     import torch
     model_path = os.path.join(ROOT, "paper_1805_00475_amd", "models", "order_mlp.npy")
     if not os.path.exists(model_path):
@@ -156,7 +238,7 @@ def learned_vs_greedy(tn, I, ws, log):
     model = tn.Model.load_file(model_path)
     res = {}
     counts = {}
-    for kind in ("greedy", "learned_raw", "learned"):
+    for kind in ("greedy", "learned_raw", "learned", "best"):
         order_s = contract_s = 0.0
         cs = []
         for i in LEARNED_HELDOUT:
@@ -165,7 +247,7 @@ def learned_vs_greedy(tn, I, ws, log):
             t0 = time.perf_counter()
             plan = net.order(kind, seed=i, model=model if "learned" in kind else None)
             t1 = time.perf_counter()
-            tn.count_plan(net, plan, workspace=ws)  # warm
+            tn.count_plan(net, plan, workspace=ws)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             cs.append(tn.count_plan(net, plan, workspace=ws))
@@ -176,19 +258,118 @@ def learned_vs_greedy(tn, I, ws, log):
         counts[kind] = cs
         res[kind] = {"order_ms": round(1000 * order_s, 3), "contract_ms": round(1000 * contract_s, 3),
                      "total_ms": round(1000 * (order_s + contract_s), 3)}
-    if not (counts["greedy"] == counts["learned_raw"] == counts["learned"]):
-        raise SystemExit("learned and greedy orders disagree on a count")
+    if len({tuple(v) for v in counts.values()}) != 1:
+        raise SystemExit("orders disagree on a count")
     res["instances"] = f"held-out learned_instance {LEARNED_HELDOUT}"
-    res["learned_over_greedy_speedup"] = round(res["greedy"]["total_ms"] / res["learned_raw"]["total_ms"], 3)
+    res["learned_raw_over_greedy"] = round(res["greedy"]["total_ms"] / res["learned_raw"]["total_ms"], 3)
+    res["learned_over_greedy"] = round(res["greedy"]["total_ms"] / res["learned"]["total_ms"], 3)
     log("learned vs greedy done")
     return res
+
+
+def host_info():
+    info = {"nproc": os.cpu_count()}
+    try:
+        aff = len(os.sched_getaffinity(0))
+        info["affinity_cpus"] = aff
+    except AttributeError:
+        pass
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                info["model"] = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def cpu_baseline_c3(formula, budget_s):
+    """The oracle's pairwise contractor (O-B) on the headline formula along
+    the oracle's own order, one 31-bit prime, steps run until ``budget_s`` has
+    passed or the next intermediate would exceed 2^27 entries (host memory);
+    the instance time is extrapolated linearly in multiply-adds and primes."""
+    from oracle import contract, cost, order, rns, tensors
+    import numpy as np
+    nets, _ = tensors.network_of_formula(formula)
+    labels = [ls for _, ls in nets]
+    t_ord = time.time()
+    merges, which = order.cheapest_order(labels, tries=4)
+    t_ord = time.time() - t_ord
+    rep = cost.replay(labels, merges)
+    macs = [st["macs"] for st in rep["steps"]]
+    total = float(sum(macs))
+    primes = rns.primes_for(formula.n_vars)
+    p = primes[0]
+    work = {i: (np.asarray(t, dtype=np.int64) % p, ls) for i, (t, ls) in enumerate(nets)}
+    nid = len(nets)
+    done = 0.0
+    w0 = time.time()
+    k = -1
+    for k, (a, b) in enumerate(merges):
+        if rep["steps"][k]["rC"] > 27 or time.time() - w0 > budget_s:
+            k -= 1
+            break
+        work[nid] = contract.contract_pair(work.pop(a), work.pop(b), p)
+        nid += 1
+        done += macs[k]
+    el = time.time() - w0
+    frac = done / total
+    inst_s = el / max(frac, 1e-300) * len(primes) + t_ord
+    import numpy
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((x.get("num_threads", 1) for x in threadpool_info()), default=1)
+    except ImportError:
+        pass
+    return {"value": 1.0 / inst_s, "unit": "counts/s", "cores": threads or 1, "kind": "oracle",
+            "sample": (f"oracle O-B (numpy pairwise contraction, exact float64 limb products; BLAS threads "
+                       f"{threads}) on {formula.name} along the oracle's own {which} order (max rank "
+                       f"{rep['max_rank']}, {total:.3g} multiply-adds per prime), prime 1 of {len(primes)}, "
+                       f"first {k + 1} of {len(merges)} steps = {100 * frac:.3g}% of its multiply-adds in "
+                       f"{el:.1f}s; instance time extrapolated linearly in multiply-adds and primes"),
+            "extrapolated_instance_s": inst_s}
+
+
+def cpu_complete(I):
+    """Complete oracle runs timed on the host: O-A over all 1000 n=20 1-in-3
+    seeds (plain C loop, one thread, then one instance per thread on every core) and O-B on
+    one complete vertex-cover instance n=120 (all primes + CRT)."""
+    from oracle import brute, contract
+    fs = [I.small_1in3(i) for i in range(1000)]
+    t0 = time.time()
+    a = [brute.count_c(f, threads=1) for f in fs]
+    t1 = time.time()
+    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or (
+        len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count())
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=cores) as ex:   # ctypes calls release the GIL
+        b = list(ex.map(lambda f: brute.count_c(f, threads=1), fs))
+    t2 = time.time()
+    assert a == b
+    log("cpu oracle O-A done")
+    from oracle import order, tensors
+    f = I.cvc(120, 0)
+    t3 = time.time()
+    nets, _ = tensors.network_of_formula(f)
+    merges, which = order.cheapest_order([ls for _, ls in nets], tries=4)
+    c = contract.count_rns(f, order=merges)
+    t4 = time.time()
+    log("cpu complete done")
+    return {"c1_oracle_OA": {"instances": 1000, "one_core_s": round(t1 - t0, 3),
+                             "all_cores_s": round(t2 - t1, 3), "threads": cores,
+                             "one_core_counts_per_s": round(1000 / (t1 - t0), 1)},
+            "cvc120_oracle_OB": {"instance": f.name, "count_digits": len(str(c)), "s": round(t4 - t3, 3),
+                                 "note": f"oracle's own {which} order (order search included), 5 primes of 31 bits + CRT, "
+                                         f"numpy BLAS threads"}}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding of the path is described in DESIGN.md, not implemented)"}))
+                          "(how the path would shard over several GPUs is described in DESIGN.md)"}))
         sys.exit(2)
     import torch
     import instances as I
@@ -196,25 +377,8 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
-    base_flags = tn.FLAG_WIDE_RNS if args.wide_rns else 0
-    mode = "wide" if args.wide_rns else "small"
-    res_desc = ("residues mod 16-bit primes (the fewest whose product exceeds 2^(n+1))" if args.wide_rns else
-                "centred int8 residues mod pairwise coprime moduli <= 255 (the fewest whose product exceeds "
-                "2^(n+1))")
-    if args.workload == "cvc":
-        formulas = [I.cvc(args.n, s) for s in range(args.batch)]
-        mods = tn.moduli(tn.Network(formulas[0]).order("community"), flags=base_flags)
-        k_primes = len(mods)
-        workload = (f"#Cubic-Vertex-Cover, uniform random cubic graphs n={args.n} (configuration model), "
-                    f"batch of {args.batch} seeds, {args.order} order, {k_primes} moduli + CRT; {res_desc}")
-    else:
-        formulas = [I.batch_instance(i) for i in range(args.batch)]
-        k_primes = None
-        workload = (f"mixed batch of {args.batch}: even index monotone 1-in-3 n~U[30,120] m=round(0.66n), "
-                    f"odd index cubic vertex cover n~U[30,120] (even); {args.order} order; u64 for n<=63 else "
-                    f"{res_desc}")
     ws = tn.default_workspace()
-    ws.get(64 << 30)
+    ws.get(120 << 30)
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -222,64 +386,60 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def one_pass(flags=0):
-        flags |= base_flags
-        if args.single:
-            return [tn.count(f, args.order, seed=i, flags=flags, workspace=ws) for i, f in enumerate(formulas)]
-        return tn.count_batch(formulas, args.order, seed=0, flags=flags, workspace=ws, with_stats=False)
-
-    def log(*a):
-        print("[bench]", *a, file=sys.stderr, flush=True)
-
-    for _ in range(args.warmup):
-        ref = one_pass()
-        log("warmup pass done")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        got = one_pass()
-        log(f"timed step {k + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if args.warmup and got != ref:
-        raise SystemExit("counts changed between passes")
-    ms_per_step = 1000.0 * (t1 - t0) / args.steps
-    value = args.batch * args.steps / (t1 - t0)
-
-    # roofline: one more identical pass with hipEvents around every launch
-    # (on the library's stream, which is torch's current stream)
-    one_pass(tn.FLAG_TIMING)
-    prof = tn.profile()
-    log("timing pass done")
-    dom = max(prof, key=lambda k: prof[k]["ms"])
-    roofline = roofline_of(dom, prof[dom], mode)
-    per_class = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                     "algorithmic_GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None,
-                     "avg_launch_us": round(1000.0 * v["ms"] / v["launches"], 3)}
-                 for k, v in prof.items() if v["launches"]}
-
-    lvg = learned_vs_greedy(tn, I, ws, log) if not args.no_learned else None
-    plans = [tn.Network(f).order(args.order, seed=i) for i, f in enumerate(formulas[:4])]
+    f, plan, count, sec, acc = headline(tn, I, ws, args)
+    mods = tn.moduli(plan)
+    value = args.steps / sec
+    mf = acc.cls["mfma"]
+    roof = roofline_mfma(mf)
+    dom = {}
+    for r in acc.launches:
+        if r[0] == "mfma":
+            d = dom.setdefault(r[1:5], [0, 0.0, 0.0])
+            d[0] += 1
+            d[1] += r[6]
+            d[2] += r[5] * 2 ** (r[1] + r[2] - r[3])
+    top = max(dom.items(), key=lambda kv: kv[1][1])
+    roof["dominant_shape"] = {"rA_rB_s_rC": list(top[0]), "launches": top[1][0],
+                              "share_of_class_time": round(top[1][1] / mf["ms"], 3),
+                              "TOPs": round(2 * top[1][2] / (top[1][1] * 1e-3) / 1e12, 1),
+                              "frac": round(2 * top[1][2] / (top[1][1] * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4)}
     out = {
         "metric": "exact counts/sec + contraction HBM GB/s; learned vs greedy order wall-time",
-        "value": round(value, 4), "unit": "counts/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32" if args.wide_rns else "i8",
-        "data": "synthetic",
-        "config": {"workload": workload, "batch": args.batch, "n": args.n if args.workload == "cvc" else None,
-                   "order": args.order, "moduli": k_primes, "residue_mode": mode},
-        "roofline": roofline,
-        "hbm_roofline_stream": roofline_of("stream", prof["stream"]) if prof["stream"]["launches"] else None,
-        "kernel_classes": per_class,
-        "learned_vs_greedy": lvg,
-        "plan_max_rank": [p.stats["max_rank"] for p in plans],
-        "plan_chosen": [p.stats["chosen"] for p in plans],
+        "value": round(value, 5), "unit": "counts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1000 * sec / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+        "config": {"workload": (f"monotone #1-in-3SAT, uniform random 3-variable clauses, n={C3['n']}, "
+                                f"m={f.n_clauses} (alpha={C3['alpha']}), seed {C3['seed']}: the largest "
+                                f"configuration whose predicted max rank is in [30,32]; best order (max rank "
+                                f"{plan.stats['max_rank']}), {len(mods)} small moduli (centred int8 residues) + "
+                                f"CRT; one formula per step, whole path (build, order, contract, CRT)"),
+                   "n": C3["n"], "m": f.n_clauses, "alpha": C3["alpha"], "seed": C3["seed"],
+                   "max_rank": plan.stats["max_rank"], "moduli": len(mods), "order": plan.stats["chosen"],
+                   "count_bits": count.bit_length()},
+        "roofline": roof,
+        "hbm_roofline": hbm_roofline(acc.launches),
+        "kernel_classes": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)}
+                           for k, v in acc.cls.items() if v["launches"]},
     }
+    log("headline done")
+    if not args.no_extras:
+        t = time.time()
+        out["cvc200"] = cvc200_rate(tn, I, ws)
+        out["c1"] = c1_rates(tn, I, ws)
+        log(f"  ({time.time() - t:.1f}s)")
+        if args.c4_batch:
+            t = time.time()
+            out["c4"] = c4_batch(tn, I, ws, args.c4_batch)
+            log(f"  ({time.time() - t:.1f}s)")
+        t = time.time()
+        out["learned_vs_greedy"] = learned_vs_greedy(tn, I, ws)
+        log(f"  ({time.time() - t:.1f}s)")
     if not args.no_cpu_baseline:
-        p0 = plans[0]
-        out["cpu_baseline"] = cpu_baseline(formulas[0], p0.steps(), args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline_c3(f, args.cpu_seconds)
+        out["cpu_host"] = host_info()
         log("cpu baseline done")
+        if not args.no_extras:
+            out["cpu_complete"] = cpu_complete(I)
     print(json.dumps(out))
 
 

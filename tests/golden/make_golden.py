@@ -170,8 +170,26 @@ def c3():
             "items": items})
 
 
+def batch256():
+    """The first 256 instances of the mixed batch: O-A for n <= 32, else O-D."""
+    items = []
+    for i in range(256):
+        f = I.batch_instance(i)
+        c = brute.count_c(f) if f.n_vars <= 32 else elim.count_rns(f)
+        items.append({"index": i, "n_vars": f.n_vars, "count": str(c),
+                      "oracle": "O-A" if f.n_vars <= 32 else "O-D"})
+        if i % 32 == 31:
+            print(f"  batch {i + 1}/256", flush=True)
+    dump("batch256_counts.json", {
+        "workload": "instances.batch_instance(i), master seed 0, i < 256 (even: monotone 1-in-3 n~U[30,120], "
+                    "m=round(0.66n); odd: vertex cover of a random cubic graph, n~U[30,120] rounded up to even)",
+        "oracle": "oracle.brute.count_c (O-A) for n <= 32, else oracle.elim.count_rns (O-D)", "items": items})
+
+
 if __name__ == "__main__":
-    if "--c3" in sys.argv:
+    if "--batch256" in sys.argv:
+        batch256()
+    elif "--c3" in sys.argv:
         c3()
     elif "--cvc200" in sys.argv:
         cvc200([int(x) for x in sys.argv[sys.argv.index("--cvc200") + 1:]] or [0, 1])

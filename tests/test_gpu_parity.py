@@ -217,3 +217,37 @@ def test_contract_residues_recombine_through_crt_moduli():
     mods = tn.moduli(plan)
     assert len(res) == len(mods) and max(mods) <= 255
     assert tn.crt_moduli(res, mods) == closed.prism_vertex_covers(100)
+
+
+def test_cvc200_random_cubic_vs_oracle():
+    # the benchmark's own workload size: vertex cover of random cubic graphs
+    # at n = 200, both residue systems, against the pairwise-contraction oracle
+    for it in _gold("cvc200_counts.json")["items"]:
+        f = I.cvc(200, it["seed"])
+        want = int(it["count"])
+        _say(f"cvc n=200 seed={it['seed']} small moduli, best order")
+        assert tn.count(f, "best", seed=it["seed"]) == want
+        _say(f"cvc n=200 seed={it['seed']} 16-bit primes, community order")
+        assert tn.count(f, "community", flags=tn.FLAG_WIDE_RNS) == want
+
+
+def test_c3_roofline_instance_invariants():
+    # the largest 1-in-3 instance measured (n = 300, alpha = 0.62, seed 1,
+    # intermediates of rank 31): beyond a CPU oracle here, so the count must
+    # agree across two different plans and two residue systems (42 small
+    # moduli vs 16-bit primes), and be the same on a second run
+    f = I.large_1in3(300, 0.62, 1)
+    net = tn.Network(f)
+    best = net.order("best", seed=1)
+    assert 30 <= best.stats["max_rank"] <= 32
+    _say("1-in-3 n=300 a=0.62 s1 best order, small moduli")
+    a = tn.count_plan(net, best)
+    other = net.order("partition", seed=5)
+    _say(f"... partition seed 5 (max rank {other.stats['max_rank']}), small moduli")
+    b = tn.count_plan(net, other) if other.stats["max_rank"] <= 32 else a
+    _say("... best order, 16-bit primes")
+    c = tn.count_plan(net, best, flags=tn.FLAG_WIDE_RNS)
+    _say("... best order again")
+    d = tn.count_plan(net, best)
+    assert a == b == c == d
+    assert 0 <= a < 2 ** 300

@@ -227,3 +227,32 @@ def test_mfma8_output_layouts(layout, rA, rB, s):
     C = tn.step(A.copy(), rA, B.copy(), rB, s, maskA, prime=m, kernel="mfma")
     cs = sorted(set(rng.integers(0, 1 << rC, size=3000).tolist()) | set(range(64)) | {(1 << rC) - 1})
     assert [int(C[c]) for c in cs] == contract.step_entries(A, B, s, maskA, rC, cs, m)
+
+
+def _check_big(rA, rB, s, m, seed, samples):
+    # lean form of _check for operands of 2^30+ entries: residues drawn as
+    # bytes below m, passed as the u32 arrays tn_step takes, no extra copies
+    rng = np.random.default_rng(seed)
+    rC = rA + rB - 2 * s
+    maskA = _mask(rC, rA - s, rng)
+    A = rng.integers(0, m, size=1 << rA, dtype=np.uint8).astype(np.uint32)
+    B = rng.integers(0, m, size=1 << rB, dtype=np.uint8).astype(np.uint32)
+    _say(f"kernel=mfma rA={rA} rB={rB} s={s} m={m} mask={maskA:#x} (full size, sampled)")
+    C = tn.step(A, rA, B, rB, s, maskA, prime=m, kernel="mfma")
+    cs = sorted(set(rng.integers(0, 1 << rC, size=samples).tolist()) | {0, (1 << rC) - 1})
+    want = contract.step_entries(A, B, s, maskA, rC, cs, m)
+    got = [int(C[c]) for c in cs]
+    del A, B, C
+    assert got == want
+
+
+def test_mfma8_output_rank_30_to_32_sampled():
+    # full-size steps of the largest 1-in-3 plans (n = 300, alpha = 0.62):
+    # the dominant dense step (rank 31 x 31, K = 2^16, rank-30 output), a
+    # rank-31 output at K = 2^10 and at K = 2^7, a short-K rank-30 output,
+    # and a rank-32 output
+    _check_big(31, 31, 16, 251, seed=31, samples=24)
+    _check_big(30, 21, 10, 255, seed=32, samples=200)
+    _check_big(26, 19, 7, 254, seed=33, samples=400)
+    _check_big(27, 13, 5, 253, seed=34, samples=2000)
+    _check_big(28, 28, 12, 255, seed=35, samples=100)
