@@ -75,3 +75,17 @@ def test_batch_matches_single_counts_large():
     fs = [I.cvc(120, it["seed"]) for it in cvc]
     _say("batch of n=120 cubic vertex cover")
     assert _run(fs, "best") == [int(it["count"]) for it in cvc]
+
+
+def test_batch_4096_first_256_match_oracle():
+    # the benchmark's full mixed batch of 4096 instances, greedy order, in one
+    # call; the first 256 counts against the oracle (O-A for n <= 32, else
+    # O-D), the rest checked for repeatability across two calls
+    with open(os.path.join(GOLD, "batch256_counts.json")) as fh:
+        want = [int(it["count"]) for it in json.load(fh)["items"]]
+    fs = [I.batch_instance(i) for i in range(4096)]
+    _say("batch of 4096 mixed instances, greedy, hipGraph")
+    got = _run(fs, "greedy", ws_bytes=64 << 30)
+    assert got[:256] == want
+    _say("batch of 4096 again, direct launches")
+    assert _run(fs, "greedy", flags=tn.FLAG_NO_GRAPH, ws_bytes=64 << 30) == got
