@@ -36,4 +36,12 @@ from .gen import (  # noqa: F401
     FAMILY_CUBIC_1IN3,
     OR,
     EXACTLY_ONE,
+    XOR,
+    exactly_one_k,
+    xor_k,
+    CSP,
+    coloring_csp,
+    hardcore_csp,
+    random_csp,
+    table_csp,
 )

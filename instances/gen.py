@@ -30,6 +30,7 @@ from typing import List, Sequence, Tuple
 
 OR = 0
 EXACTLY_ONE = 1
+XOR = 2
 
 _M64 = (1 << 64) - 1
 
@@ -339,3 +340,106 @@ def cubic_1in3(n_vertices: int, index: int) -> Formula:
     rng = Rng(instance_seed(FAMILY_CUBIC_1IN3, (n_vertices << 20) | index))
     return perfect_matching_formula(cubic_graph(n_vertices, rng), n_vertices,
                                     name=f"cubic1in3-N{3 * n_vertices // 2}-s{index}")
+
+
+# --------------------------------------------------------------------------
+# other clause types and general weighted constraint networks (Sec. 4)
+# --------------------------------------------------------------------------
+
+def exactly_one_k(n: int, m: int, k: int, rng: Rng, name: str = "") -> Formula:
+    """Monotone 1-in-k: m clauses, each k distinct variables drawn uniformly
+    (a partial Fisher-Yates draw)."""
+    if m > 0 and n < k:
+        raise ValueError("need n >= k")
+    f = Formula(n, name=name)
+    for _ in range(m):
+        pool = list(range(n))
+        cl = []
+        for j in range(k):
+            t = j + rng.below(n - j)
+            pool[j], pool[t] = pool[t], pool[j]
+            cl.append(pool[j] + 1)
+        f.clauses.append((EXACTLY_ONE, cl))
+    return f
+
+
+def xor_k(n: int, m: int, k: int, rng: Rng, name: str = "") -> Formula:
+    """Random k-XORSAT: m parity clauses over k distinct uniform variables,
+    each literal negated with probability 1/2 (a random right-hand side)."""
+    f = exactly_one_k(n, m, k, rng, name=name)
+    f.clauses = [(XOR, [v if rng.coin() else -v for v in cl]) for _, cl in f.clauses]
+    return f
+
+
+@dataclass
+class CSP:
+    """A weighted constraint network: variable v (1-based) takes values
+    0..domain[v-1]-1; constraint c has a scope (variables, repeats allowed)
+    and a table of non-negative integer weights over the scope's values,
+    row-major with the first scope variable slowest. The count is the sum over
+    all assignments of the product of the constraints' weights."""
+
+    n_vars: int
+    domain: List[int]
+    constraints: List[Tuple[Tuple[int, ...], List[int]]] = field(default_factory=list)
+    name: str = ""
+
+    def arrays(self):
+        """(domain, scope_ptr, scope, table_ptr, weights) in the C-ABI layout."""
+        sp, sc, tp, w = [0], [], [0], []
+        for scope, table in self.constraints:
+            sc.extend(int(v) for v in scope)
+            sp.append(len(sc))
+            w.extend(int(x) for x in table)
+            tp.append(len(w))
+        return list(self.domain), sp, sc, tp, w
+
+
+def coloring_csp(edges: Sequence[Tuple[int, int]], n: int, q: int, name: str = "") -> CSP:
+    """Proper q-colourings of a graph: domain q, one 'differ' table per edge."""
+    table = [1 if a != b else 0 for a in range(q) for b in range(q)]
+    return CSP(n, [q] * n, [((u + 1, v + 1), list(table)) for u, v in edges], name=name)
+
+
+def hardcore_csp(edges: Sequence[Tuple[int, int]], n: int, lam: int, name: str = "") -> CSP:
+    """Independent sets weighted by lam^size: a unary table [1, lam] per vertex
+    and a 'not both' table per edge."""
+    cons = [((v + 1,), [1, lam]) for v in range(n)]
+    cons += [((u + 1, v + 1), [1, 1, 1, 0]) for u, v in edges]
+    return CSP(n, [2] * n, cons, name=name)
+
+
+def random_csp(n: int, m: int, rng: Rng, max_domain: int = 5, max_arity: int = 3, max_weight: int = 3,
+               zero_prob: float = 0.3, name: str = "") -> CSP:
+    """Mixed domains 1..max_domain, constraints of arity 0..max_arity over
+    uniform variables (repeats allowed), weights uniform in 1..max_weight or
+    0 with probability about zero_prob."""
+    dom = [1 + rng.below(max_domain) for _ in range(n)]
+    cons = []
+    zero_thresh = int(zero_prob * 1000)
+    for _ in range(m):
+        ar = rng.below(max_arity + 1)
+        scope = tuple(1 + rng.below(n) for _ in range(ar))
+        size = 1
+        for v in scope:
+            size *= dom[v - 1]
+        table = [0 if rng.below(1000) < zero_thresh else 1 + rng.below(max_weight) for _ in range(size)]
+        cons.append((scope, table))
+    return CSP(n, dom, cons, name=name)
+
+
+def table_csp(formula: Formula) -> CSP:
+    """The boolean CSP of a formula: one 0/1 truth table per clause over its
+    literal occurrences' variables (OR, exactly-one and parity rules,
+    negation reversing a value)."""
+    import itertools
+    cons = []
+    for kind, lits in formula.clauses:
+        scope = tuple(abs(l) for l in lits)
+        table = []
+        for vals in itertools.product((0, 1), repeat=len(lits)):
+            t = sum(1 for l, x in zip(lits, vals) if (x == 1) == (l > 0))
+            ok = t >= 1 if kind == OR else t == 1 if kind == EXACTLY_ONE else t % 2 == 1
+            table.append(1 if ok else 0)
+        cons.append((scope, table))
+    return CSP(formula.n_vars, [2] * formula.n_vars, cons, name=formula.name + "-table")

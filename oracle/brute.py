@@ -5,9 +5,11 @@ The count of a formula F over n boolean variables is
 (the partition function of Eq. 2 in the zero-temperature limit, Sec. 2.1).
 A literal +v is true when x_v = 1 and -v when x_v = 0 (negated indices,
 Sec. 2.1). An OR clause is satisfied when at least one literal is true
-(Eq. 3); an exactly-one clause when precisely one literal is true (Eq. 6).
-An empty OR clause is therefore never satisfied, and an empty exactly-one
-clause neither (zero literals are true, not one).
+(Eq. 3); an exactly-one clause when precisely one literal is true (Eq. 6);
+a parity (XOR) clause when an odd number of literals is true (#XORSAT, one
+of the other clause types Sec. 4 names). Literals are counted per occurrence.
+An empty OR clause is therefore never satisfied, and an empty exactly-one or
+parity clause neither (zero literals are true, not one, and zero is even).
 
 Variable v (1-based) is bit v-1 of the assignment index x.
 """
@@ -21,6 +23,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 OR = 0
 EXACTLY_ONE = 1
+XOR = 2
 
 
 def clause_true_count(x: np.ndarray, lits) -> np.ndarray:
@@ -48,6 +51,8 @@ def count_numpy(formula, chunk_bits: int = 20) -> int:
                 ok &= t >= 1
             elif kind == EXACTLY_ONE:
                 ok &= t == 1
+            elif kind == XOR:
+                ok &= (t & 1) == 1
             else:
                 raise ValueError(f"unknown clause kind {kind}")
         total += int(ok.sum())

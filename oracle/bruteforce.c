@@ -1,7 +1,8 @@
 /* O-A in plain C: enumerate every assignment x in {0,1}^n and count those
  * satisfying every clause -- the zero-temperature partition function of
- * Eq. 2 (Sec. 2.1) with OR clauses (Eq. 3), exactly-one clauses (Eq. 6) and
- * negated literals (Sec. 2.1). Test infrastructure only.
+ * Eq. 2 (Sec. 2.1) with OR clauses (Eq. 3), exactly-one clauses (Eq. 6),
+ * parity clauses (kind 2: an odd number of true literals) and negated
+ * literals (Sec. 2.1). Test infrastructure only.
  *
  * Variable v (1-based) is bit v-1 of x. For clause c, pos_c / neg_c are the
  * bit masks of its positive / negated literals; the literals true under x are
@@ -28,7 +29,7 @@ int bf_count(int n, int m, const int32_t* clause_ptr, const int32_t* lits,
         lneg[i] = lits[i] < 0;
     }
     for (int c = 0; c < m; ++c)
-        if (kinds[c] > 1 || clause_ptr[c + 1] < clause_ptr[c]) { free(lmask); free(lneg); return -1; }
+        if (kinds[c] > 2 || clause_ptr[c + 1] < clause_ptr[c]) { free(lmask); free(lneg); return -1; }
     /* clauses whose variables are all distinct use a popcount test on two
      * masks; a clause naming one variable twice keeps the per-literal loop */
     uint64_t* pos = (uint64_t*)calloc(m + 1, sizeof(uint64_t));
@@ -59,7 +60,7 @@ int bf_count(int n, int m, const int32_t* clause_ptr, const int32_t* lits,
                     t += lneg[i] ? !bit : bit;
                 }
             }
-            ok = kinds[c] == 0 ? (t >= 1) : (t == 1);
+            ok = kinds[c] == 0 ? (t >= 1) : kinds[c] == 1 ? (t == 1) : (t & 1);
         }
         total += (uint64_t)ok;
     }

@@ -25,6 +25,7 @@ from . import rns
 
 OR = 0
 EXACTLY_ONE = 1
+XOR = 2
 
 Factor = Tuple[np.ndarray, Tuple[int, ...]]
 
@@ -36,7 +37,7 @@ def clause_factor(kind: int, lits: Sequence[int], dtype=object) -> Factor:
     for idx in itertools.product((0, 1), repeat=len(vs)):
         val = dict(zip(vs, idx))
         true = sum(1 for l in lits if (val[abs(l)] == 1) == (l > 0))
-        ok = (true >= 1) if kind == OR else (true == 1)
+        ok = (true >= 1) if kind == OR else (true == 1) if kind == EXACTLY_ONE else (true % 2 == 1)
         t[idx] = 1 if ok else 0
     return t, vs
 

@@ -9,6 +9,8 @@ index k of the array being index i_{k+1} of the paper's notation.
   d >= 1) gives the scalar 2 for d = 0 and [1, 1] for d = 1.
 * OR (Eq. 3): 0 when all (effective) indices are 0, else 1.
 * exactly-one (Eq. 6): 1 when the (effective) indices sum to 1, else 0.
+* parity (XOR, a clause type of Sec. 4): 1 when the (effective) indices sum
+  to an odd number, else 0.
 * A negated literal reverses the values of its index (Sec. 2.1): the
   effective index is 1 - i.
 """
@@ -20,6 +22,7 @@ import numpy as np
 
 OR = 0
 EXACTLY_ONE = 1
+XOR = 2
 
 
 def copy_tensor(d: int) -> np.ndarray:
@@ -42,6 +45,8 @@ def clause_tensor(kind: int, negated) -> np.ndarray:
             val = 0 if all(e == 0 for e in eff) else 1
         elif kind == EXACTLY_ONE:
             val = 1 if sum(eff) == 1 else 0
+        elif kind == XOR:
+            val = sum(eff) % 2
         else:
             raise ValueError(f"unknown clause kind {kind}")
         t[idx] = val
