@@ -61,8 +61,13 @@ typedef enum {
 /* Most primes one contraction may use (counts up to ~2^2000). */
 #define TN_MAX_PRIMES 128
 
-/* Clause kinds: OR (Eq. 3) and exactly-one (Eq. 6, with negation allowed). */
-typedef enum { TN_CLAUSE_OR = 0, TN_CLAUSE_EXACTLY_ONE = 1 } tn_clause_kind;
+/* Clause kinds: OR (Eq. 3), exactly-one (Eq. 6, with negation allowed; any
+ * number of literals: #1-in-k SAT) and parity (#XORSAT, one of the other
+ * clause types Sec. 4 names: satisfied when an odd number of literals is
+ * true). Literals are counted per occurrence. */
+typedef enum { TN_CLAUSE_OR = 0, TN_CLAUSE_EXACTLY_ONE = 1, TN_CLAUSE_XOR = 2 } tn_clause_kind;
+/* Largest domain of a variable of a constraint network (tn_build_csp). */
+#define TN_MAX_DOMAIN 256
 
 /* A formula. Variables are 1..n_vars. Clause c owns literals
  * lits[clause_ptr[c] .. clause_ptr[c+1]-1]; a literal is +v or -v
@@ -136,6 +141,53 @@ typedef struct {
  * more than TN_MAX_INIT_RANK times or a clause has more literals. */
 tn_status tn_build(const tn_formula* f, tn_network** out);
 void tn_network_free(tn_network* net);
+
+/* Degree reduction (Sec. 4: splitting long clauses, COPY tensors as rings of
+ * rank-3 tensors), flags of tn_build_ex and tn_build_csp. RING_COPY: a
+ * boolean COPY tensor of rank d > 3 becomes d rank-3 COPY tensors on a ring
+ * of d new bonds, each holding one of the original bonds. SPLIT_CLAUSES: an
+ * OR, exactly-one or parity clause of k > 3 literals becomes a chain of k - 2
+ * rank-3 tensors linked by k - 3 new bonds that carry the clause's running
+ * state ("some literal true", "one literal true so far", parity); the count
+ * is unchanged and no initial tensor keeps a rank above 3 (other than
+ * tables of tn_build_csp). New tensors follow the original ones. */
+#define TN_BUILD_RING_COPY 1
+#define TN_BUILD_SPLIT_CLAUSES 2
+/* tn_build, then the degree reduction of ``flags``. */
+tn_status tn_build_ex(const tn_formula* f, uint32_t flags, tn_network** out);
+
+/* A weighted constraint network over variables of any domain (Sec. 4:
+ * non-boolean and mixed domains, weighted #CSP): variable v (1..n_vars)
+ * takes the values 0..domain[v-1]-1, 1 <= domain[v-1] <= TN_MAX_DOMAIN (NULL:
+ * every variable boolean). Constraint c has a scope scope[scope_ptr[c] ..
+ * scope_ptr[c+1]-1] of variables (a variable may repeat; an empty scope is
+ * a constant weight) and a table of non-negative integer weights
+ * weights[table_ptr[c] .. table_ptr[c+1]-1], one per joint value of its
+ * scope, row-major with the first scope variable slowest. The count is the
+ * sum over all assignments of the product of the constraints' weights (the
+ * partition function of Eq. 2 with the constraint tensors in place of
+ * exp(-beta E)); it is exact for any weights. The network keeps the boolean
+ * bonds of Sec. 2.1: a variable of D values has ceil(log2 D) bonds per
+ * occurrence (its value in binary), its COPY tensor is 1 where every
+ * occurrence holds the same value below D (the scalar D when it has no bond),
+ * and a constraint's tensor is 0 wherever an occurrence holds a code of D or
+ * more. Host arrays are borrowed and copied. TN_EINVAL on a malformed
+ * network or a table of the wrong size; TN_ERANK when a constraint's or a
+ * variable's bonds exceed TN_MAX_INIT_RANK. flags: TN_BUILD_* (boolean COPY
+ * tensors only). */
+typedef struct {
+    int32_t n_vars;
+    const int32_t* domain;      /* n_vars entries, or NULL */
+    int32_t n_cons;
+    const int32_t* scope_ptr;   /* n_cons + 1 entries, scope_ptr[0] = 0 */
+    const int32_t* scope;       /* scope_ptr[n_cons] entries */
+    const int64_t* table_ptr;   /* n_cons + 1 entries, table_ptr[0] = 0 */
+    const uint32_t* weights;    /* table_ptr[n_cons] entries */
+} tn_csp;
+tn_status tn_build_csp(const tn_csp* c, uint32_t flags, tn_network** out);
+/* Largest rank among the initial tensors, and the bound the arithmetic is
+ * sized for: every count of the network is at most 2^count_bits. */
+tn_status tn_network_ranks(const tn_network* net, int32_t* max_init_rank, int32_t* count_bits);
 /* Number of tensors (n_vars COPY tensors first, then one per clause) and
  * bonds (one per literal occurrence). */
 tn_status tn_network_info(const tn_network* net, int32_t* n_tensors, int32_t* n_bonds);
@@ -218,9 +270,10 @@ tn_status tn_count_batch(const tn_formula* fs, int32_t n, tn_order_kind kind, ui
  * multiply-adds per step and residue plane. */
 typedef enum {
     TN_KC_GENERIC = 0, TN_KC_STREAM = 1, TN_KC_ROWDOT = 2, TN_KC_MFMA = 3, TN_KC_BATCH = 4, TN_KC_DOT = 5,
-    TN_KC_DIGITS = 6   /* in-place digit pass before TN_KC_MFMA */
+    TN_KC_DIGITS = 6,  /* in-place digit pass before TN_KC_MFMA */
+    TN_KC_NARROW = 7   /* int8 matrix cores, B side of at most 64 rows: streams A once */
 } tn_kernel_class;
-#define TN_KERNEL_CLASSES 7
+#define TN_KERNEL_CLASSES 8
 typedef struct {
     int64_t launches;
     double ms;

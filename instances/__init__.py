@@ -28,6 +28,7 @@ from .gen import (  # noqa: F401
     large_1in3,
     learned_instance,
     cubic_1in3,
+    planar_cubic_graph,
     FAMILY_SMALL_1IN3,
     FAMILY_CVC,
     FAMILY_LARGE_1IN3,

@@ -443,3 +443,55 @@ def table_csp(formula: Formula) -> CSP:
             table.append(1 if ok else 0)
         cons.append((scope, table))
     return CSP(formula.n_vars, [2] * formula.n_vars, cons, name=formula.name + "-table")
+
+
+def planar_cubic_graph(n: int, rng: Rng, flips_per_vertex: int = 10) -> List[Tuple[int, int]]:
+    """A random simple planar cubic graph on n (even, >= 4) vertices: the dual
+    of a random triangulation of the sphere with n/2 + 2 vertices (2V - 4 = n
+    triangles). The triangulation starts from K4, grows by inserting a vertex
+    into a uniformly chosen triangle, then is mixed by random edge flips that
+    keep it simple and every degree at least 3. Vertices of the result are the
+    triangles; two are adjacent when they share an edge."""
+    if n % 2 or n < 4:
+        raise ValueError("need an even n >= 4")
+    V = n // 2 + 2
+    faces = [[0, 1, 2], [0, 2, 3], [0, 3, 1], [1, 3, 2]]  # consistently oriented
+    for v in range(4, V):
+        f = faces.pop(rng.below(len(faces)))
+        a, b, c = f
+        faces += [[a, b, v], [b, c, v], [c, a, v]]
+
+    def edge_map():
+        em = {}
+        for i, (a, b, c) in enumerate(faces):
+            for x, y in ((a, b), (b, c), (c, a)):
+                em[(x, y)] = i
+        return em
+
+    deg = [0] * V
+    for a, b, c in faces:
+        for x in (a, b, c):
+            deg[x] += 1
+    for _ in range(flips_per_vertex * V):
+        em = edge_map()
+        i = rng.below(len(faces))
+        k = rng.below(3)
+        a, b = faces[i][k], faces[i][(k + 1) % 3]
+        c = faces[i][(k + 2) % 3]
+        j = em[(b, a)]
+        d = [x for x in faces[j] if x != a and x != b][0]
+        if c == d or (c, d) in em or (d, c) in em or deg[a] <= 3 or deg[b] <= 3:
+            continue
+        # (a, b, c) and (b, a, d) become (c, a, d) and (d, b, c)
+        faces[i] = [c, a, d]
+        faces[j] = [d, b, c]
+        deg[a] -= 1
+        deg[b] -= 1
+        deg[c] += 1
+        deg[d] += 1
+    em = edge_map()
+    edges = set()
+    for (x, y), i in em.items():
+        j = em[(y, x)]
+        edges.add((min(i, j), max(i, j)))
+    return sorted(edges)

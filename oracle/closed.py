@@ -70,3 +70,51 @@ def prism_perfect_matchings(k: int) -> int:
 
 def disjoint_1in3(n: int, m: int) -> int:
     return 3 ** m * 2 ** (n - 3 * m)
+
+
+# ----------------------------------------------- other constraint networks
+def chromatic_cycle(n: int, q: int) -> int:
+    """Proper q-colourings of the cycle C_n: (q-1)^n + (-1)^n (q-1)."""
+    return (q - 1) ** n + (-1) ** n * (q - 1)
+
+
+def chromatic_complete(n: int, q: int) -> int:
+    """Proper q-colourings of K_n: q (q-1) ... (q-n+1)."""
+    out = 1
+    for i in range(n):
+        out *= q - i
+    return out
+
+
+def hardcore_cycle(n: int, lam: int) -> int:
+    """Independent sets of C_n weighted by lam^size: the trace of T^n with the
+    transfer matrix T[s][t] = lam^t unless both sites are occupied."""
+    T = [[1, lam], [1, 0]]
+    M = [[1, 0], [0, 1]]
+    for _ in range(n):
+        M = [[sum(M[i][k] * T[k][j] for k in range(2)) for j in range(2)] for i in range(2)]
+    return M[0][0] + M[1][1]
+
+
+def xorsat_count(formula) -> int:
+    """Solutions of a system of parity clauses (an odd number of true
+    literals each): 2^(n - rank) over GF(2) when consistent, else 0. A negated
+    literal adds 1 to its clause's right-hand side."""
+    piv = []
+    rank = 0
+    for _, lits in formula.clauses:
+        mask, rhs = 0, 1
+        for l in lits:
+            mask ^= 1 << (abs(l) - 1)
+            if l < 0:
+                rhs ^= 1
+        for pm, pr in piv:
+            if mask & (pm & -pm):
+                mask ^= pm
+                rhs ^= pr
+        if mask:
+            piv.append((mask, rhs))
+            rank += 1
+        elif rhs:
+            return 0
+    return 2 ** (formula.n_vars - rank)

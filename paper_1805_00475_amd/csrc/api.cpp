@@ -43,6 +43,27 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         // evaluation); plans whose ranks exceed the cap are excluded
         bool have = false;
         tn_status last = TN_ERANK;
+        if (kind == TN_ORDER_LEARNED) {
+            // The learned order judged by the greedy order (Sec. 4: portfolio
+            // with lazy cost prediction): both plans cost well under the
+            // contraction they order, and the cheaper under the cost model is
+            // kept (fallback = 1 when greedy wins). Only when neither fits the
+            // rank cap does the full judge below run.
+            bool ok = false;
+            auto lm = order_learned(N, model, &ok);
+            Plan lp, gp;
+            const bool lok = ok && make_plan(N, lm, TN_ORDER_LEARNED, lp) == TN_OK;
+            const bool gok = make_plan(N, order_greedy(N), TN_ORDER_GREEDY, gp) == TN_OK;
+            if (lok && (!gok || plan_cost(lp) <= plan_cost(gp))) {
+                out = std::move(lp);
+                return TN_OK;
+            }
+            if (gok) {
+                out = std::move(gp);
+                out.stats.fallback = 1;
+                return TN_OK;
+            }
+        }
         // candidates: greedy, community, and kPartitionTrials randomized
         // recursive bisections (each itself best-of-2 per level)
         auto consider = [&](tn_status s2, Plan& p) {
@@ -100,17 +121,9 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 out = std::move(p);
             }
         }
-        if (kind == TN_ORDER_LEARNED) {
-            bool ok = false;
-            auto lm = order_learned(N, model, &ok);
-            Plan p;
-            if (ok && make_plan(N, lm, TN_ORDER_LEARNED, p) == TN_OK && (!have || plan_cost(p) <= plan_cost(out))) {
-                out = std::move(p);
-                have = true;
-            } else if (have) {
-                out.stats.fallback = 1;
-            }
-        }
+        // (learned: reached only when neither the learned nor the greedy plan
+        // fits the rank cap)
+        if (kind == TN_ORDER_LEARNED && have) out.stats.fallback = 1;
         return have ? TN_OK : last;
     } catch (const std::bad_alloc&) {
         return TN_ENOMEM;
@@ -138,6 +151,42 @@ tn_status tn_build(const tn_formula* f, tn_network** out) {
 }
 
 void tn_network_free(tn_network* net) { delete net; }
+
+tn_status tn_build_ex(const tn_formula* f, uint32_t flags, tn_network** out) {
+    if (!out || (flags & ~uint32_t(TN_BUILD_RING_COPY | TN_BUILD_SPLIT_CLAUSES))) return TN_EINVAL;
+    tn_status st = tn_build(f, out);
+    if (st != TN_OK || !flags) return st;
+    st = reduce_degree((*out)->net, flags);
+    if (st != TN_OK) {
+        delete *out;
+        *out = nullptr;
+    }
+    return st;
+}
+
+tn_status tn_build_csp(const tn_csp* c, uint32_t flags, tn_network** out) {
+    if (!c || !out || (flags & ~uint32_t(TN_BUILD_RING_COPY | TN_BUILD_SPLIT_CLAUSES))) return TN_EINVAL;
+    *out = nullptr;
+    tn_network* h = new (std::nothrow) tn_network;
+    if (!h) return TN_ENOMEM;
+    tn_status st = build_csp(c, h->net);
+    if (st == TN_OK && flags) st = reduce_degree(h->net, flags);
+    if (st != TN_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return TN_OK;
+}
+
+tn_status tn_network_ranks(const tn_network* net, int32_t* max_init_rank, int32_t* count_bits) {
+    if (!net) return TN_EINVAL;
+    int32_t r = 0;
+    for (const auto& t : net->net.t) r = std::max(r, int32_t(t.bonds.size()));
+    if (max_init_rank) *max_init_rank = r;
+    if (count_bits) *count_bits = net->net.count_bits;
+    return TN_OK;
+}
 
 tn_status tn_network_info(const tn_network* net, int32_t* n_tensors, int32_t* n_bonds) {
     if (!net) return TN_EINVAL;

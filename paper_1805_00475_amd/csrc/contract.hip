@@ -354,6 +354,7 @@ KernelClass choose_class(const Step& st, int el, int flags) {
     if (flags & TN_FLAG_GENERIC_ONLY) return KC_GENERIC;
     if (a.rC <= 6 && a.s >= 10) return KC_DOT;
     if (el != EL_U64 && !st.initA && !st.initB && mfma_eligible(a, el) && !(flags & TN_FLAG_NO_MFMA)) return KC_MFMA;
+    if (el == EL_I8 && narrow8_eligible(a) && !(flags & TN_FLAG_NO_MFMA)) return KC_NARROW;
     if (a.s <= 5 && a.fA >= 8) return KC_STREAM;
     if (a.s >= 6) return KC_ROWDOT;
     return KC_GENERIC;
@@ -399,7 +400,7 @@ void fill_moduli(StepArgs& a, const uint32_t* primes, int G) {
 // Choose and launch the kernel of one step for a group of G residue planes.
 hipError_t launch_step(const Step& st0, int el, int flags, const uint32_t* primes, int G, char* init_base,
                        char* arena_base, int64_t arena_elems, char* scratch, hipStream_t stream, KernelClass* kc,
-                       int force, unsigned dig) {
+                       int force, unsigned dig, int64_t init_stride) {
     const size_t es = size_t(elem_size(el));
     Profiler& prof = profiler();
     // algorithmic work of the step: entries read and written, multiply-adds
@@ -416,8 +417,8 @@ hipError_t launch_step(const Step& st0, int el, int flags, const uint32_t* prime
     a.B = st.initB ? init_base + st.offB * es : arena_base + st.offB * es;
     a.A = st.initA ? init_base + st.offA * es : arena_base + st.offA * es;
     a.C = arena_base + st.offC * es;
-    a.strideA = st.initA ? 0 : arena_elems;
-    a.strideB = st.initB ? 0 : arena_elems;
+    a.strideA = st.initA ? init_stride : arena_elems;
+    a.strideB = st.initB ? init_stride : arena_elems;
     a.strideC = arena_elems;
     const uint64_t cmask = st.rC >= 64 ? ~0ull : ((uint64_t(1) << st.rC) - 1);
     a.maskA = st.maskA;
@@ -443,6 +444,7 @@ hipError_t launch_step(const Step& st0, int el, int flags, const uint32_t* prime
     if (force == KC_ROWDOT && a.rC > 40) return hipErrorInvalidValue;
     const bool can_dot = a.rC <= 6 && a.s >= 10;
     if (force == KC_DOT && !can_dot) return hipErrorInvalidValue;
+    if (force == KC_NARROW && !(el == EL_I8 && narrow8_eligible(a))) return hipErrorInvalidValue;
     // one decision rule for launches and for the digit-plane hand-over
     const int pick = force >= 0 ? force : int(choose_class(st0, el, flags));
     if (pick != KC_MFMA && (dig & 3u)) return hipErrorInvalidValue;  // operands must be plain residues
@@ -456,6 +458,10 @@ hipError_t launch_step(const Step& st0, int el, int flags, const uint32_t* prime
         prof.after_raw(stream, KC_DOT, step_bytes, step_macs);
         TN_LAUNCH_EL(el, k_dot_final, g2, dim3(64), stream, a, scr, nblk);
         return hipGetLastError();
+    }
+    if (pick == KC_NARROW) {
+        *kc = KC_NARROW;
+        return launch_narrow8(a, G, stream, &prof, step_bytes, step_macs, scratch, kScratchPerPrime);
     }
     if (pick == KC_MFMA) {
         *kc = KC_MFMA;
@@ -492,9 +498,15 @@ hipError_t launch_step(const Step& st0, int el, int flags, const uint32_t* prime
 }
 
 // Value of one initial tensor entry x in the plan's bit order ``layout``
-// (Eq. 3, Eq. 4, Eq. 6; a negated index is reversed, Sec. 2.1).
+// (Eq. 3, Eq. 4, Eq. 6, parity; a negated index is reversed, Sec. 2.1; a
+// table lists its entries by its own bond order).
 uint64_t init_entry(const InitTensor& t, const std::vector<int32_t>& pos, uint64_t x) {
     const int r = int(t.bonds.size());
+    if (t.kind == T_TABLE) {
+        uint64_t own = 0;
+        for (int k = 0; k < r; ++k) own |= ((x >> pos[k]) & 1) << k;
+        return t.table[size_t(own)];
+    }
     if (t.kind == T_COPY) {
         if (r == 0) return 2;  // a variable in no clause: both values count
         const uint64_t all = (r >= 64) ? ~0ull : ((uint64_t(1) << r) - 1);
@@ -506,10 +518,14 @@ uint64_t init_entry(const InitTensor& t, const std::vector<int32_t>& pos, uint64
         ntrue += bit ^ int((t.neg >> k) & 1);
     }
     if (t.kind == T_OR) return ntrue >= 1 ? 1 : 0;
+    if (t.kind == T_XOR) return uint64_t(ntrue & 1);
     return ntrue == 1 ? 1 : 0;
 }
 
-void fill_init(const Network& net, const Plan& plan, int el, uint8_t* host) {
+// Initial tensors in plan layout. Without moduli the raw entries are stored
+// (entries of at most 127 are valid residues in every plane); with ``mod``
+// (one modulus) each entry is reduced: centred for int8 planes.
+void fill_init(const Network& net, const Plan& plan, int el, uint8_t* host, const uint32_t* mod) {
     for (int32_t i = 0; i < plan.n_init; ++i) {
         const InitTensor& t = net.t[i];
         const auto& L = plan.layout[i];
@@ -518,22 +534,37 @@ void fill_init(const Network& net, const Plan& plan, int el, uint8_t* host) {
             pos[k] = int32_t(std::find(L.begin(), L.end(), t.bonds[k]) - L.begin());
         const uint64_t n = uint64_t(1) << t.bonds.size();
         for (uint64_t x = 0; x < n; ++x) {
-            const uint64_t v = init_entry(t, pos, x);  // 0, 1 or 2: the same residue in every plane
-            if (el == EL_U64)
+            uint64_t v = init_entry(t, pos, x);
+            if (el == EL_U64) {
                 reinterpret_cast<uint64_t*>(host)[plan.init_off[i] + x] = v;
-            else if (el == EL_I8)
-                reinterpret_cast<int8_t*>(host)[plan.init_off[i] + x] = int8_t(v);
-            else
-                reinterpret_cast<uint32_t*>(host)[plan.init_off[i] + x] = uint32_t(v);
+            } else if (el == EL_I8) {
+                int32_t c = int32_t(v);
+                if (mod) {
+                    const int32_t m = int32_t(*mod), rr = int32_t(v % uint64_t(m));
+                    c = rr > m / 2 ? rr - m : rr;
+                }
+                reinterpret_cast<int8_t*>(host)[plan.init_off[i] + x] = int8_t(c);
+            } else {
+                reinterpret_cast<uint32_t*>(host)[plan.init_off[i] + x] = uint32_t(mod ? v % *mod : v);
+            }
         }
     }
 }
 
+// Whether the initial entries must be reduced per residue plane: an int8
+// plane holds raw entries of at most 127 (any modulus), a u32 plane entries
+// below its prime.
+bool init_per_plane(const Plan& plan, const Resolved& R) {
+    if (R.u64) return false;
+    if (R.i8) return plan.max_entry > 127;
+    return plan.max_entry >= *std::min_element(R.primes.begin(), R.primes.end());
+}
+
 tn_status resolve(const Plan& plan, const tn_contract_opts* o, Resolved& r) {
     int32_t arith = o ? o->arith : TN_ARITH_AUTO;
-    if (arith == TN_ARITH_AUTO) arith = plan.n_vars <= 63 ? TN_ARITH_U64 : TN_ARITH_RNS;
+    if (arith == TN_ARITH_AUTO) arith = plan.count_bits <= 63 ? TN_ARITH_U64 : TN_ARITH_RNS;
     if (arith == TN_ARITH_U64) {
-        if (plan.n_vars > 63) return TN_EINVAL;  // 64-bit wrapping is exact only below 2^64
+        if (plan.count_bits > 63) return TN_EINVAL;  // 64-bit wrapping is exact only below 2^64
         r.u64 = true;
         r.k = 1;
         return TN_OK;
@@ -542,7 +573,7 @@ tn_status resolve(const Plan& plan, const tn_contract_opts* o, Resolved& r) {
     r.u64 = false;
     // small moduli (int8 residues) unless a prime count is given, 16-bit
     // primes are asked for, or the count needs more bits than they hold
-    const int32_t ks = small_moduli_needed(plan.n_vars);
+    const int32_t ks = small_moduli_needed(plan.count_bits);
     if (!(o && o->n_primes > 0) && !(o && (o->flags & TN_FLAG_WIDE_RNS)) && ks > 0) {
         r.i8 = true;
         r.k = ks;
@@ -551,7 +582,7 @@ tn_status resolve(const Plan& plan, const tn_contract_opts* o, Resolved& r) {
         return TN_OK;
     }
     r.i8 = false;
-    r.k = (o && o->n_primes > 0) ? o->n_primes : primes_needed(plan.n_vars);
+    r.k = (o && o->n_primes > 0) ? o->n_primes : primes_needed(plan.count_bits);
     if (r.k > TN_MAX_PRIMES) return TN_EINVAL;
     const auto& P = prime_table(r.k);
     r.primes.assign(P.begin(), P.begin() + r.k);
@@ -580,25 +611,32 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
         return TN_OK;
     }
     if (!o || !o->workspace) return TN_EINVAL;
+    // initial tensors: one region for every plane, or one per plane of a
+    // group when an entry needs reducing modulo each plane's modulus
+    const bool pp = init_per_plane(plan, R);
     const int64_t init_bytes = align256(plan.init_elems * int64_t(es));
     const int64_t arena_bytes = align256(plan.arena_elems * int64_t(es));
     const int64_t arena_elems = arena_bytes / int64_t(es);
     const int64_t ws = int64_t(o->workspace_bytes);
     if (init_bytes + arena_bytes + kScratchPerPrime > ws) return TN_ETOOBIG;
-    int G = int((ws - init_bytes) / (arena_bytes + kScratchPerPrime));
+    int G = pp ? int(ws / (init_bytes + arena_bytes + kScratchPerPrime))
+               : int((ws - init_bytes) / (arena_bytes + kScratchPerPrime));
     G = std::min({G, R.k, kMaxGroup});
     if (o->prime_group > 0) G = std::min(G, int(o->prime_group));
     G = std::max(G, 1);
     hipStream_t stream = static_cast<hipStream_t>(o->stream);
     char* base = static_cast<char*>(o->workspace);
     char* init_base = base;
-    char* arena_base = base + init_bytes;
+    char* arena_base = base + (pp ? int64_t(G) : 1) * init_bytes;
     char* scratch = arena_base + int64_t(G) * arena_bytes;
-    // initial tensors in plan layout, identical for every prime (0/1/2 entries)
-    std::vector<uint8_t> host(size_t(plan.init_elems) * es, 0);
-    fill_init(net, plan, el, host.data());
+    const int64_t init_stride = pp ? init_bytes / int64_t(es) : 0;
+    // host images: one region, or one per modulus (held until the end)
+    const int n_img = pp ? R.k : 1;
+    std::vector<uint8_t> host(size_t(init_bytes) * size_t(n_img), 0);
+    for (int q = 0; q < n_img; ++q)
+        fill_init(net, plan, el, host.data() + size_t(q) * size_t(init_bytes), pp ? &R.primes[size_t(q)] : nullptr);
     Profiler& prof = profiler();
-    hipError_t err = hipMemcpyAsync(init_base, host.data(), host.size(), hipMemcpyHostToDevice, stream);
+    hipError_t err = pp ? hipSuccess : hipMemcpyAsync(init_base, host.data(), host.size(), hipMemcpyHostToDevice, stream);
     // on any failure, drain the stream before the host staging buffer goes away
     auto fail = [&]() {
         (void)hipStreamSynchronize(stream);
@@ -613,10 +651,16 @@ tn_status run_plan(const Network& net, const Plan& plan, const tn_contract_opts*
     std::vector<uint64_t> out(size_t(R.k), 0);
     for (int g0 = 0; g0 < R.k; g0 += G) {
         const int gn = std::min(G, R.k - g0);
+        if (pp) {
+            // this group's planes of the initial tensors
+            err = hipMemcpyAsync(init_base, host.data() + size_t(g0) * size_t(init_bytes),
+                                 size_t(gn) * size_t(init_bytes), hipMemcpyHostToDevice, stream);
+            if (err != hipSuccess) return fail();
+        }
         for (size_t k = 0; k < plan.steps.size(); ++k) {
             KernelClass kc = KC_GENERIC;
             err = launch_step(plan.steps[k], el, o->flags, R.u64 ? nullptr : R.primes.data() + g0, gn, init_base,
-                              arena_base, arena_elems, scratch, stream, &kc, -1, dig[k]);
+                              arena_base, arena_elems, scratch, stream, &kc, -1, dig[k], init_stride);
             if (err != hipSuccess) return fail();
         }
         for (int g = 0; g < gn; ++g) {
@@ -656,7 +700,8 @@ tn_status tn_workspace_bytes(const tn_network* net, const tn_plan* plan, const t
     if (st != TN_OK) return st;
     const int64_t es = R.es();
     int G = (opts && opts->prime_group > 0) ? std::min<int>(opts->prime_group, std::min(R.k, kMaxGroup)) : 1;
-    *bytes = size_t(align256(plan->plan.init_elems * es) +
+    const int64_t init = align256(plan->plan.init_elems * es);
+    *bytes = size_t((init_per_plane(plan->plan, R) ? int64_t(G) : 1) * init +
                     int64_t(G) * (align256(plan->plan.arena_elems * es) + kScratchPerPrime));
     return TN_OK;
 }
@@ -791,7 +836,7 @@ extern "C" tn_status tn_step(const void* A, int32_t rA, const void* B, int32_t r
         (arith != TN_ARITH_RNS || prime <= 65536u - 2048u || prime >= kPrimeBound || prime % 2 == 0))
         return TN_EINVAL;
     if (small && arith != TN_ARITH_RNS) return TN_EINVAL;
-    if (kernel < -1 || kernel > KC_DOT || kernel == KC_BATCH) return TN_EINVAL;
+    if (kernel < -1 || kernel > KC_NARROW || kernel == KC_BATCH || kernel == KC_DIGITS) return TN_EINVAL;
     const int el = u64 ? EL_U64 : small ? EL_I8 : EL_U32;
     const int64_t es = elem_size(el);
     const int64_t nA = align256((int64_t(1) << rA) * es), nB = align256((int64_t(1) << rB) * es),

@@ -11,22 +11,26 @@
 
 namespace tn {
 
-enum TKind : uint8_t { T_COPY = 0, T_OR = 1, T_EXONE = 2 };
+enum TKind : uint8_t { T_COPY = 0, T_OR = 1, T_EXONE = 2, T_XOR = 3, T_TABLE = 4 };
 
 // A tensor of the original network (Sec. 2.1). ``bonds[k]`` is the bond on
 // index k: for a COPY tensor the k-th occurrence of its variable, for a
-// clause tensor its k-th literal. Bit k of ``neg`` reverses index k.
+// clause tensor its k-th literal. Bit k of ``neg`` reverses index k. A
+// T_TABLE tensor lists its entries: table[x], bit k of x the value of bond k.
 struct InitTensor {
     uint8_t kind = T_COPY;
     std::vector<int32_t> bonds;
     uint64_t neg = 0;
+    std::vector<uint32_t> table;
 };
 
 struct Network {
     int32_t n_vars = 0;
     int32_t n_clauses = 0;
-    std::vector<InitTensor> t;                   // variables first, then clauses
-    std::vector<std::array<int32_t, 2>> bond_end;  // (COPY tensor, clause tensor)
+    int32_t count_bits = 0;   // the count is at most 2^count_bits
+    uint64_t max_entry = 2;   // largest entry of an initial tensor
+    std::vector<InitTensor> t;                   // variables first, then clauses, then split pieces
+    std::vector<std::array<int32_t, 2>> bond_end;  // the two tensors of every bond
 };
 
 // One pairwise contraction C = A (x) B in the layout convention of the plan:
@@ -49,6 +53,8 @@ struct Step {
 struct Plan {
     int32_t n_init = 0;
     int32_t n_vars = 0;
+    int32_t count_bits = 0;   // the network's bound: the count is at most 2^count_bits
+    uint64_t max_entry = 2;   // largest initial entry (above 127: initial tensors per residue plane)
     std::vector<std::pair<int32_t, int32_t>> merges;
     std::vector<Step> steps;
     std::vector<int32_t> rank;                 // per tensor id
@@ -65,6 +71,8 @@ constexpr int64_t kAlignElems = 64;  // 256 bytes for 32-bit entries
 
 // network.cpp
 tn_status build_network(const tn_formula* f, Network& net);
+tn_status build_csp(const tn_csp* c, Network& net);
+tn_status reduce_degree(Network& net, uint32_t flags);
 
 // order_*.cpp: produce merges (pairs of tensor ids; merge k creates id
 // n_init + k). Every order ends with a single tensor.
@@ -89,12 +97,13 @@ Reduced absorb_small(const Network& net);
 // plan.cpp
 tn_status make_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>> merges,
                     int32_t chosen, Plan& plan);
-// Residue arithmetic a contraction uses by default for n_vars variables:
-// 64-bit wrapping counts (n_vars <= 63), small moduli (int8 residues) when
-// their product holds the count, else 16-bit primes; and its plane count.
+// Residue arithmetic a contraction uses by default for counts of at most
+// 2^count_bits: 64-bit wrapping counts (count_bits <= 63), small moduli
+// (int8 residues) when their product holds the count, else 16-bit primes;
+// and its plane count.
 enum ResidueMode : int { RM_U64 = 0, RM_WIDE = 1, RM_SMALL = 2 };
-int default_residue_mode(int32_t n_vars);
-int32_t default_planes(int32_t n_vars);
+int default_residue_mode(int32_t count_bits);
+int32_t default_planes(int32_t count_bits);
 // Predicted device time in microseconds: of a whole plan under its default
 // residue mode (all planes, launches included), and of one step for one
 // residue plane (launch excluded).

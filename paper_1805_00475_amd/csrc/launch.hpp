@@ -29,7 +29,7 @@ int64_t align256(int64_t b);
 // and for the output's consumer).
 hipError_t launch_step(const Step& st, int el, int flags, const uint32_t* primes, int G, char* init_base,
                        char* arena_base, int64_t arena_elems, char* scratch, hipStream_t stream, KernelClass* kc,
-                       int force = -1, unsigned dig = 0);
+                       int force = -1, unsigned dig = 0, int64_t init_stride = 0);
 
 // The kernel class launch_step picks for a step (no launch, force < 0).
 KernelClass choose_class(const Step& st, int el, int flags);
@@ -48,6 +48,7 @@ void fill_moduli(StepArgs& a, const uint32_t* primes, int G);
 // Entry x of an initial tensor whose bonds sit at bit positions pos.
 uint64_t init_entry(const InitTensor& t, const std::vector<int32_t>& pos, uint64_t x);
 // Writes every initial tensor of a plan, in plan layout, at its init offset.
-void fill_init(const Network& net, const Plan& plan, int el, uint8_t* host);
+void fill_init(const Network& net, const Plan& plan, int el, uint8_t* host, const uint32_t* mod = nullptr);
+bool init_per_plane(const Plan& plan, const Resolved& R);
 
 }  // namespace tn

@@ -187,7 +187,7 @@ std::vector<std::pair<int32_t, int32_t>> refine_order(const Network& net,
     int maxr = 0;
     for (int32_t v = 0; v < n; ++v) maxr = std::max(maxr, t.rank(v));
     g_rank_cap = maxr;  // keep peak memory: never raise the largest rank
-    g_mode = default_residue_mode(net.n_vars);
+    g_mode = default_residue_mode(net.count_bits);
     std::vector<char> is_frontier(n, 0);
     for (int sweep = 0; sweep < 4; ++sweep) {
         bool any = false;

@@ -76,16 +76,16 @@ struct Arena {
 
 }  // namespace
 
-int default_residue_mode(int32_t n_vars) {
-    if (n_vars <= 63) return RM_U64;
-    return small_moduli_needed(n_vars) > 0 ? RM_SMALL : RM_WIDE;
+int default_residue_mode(int32_t count_bits) {
+    if (count_bits <= 63) return RM_U64;
+    return small_moduli_needed(count_bits) > 0 ? RM_SMALL : RM_WIDE;
 }
 
-int32_t default_planes(int32_t n_vars) {
-    switch (default_residue_mode(n_vars)) {
+int32_t default_planes(int32_t count_bits) {
+    switch (default_residue_mode(count_bits)) {
         case RM_U64: return 1;
-        case RM_SMALL: return small_moduli_needed(n_vars);
-        default: return primes_needed(n_vars);
+        case RM_SMALL: return small_moduli_needed(count_bits);
+        default: return primes_needed(count_bits);
     }
 }
 
@@ -98,8 +98,11 @@ int32_t default_planes(int32_t n_vars) {
 //    plus the entries read and written at 2e12 B/s (within 15 % from K = 2^5
 //    to 2^13: small K is bound by the output write, large K by the matrix
 //    cores at about 60 % of the int8 peak); the split-K dot (rC <= 6,
-//    s >= 10) moves its bytes at 1.8e12 B/s, the wave-per-output kernel
-//    (other s >= 6) at 4e10 B/s, streaming steps (s <= 5) at 7e11 B/s.
+//    s >= 10) moves its bytes at 1.8e12 B/s, the narrow matrix-core kernel
+//    (B side of at most 64 rows, s >= 6; A read once) at NARROW_BPS plus the
+//    int8 rate, streaming steps (s <= 5) at 7e11 B/s.
+//  - 64-bit counts and 16-bit primes: the wave-per-output kernel (s >= 6,
+//    narrow sides) at 4e10 B/s.
 //  - 64-bit counts (8-byte entries, no matrix cores): the same non-matrix
 //    classes.
 //  - 16-bit primes (4-byte entries): the int8-limb matrix-core kernel at the
@@ -115,8 +118,11 @@ double step_cost_model(int rA, int rB, int s, int rC, int mode) {
     const double es = mode == RM_U64 ? 8.0 : mode == RM_WIDE ? 4.0 : 1.0;
     const double bytes = es * (ea + eb + ec);
     double t;
+    constexpr double NARROW_BPS = 3e12;
     if (mode == RM_SMALL && fa >= 7 && fb >= 6) {
         t = macs / 1.5e15 + bytes / 2e12;
+    } else if (mode == RM_SMALL && s >= 6 && !(s >= 10 && rC <= 6) && (fb <= 5 || (fb == 6 && fa < 7))) {
+        t = macs / 1.5e15 + bytes / NARROW_BPS;
     } else if (mode == RM_WIDE && s >= 6 && fa >= 7 && fb >= 6) {
         static const double eff[] = {0.042, 0.087, 0.12, 0.22, 0.31, 0.39, 0.45, 0.45};
         const double e = eff[std::min(s, 13) - 6];
@@ -134,8 +140,8 @@ double step_cost_model(int rA, int rB, int s, int rC, int mode) {
 double plan_cost(const Plan& plan) {
     constexpr int kPlanesPerLaunch = 16;  // residue planes of one launch
     constexpr double kLaunchUs = 5.0;
-    const int mode = default_residue_mode(plan.n_vars);
-    const int32_t planes = default_planes(plan.n_vars);
+    const int mode = default_residue_mode(plan.count_bits);
+    const int32_t planes = default_planes(plan.count_bits);
     const double launches = double((planes + kPlanesPerLaunch - 1) / kPlanesPerLaunch);
     double t = 0;
     for (const Step& st : plan.steps)
@@ -150,6 +156,8 @@ tn_status make_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>>
         plan = Plan{};
         plan.n_init = n_init;
         plan.n_vars = net.n_vars;
+        plan.count_bits = net.count_bits;
+        plan.max_entry = net.max_entry;
         const int32_t n_bonds = int32_t(net.bond_end.size());
         const int32_t n_ids = n_init + int32_t(merges.size());
         // --- validate the merge list and compute bond sets

@@ -25,9 +25,11 @@ FLAG_NO_MFMA = 2
 FLAG_TIMING = 4
 FLAG_NO_GRAPH = 8
 FLAG_WIDE_RNS = 16
-KERNEL_CLASSES = ["generic", "stream", "rowdot", "mfma", "batch", "dot", "digits"]
+KERNEL_CLASSES = ["generic", "stream", "rowdot", "mfma", "batch", "dot", "digits", "narrow"]
 MAX_RANK = 34
 MAX_PRIMES = 128
+BUILD_RING_COPY = 1
+BUILD_SPLIT_CLAUSES = 2
 
 
 class TNError(RuntimeError):
@@ -40,6 +42,12 @@ class Formula_c(ctypes.Structure):
     _fields_ = [("n_vars", ctypes.c_int32), ("n_clauses", ctypes.c_int32),
                 ("clause_ptr", ctypes.POINTER(ctypes.c_int32)), ("lits", ctypes.POINTER(ctypes.c_int32)),
                 ("kinds", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class CSP_c(ctypes.Structure):
+    _fields_ = [("n_vars", ctypes.c_int32), ("domain", ctypes.POINTER(ctypes.c_int32)), ("n_cons", ctypes.c_int32),
+                ("scope_ptr", ctypes.POINTER(ctypes.c_int32)), ("scope", ctypes.POINTER(ctypes.c_int32)),
+                ("table_ptr", ctypes.POINTER(ctypes.c_int64)), ("weights", ctypes.POINTER(ctypes.c_uint32))]
 
 
 class PlanStats_c(ctypes.Structure):
@@ -71,6 +79,9 @@ _P = ctypes.POINTER
 _SIGS = {
     "tn_build": ([_P(Formula_c), _P(ctypes.c_void_p)], ctypes.c_int),
     "tn_network_free": ([ctypes.c_void_p], None),
+    "tn_build_ex": ([_P(Formula_c), ctypes.c_uint32, _P(ctypes.c_void_p)], ctypes.c_int),
+    "tn_build_csp": ([_P(CSP_c), ctypes.c_uint32, _P(ctypes.c_void_p)], ctypes.c_int),
+    "tn_network_ranks": ([ctypes.c_void_p, _P(ctypes.c_int32), _P(ctypes.c_int32)], ctypes.c_int),
     "tn_network_info": ([ctypes.c_void_p, _P(ctypes.c_int32), _P(ctypes.c_int32)], ctypes.c_int),
     "tn_order": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, _P(ctypes.c_void_p),
                   _P(PlanStats_c)], ctypes.c_int),
@@ -169,16 +180,45 @@ def _stats_dict(s: PlanStats_c) -> dict:
             "fallback": bool(s.fallback), "refined": bool(s.refined)}
 
 
-class Network:
-    """Handle of a built network (tn_build)."""
+class _CSPArrays:
+    """Keeps the ctypes arrays of one weighted constraint network alive."""
 
-    def __init__(self, formula):
+    def __init__(self, c):
+        dom, sp, sc, tp, w = c.arrays()
+        self.dom = (ctypes.c_int32 * max(1, len(dom)))(*dom)
+        self.sp = (ctypes.c_int32 * len(sp))(*sp)
+        self.sc = (ctypes.c_int32 * max(1, len(sc)))(*sc)
+        self.tp = (ctypes.c_int64 * len(tp))(*tp)
+        self.w = (ctypes.c_uint32 * max(1, len(w)))(*w)
+        self.c = CSP_c(c.n_vars, self.dom, len(sp) - 1, self.sp, self.sc, self.tp, self.w)
+
+
+class Network:
+    """Handle of a built network: tn_build / tn_build_ex for a formula
+    (clause lists), tn_build_csp for a weighted constraint network (an object
+    with ``domain`` and ``constraints``); ``flags``: BUILD_* degree
+    reduction."""
+
+    def __init__(self, formula, flags: int = 0):
         lib = load()
         self.formula = formula
-        fa = _FormulaArrays(formula)
         h = ctypes.c_void_p()
-        _check(lib.tn_build(ctypes.byref(fa.c), ctypes.byref(h)), "tn_build")
+        if hasattr(formula, "domain"):
+            ca = _CSPArrays(formula)
+            _check(lib.tn_build_csp(ctypes.byref(ca.c), flags, ctypes.byref(h)), "tn_build_csp")
+        else:
+            fa = _FormulaArrays(formula)
+            if flags:
+                _check(lib.tn_build_ex(ctypes.byref(fa.c), flags, ctypes.byref(h)), "tn_build_ex")
+            else:
+                _check(lib.tn_build(ctypes.byref(fa.c), ctypes.byref(h)), "tn_build")
         self.h = h
+
+    def ranks(self):
+        """(largest initial tensor rank, count_bits)."""
+        r, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().tn_network_ranks(self.h, ctypes.byref(r), ctypes.byref(b)), "tn_network_ranks")
+        return r.value, b.value
 
     def info(self):
         nt, nb = ctypes.c_int32(), ctypes.c_int32()
@@ -329,9 +369,9 @@ def count_plan(net: Network, plan: Plan, arith="auto", n_primes=0, workspace: Wo
 
 
 def count(formula, order: str = "greedy", seed: int = 0, arith="auto", n_primes=0, flags=0,
-          workspace: Workspace = None) -> int:
-    """Build, order, contract and recombine one formula."""
-    net = Network(formula)
+          workspace: Workspace = None, build_flags: int = 0) -> int:
+    """Build, order, contract and recombine one formula or constraint network."""
+    net = Network(formula, build_flags)
     plan = net.order(order, seed)
     return count_plan(net, plan, arith, n_primes, workspace, flags=flags)
 

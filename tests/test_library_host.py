@@ -242,3 +242,43 @@ def test_crt_moduli_rejects_bad_input():
     for mods in ((6, 9), (5, 1), (3, 2)):   # shared factor, modulus 1, residue >= modulus
         m = (ctypes.c_uint32 * 2)(*mods)
         assert lib.tn_crt_moduli(r, m, 2, None, 0, ctypes.byref(n)) == -1
+
+
+def test_degree_reduction_structure():
+    f = I.exactly_one_k(30, 8, 7, I.Rng(3))
+    f.clauses += [(I.XOR, [1, -2, 3, 4, 5]), (I.OR, [6, 7, 8, -9])]
+    base = tn.Network(f)
+    red = tn.Network(f, tn.BUILD_RING_COPY | tn.BUILD_SPLIT_CLAUSES)
+    (nt0, nb0), (nt1, nb1) = base.info(), red.info()
+    assert base.ranks()[0] == 7 and red.ranks()[0] == 3
+    # a clause of k literals -> k - 2 pieces and k - 3 new bonds; a COPY of
+    # rank d > 3 -> d tensors and d new bonds
+    occ = f.occurrences()
+    ring_t = sum(d - 1 for d in occ if d > 3)
+    ring_b = sum(d for d in occ if d > 3)
+    chain_t = sum(len(c) - 3 for _, c in f.clauses if len(c) > 3)
+    chain_b = sum(len(c) - 3 for _, c in f.clauses if len(c) > 3)
+    assert nt1 == nt0 + ring_t + chain_t and nb1 == nb0 + ring_b + chain_b
+    for kind in ("greedy", "partition", "community", "best"):
+        assert red.order(kind, seed=1).verify()
+
+
+def test_csp_build_validation_and_bounds():
+    c = I.coloring_csp(I.cycle_graph(12), 12, 3)
+    assert tn.Network(c).ranks() == (4, 20)          # COPY: 2 occurrences x 2 bits; 12 log2 3 = 19.02
+    h = I.hardcore_csp(I.cycle_graph(8), 8, 1000)
+    assert tn.Network(h).ranks()[1] == 8 + int(-(-8 * __import__("math").log2(1000) // 1))
+    bad = [I.CSP(2, [2, 0], []),                                 # empty domain
+           I.CSP(2, [2, 300], []),                               # domain above 256
+           I.CSP(2, [2, 3], [((1, 2), [1] * 5)]),                # table of the wrong size
+           I.CSP(2, [2, 3], [((1, 3), [1] * 4)])]                # variable out of range
+    for c in bad:
+        with pytest.raises(tn.TNError) as e:
+            tn.Network(c)
+        assert e.value.status == -1
+    with pytest.raises(tn.TNError) as e:   # 13 occurrences of a 4-valued variable: 26 bonds on its COPY
+        tn.Network(I.CSP(1, [4], [((1,), [1] * 4)] * 13))
+    assert e.value.status == -5
+    # constant weights and one-value variables need no bond
+    k = tn.Network(I.CSP(3, [1, 1, 5], [((), [7]), ((1, 2), [3])]))
+    assert k.info() == (5, 0)

@@ -14,48 +14,7 @@ import instances as I
 from oracle import brute, contract, csp, elim
 
 
-# ------------------------------------------------------------ closed forms
-def chromatic_cycle(n, q):
-    return (q - 1) ** n + (-1) ** n * (q - 1)
-
-
-def chromatic_complete(n, q):
-    return math.prod(q - i for i in range(n))
-
-
-def hardcore_cycle(n, lam):
-    # transfer matrix: T[s][t] = lam^t unless both occupied
-    T = [[1, lam], [1, 0]]
-    M = [[1, 0], [0, 1]]
-    for _ in range(n):
-        M = [[sum(M[i][k] * T[k][j] for k in range(2)) for j in range(2)] for i in range(2)]
-    return M[0][0] + M[1][1]
-
-
-def xorsat_count(f):
-    # 2^(n - rank) when the GF(2) system is consistent, else 0
-    rows = []
-    for _, lits in f.clauses:
-        mask = 0
-        rhs = 1
-        for l in lits:
-            mask ^= 1 << (abs(l) - 1)
-            if l < 0:
-                rhs ^= 1      # a negated literal flips the parity it adds
-        rows.append((mask, rhs))
-    rank = 0
-    piv = []
-    for mask, rhs in rows:
-        for pm, pr in piv:
-            if mask & (pm & -pm):
-                mask ^= pm
-                rhs ^= pr
-        if mask:
-            piv.append((mask, rhs))
-            rank += 1
-        elif rhs:
-            return 0
-    return 2 ** (f.n_vars - rank)
+from oracle.closed import chromatic_complete, chromatic_cycle, hardcore_cycle, xorsat_count  # noqa: E402
 
 
 def _pins_hold():
