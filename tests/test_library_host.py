@@ -126,7 +126,7 @@ def test_rank_cap_reported():
     ([(0, [0])], 3),            # literal 0
     ([(0, [4])], 3),            # variable out of range
     ([(0, [-4])], 3),
-    ([(2, [1])], 3),            # unknown clause kind
+    ([(3, [1])], 3),            # unknown clause kind (0 OR, 1 exactly-one, 2 parity)
 ])
 def test_build_rejects_malformed(clauses, n):
     with pytest.raises(tn.TNError) as e:
