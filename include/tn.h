@@ -347,6 +347,27 @@ tn_status tn_mlp_backward(const float* params, const float* x, const float* h1, 
 tn_status tn_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
                       float beta2, float eps, void* stream);
 
+/* -------------------------------------------------------------- autotuner
+ * tn_autotune times every configuration of the tunable kernels over a grid
+ * of step shapes on the current device (hipEvents on ``stream``, the best of
+ * ``reps`` timed launches after one warm-up): the tile shape (256 x 256,
+ * 256 x 128, 128 x 128, 256 x 64, 128 x 64) of the tiled int8 matrix-core
+ * kernel, and the B rows per thread (1..16) of the streaming kernel for int8
+ * residues and 64-bit counts. The fastest configuration per shape is used by
+ * every later launch in the process (the nearest tuned shape of the same
+ * kernel and element kind whose configuration fits the step), and the table
+ * is written to ``out_path`` (nullable) as JSON: one entry per shape with the
+ * measured microseconds per residue plane of every configuration.
+ * ``workspace`` (device, at least 64 MiB; larger shapes are skipped when it
+ * is small) is overwritten. TN_EHIP if a launch fails. */
+tn_status tn_autotune(const char* out_path, void* workspace, size_t workspace_bytes, void* stream, int32_t reps);
+/* Installs the table of a cache written by tn_autotune (replacing any table
+ * in use; launches in flight keep the old one). ``arch`` (nullable): refuse
+ * with TN_EUNSUPPORTED a cache measured on another architecture, e.g.
+ * "gfx950". path = NULL removes the table (built-in rules everywhere).
+ * TN_EINVAL if the file cannot be read or parsed. */
+tn_status tn_tune_load(const char* path, const char* arch);
+
 /* -------------------------------------------------------------- utilities */
 /* The k largest primes below 65280, descending, as used by the RNS path
  * (k <= TN_MAX_PRIMES; all lie above 2^16 - 2^11). */

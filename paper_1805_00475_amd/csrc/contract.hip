@@ -22,6 +22,7 @@
 #include "mfma.hpp"
 #include "profile.hpp"
 #include "launch.hpp"
+#include "tune.hpp"
 
 namespace tn {
 
@@ -345,6 +346,18 @@ hipError_t launch_stream(int logk, int nb, dim3 grid, hipStream_t st, const Step
 
 inline uint32_t cap32(uint64_t x, uint32_t hi) { return uint32_t(std::min<uint64_t>(std::max<uint64_t>(x, 1), hi)); }
 
+// The streaming kernel with 2^nb B rows per thread (nb <= min(fB, 4)),
+// without profiling (the autotuner's measurement launches).
+hipError_t launch_stream_step(const StepArgs& a, int el, int G, int nb, hipStream_t st) {
+    if (nb < 0 || nb > 4 || nb > a.fB || a.s > 5 || a.fA < 8) return hipErrorInvalidValue;
+    const uint64_t n_iter = (uint64_t(1) << a.fA) >> 8;
+    const uint64_t n_chunk = (uint64_t(1) << a.fB) >> nb;
+    dim3 grid(cap32(n_iter, 1u << 20), cap32(n_chunk, 65535), uint32_t(G));
+    return el == EL_U64  ? launch_stream<EL_U64>(a.s, 1 << nb, grid, st, a)
+           : el == EL_I8 ? launch_stream<EL_I8>(a.s, 1 << nb, grid, st, a)
+                         : launch_stream<EL_U32>(a.s, 1 << nb, grid, st, a);
+}
+
 KernelClass choose_class(const Step& st, int el, int flags) {
     StepArgs a{};
     a.s = st.s;
@@ -469,7 +482,9 @@ hipError_t launch_step(const Step& st0, int el, int flags, const uint32_t* prime
         return launch_mfma(a, G, stream, &prof, step_bytes, step_macs, scratch, kScratchPerPrime, dig);
     }
     if (pick == KC_STREAM) {
-        const int nb = std::min(a.fB, 4);
+        // B rows per thread: the autotuner's choice for the nearest tuned shape, else 2^min(fB, 4)
+        const int tuned = tuned_choice(TK_STREAM, el, a.fA, a.fB, a.s);
+        const int nb = tuned >= 0 ? std::min({tuned, a.fB, 4}) : std::min(a.fB, 4);
         const uint64_t n_iter = (uint64_t(1) << a.fA) >> 8;
         const uint64_t n_chunk = (uint64_t(1) << a.fB) >> nb;
         dim3 grid(cap32(n_iter, 1u << 20), cap32(n_chunk, 65535), G);

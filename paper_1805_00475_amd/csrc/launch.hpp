@@ -45,6 +45,9 @@ int elem_size(int el);
 // Moduli and their reduction constants of G residue planes.
 void fill_moduli(StepArgs& a, const uint32_t* primes, int G);
 
+// The streaming kernel with 2^nb B rows per thread (autotuner launches).
+hipError_t launch_stream_step(const StepArgs& a, int el, int G, int nb, hipStream_t st);
+
 // Entry x of an initial tensor whose bonds sit at bit positions pos.
 uint64_t init_entry(const InitTensor& t, const std::vector<int32_t>& pos, uint64_t x);
 // Writes every initial tensor of a plan, in plan layout, at its init offset.

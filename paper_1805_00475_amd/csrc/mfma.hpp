@@ -44,5 +44,16 @@ hipError_t launch_mfma(const StepArgs& a, int G, hipStream_t stream, Profiler* p
 hipError_t launch_mfma8(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
                         double step_macs, char* scratch, int64_t scratch_per_plane);
 bool mfma8_eligible(const StepArgs& a);
+// The tiled int8 kernel with a given tile shape (Mfma8Cfg of tune.hpp;
+// MFMA8_RULE = the built-in rule), without profiling (the autotuner's
+// measurement launches).
+hipError_t launch_mfma8_cfg(const StepArgs& a, int G, hipStream_t stream, char* scratch, int64_t scratch_per_plane,
+                            int cfg);
+// Narrow int8 matrix-core step (narrow8.hip): B side of at most 64 rows,
+// K >= 64; A is read once (split K over block rows when the step has few
+// row tiles, partial residues in scratch).
+hipError_t launch_narrow8(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
+                          double step_macs, char* scratch, int64_t scratch_per_plane);
+bool narrow8_eligible(const StepArgs& a);
 
 }  // namespace tn

@@ -34,6 +34,7 @@
 #include "mfma.hpp"
 #include "mfma_common.hpp"
 #include "profile.hpp"
+#include "tune.hpp"
 
 namespace tn {
 
@@ -674,21 +675,35 @@ bool mfma8_eligible(const StepArgs& a) {
     return a.s >= 0 && a.s <= k8MaxRowBytesLog && a.fA >= 7 && a.fB >= 6 && a.fA + a.fB <= 45;
 }
 
+// The tile shape of the built-in rule: the largest that fits both free sides.
+int mfma8_rule_cfg(const StepArgs& a) {
+    if (a.fB >= 8) return MFMA8_256x256;
+    if (a.fB == 7) return a.fA >= 8 ? MFMA8_256x128 : MFMA8_128x128;
+    return a.fA >= 8 ? MFMA8_256x64 : MFMA8_128x64;
+}
+
+hipError_t launch_mfma8_cfg(const StepArgs& a, int G, hipStream_t stream, char* scratch, int64_t scratch_per_plane,
+                            int cfg) {
+    if (!mfma8_eligible(a) || (cfg != MFMA8_RULE && !mfma8_cfg_fits(cfg, a.fA, a.fB))) return hipErrorInvalidValue;
+    if (a.s < 6)
+        return a.fB >= 7 ? launch_short_s<Cfg128x128>(a, G, stream) : launch_short_s<Cfg128x64>(a, G, stream);
+    if (cfg == MFMA8_RULE) cfg = mfma8_rule_cfg(a);
+    switch (cfg) {
+        case MFMA8_256x256: return launch_cfg<Cfg256x256>(a, G, stream, scratch, scratch_per_plane);
+        case MFMA8_256x128: return launch_cfg<Cfg256x128>(a, G, stream, scratch, scratch_per_plane);
+        case MFMA8_128x128: return launch_cfg<Cfg128x128>(a, G, stream, scratch, scratch_per_plane);
+        case MFMA8_256x64: return launch_cfg<Cfg256x64>(a, G, stream, scratch, scratch_per_plane);
+        default: return launch_cfg<Cfg128x64>(a, G, stream, scratch, scratch_per_plane);
+    }
+}
+
 hipError_t launch_mfma8(const StepArgs& a, int G, hipStream_t stream, Profiler* prof, double step_bytes,
                         double step_macs, char* scratch, int64_t scratch_per_plane) {
     if (!mfma8_eligible(a)) return hipErrorInvalidValue;
     prof->before(stream);
-    hipError_t e;
-    if (a.s < 6)
-        e = a.fB >= 7 ? launch_short_s<Cfg128x128>(a, G, stream) : launch_short_s<Cfg128x64>(a, G, stream);
-    else if (a.fB >= 8)
-        e = launch_cfg<Cfg256x256>(a, G, stream, scratch, scratch_per_plane);
-    else if (a.fB == 7)
-        e = a.fA >= 8 ? launch_cfg<Cfg256x128>(a, G, stream, scratch, scratch_per_plane)
-                      : launch_cfg<Cfg128x128>(a, G, stream, scratch, scratch_per_plane);
-    else
-        e = a.fA >= 8 ? launch_cfg<Cfg256x64>(a, G, stream, scratch, scratch_per_plane)
-                      : launch_cfg<Cfg128x64>(a, G, stream, scratch, scratch_per_plane);
+    // the autotuner's measured tile shape for the nearest tuned shape, else the rule
+    const int cfg = a.s >= 6 ? tuned_choice(TK_MFMA8, EL_I8, a.fA, a.fB, a.s) : MFMA8_RULE;
+    const hipError_t e = launch_mfma8_cfg(a, G, stream, scratch, scratch_per_plane, cfg);
     prof->after_raw(stream, KC_MFMA, step_bytes, step_macs);
     return e;
 }

@@ -133,6 +133,8 @@ _SIGS = {
                          _P(ctypes.c_uint8)], ctypes.c_int),
     "tn_gen_cubic_1in3": ([ctypes.c_int32, ctypes.c_uint64, _P(ctypes.c_int32), _P(ctypes.c_int32),
                            _P(ctypes.c_uint8)], ctypes.c_int),
+    "tn_autotune": ([ctypes.c_char_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int32], ctypes.c_int),
+    "tn_tune_load": ([ctypes.c_char_p, ctypes.c_char_p], ctypes.c_int),
     "tn_status_str": ([ctypes.c_int], ctypes.c_char_p),
     "tn_version": ([], ctypes.c_char_p),
 }
@@ -151,6 +153,10 @@ def load(path: str = LIB_PATH):
         fn.argtypes = args
         fn.restype = res
     _lib = lib
+    # the autotuner's measured launch choices for this architecture, when a
+    # cache ships with the package
+    if os.path.exists(TUNE_CACHE):
+        _check(lib.tn_tune_load(TUNE_CACHE.encode(), b"gfx950"), "tn_tune_load")
     return lib
 
 
@@ -615,6 +621,23 @@ def launches() -> list:
     buf = (LaunchRecord_c * max(1, n.value))()
     _check(load().tn_profile_launches(buf, n.value, ctypes.byref(n)), "tn_profile_launches")
     return [(KERNEL_CLASSES[r.kernel_class], r.rA, r.rB, r.s, r.rC, r.planes, r.ms) for r in buf[:n.value]]
+
+
+TUNE_CACHE = os.path.join(HERE, "tune", "gfx950.json")
+
+
+def autotune(out_path: str = None, reps: int = 3, workspace: Workspace = None, nbytes: int = 32 << 30):
+    """Run the library's autotuner on the current GPU (tn_autotune); the
+    table is used by every later launch and written to out_path."""
+    ws = workspace or default_workspace()
+    ptr, nb = ws.get(nbytes)
+    _check(load().tn_autotune(out_path.encode() if out_path else None, ptr, nb, current_stream_handle(), reps),
+           "tn_autotune")
+
+
+def tune_load(path: str = TUNE_CACHE, arch: str = "gfx950"):
+    """Install an autotuner cache (tn_tune_load); None removes the table."""
+    _check(load().tn_tune_load(path.encode() if path else None, arch.encode() if arch else None), "tn_tune_load")
 
 
 def version() -> str:
