@@ -141,7 +141,8 @@ def cvc200(seeds):
 # 0.62-0.70) small enough for a CPU oracle: O-B along the oracle's own order
 # where that order stays at rank <= 28, O-D where its elimination width does
 C3_CASES = [(200, 0.66, 0, "ob"), (200, 0.66, 1, "od"), (200, 0.66, 3, "ob"), (200, 0.70, 3, "ob"),
-            (250, 0.62, 1, "ob")]
+            (250, 0.62, 1, "ob"), (200, 0.62, 0, "ob"), (200, 0.62, 1, "ob+od"), (200, 0.62, 2, "ob+od"),
+            (200, 0.62, 3, "ob"), (200, 0.62, 4, "ob"), (200, 0.62, 5, "ob"), (250, 0.62, 4, "ob")]
 
 
 def c3():
@@ -153,9 +154,12 @@ def c3():
             continue
         f = I.large_1in3(n, a, s)
         t = time.time()
-        if how == "ob":
+        if how.startswith("ob"):
             c, which, mr = count_ob(f)
             it = {"n": n, "alpha": a, "seed": s, "count": str(c), "oracle": "O-B", "order": which, "max_rank": mr}
+            if how == "ob+od":
+                assert elim.count_rns(f) == c, "O-B and O-D disagree"
+                it["oracle"] = "O-B, O-D"
         else:
             c = elim.count_rns(f)
             it = {"n": n, "alpha": a, "seed": s, "count": str(c), "oracle": "O-D", "width": elim.width(f)}
@@ -165,6 +169,40 @@ def c3():
         dump("c3_1in3_counts.json", {
             "workload": "instances.large_1in3(n, alpha, seed): monotone 1-in-3, clauses of 3 distinct uniform "
                         "variables, m = round(alpha n)",
+            "oracle": "O-B: oracle.contract.count_mod per 31-bit prime along oracle.order.cheapest_order + "
+                      "oracle.rns.crt, checked modulo one extra prime; O-D: oracle.elim.count_rns",
+            "items": items})
+
+
+# the paper's own 1-in-3 family (Sec. 3.2): cubic graphs on nv vertices, one
+# variable per edge (N = 3 nv / 2), one exactly-one clause per vertex; the
+# solutions are the perfect matchings. O-B along the oracle's own order, and
+# O-D as well where its elimination width is small.
+F1_CASES = [(60, 0, "ob+od"), (60, 1, "ob+od"), (60, 2, "ob+od"), (100, 0, "ob"), (100, 1, "ob"), (100, 2, "ob"),
+            (140, 0, "ob"), (140, 1, "ob"), (140, 2, "ob"), (200, 1, "ob")]
+
+
+def f1():
+    path = os.path.join(HERE, "cubic_1in3_counts.json")
+    items = json.load(open(path))["items"] if os.path.exists(path) else []
+    have = {(it["n_vertices"], it["seed"]) for it in items}
+    for nv, s, how in F1_CASES:
+        if (nv, s) in have:
+            continue
+        f = I.cubic_1in3(nv, s)
+        t = time.time()
+        c, which, mr = count_ob(f)
+        it = {"n_vertices": nv, "n_vars": f.n_vars, "seed": s, "count": str(c), "oracle": "O-B", "order": which,
+              "max_rank": mr}
+        if how == "ob+od":
+            assert elim.count_rns(f) == c, "O-B and O-D disagree"
+            it["oracle"] = "O-B, O-D"
+        print(f"  cubic 1-in-3 nv={nv} s={s}: {c} ({time.time() - t:.1f}s)", flush=True)
+        items.append(it)
+        items.sort(key=lambda x: (x["n_vertices"], x["seed"]))
+        dump("cubic_1in3_counts.json", {
+            "workload": "instances.cubic_1in3(n_vertices, seed): the paper's 1-in-3 family, one variable per edge "
+                        "of a uniform random cubic graph, one exactly-one clause per vertex (perfect matchings)",
             "oracle": "O-B: oracle.contract.count_mod per 31-bit prime along oracle.order.cheapest_order + "
                       "oracle.rns.crt, checked modulo one extra prime; O-D: oracle.elim.count_rns",
             "items": items})
@@ -187,7 +225,9 @@ def batch256():
 
 
 if __name__ == "__main__":
-    if "--batch256" in sys.argv:
+    if "--f1" in sys.argv:
+        f1()
+    elif "--batch256" in sys.argv:
         batch256()
     elif "--c3" in sys.argv:
         c3()

@@ -55,3 +55,25 @@ def test_generated_formula_builds():
     f = tn.gen_cubic_1in3(20, 7)
     net = tn.Network(f)
     assert net.info() == (30 + 20, 60)
+
+
+@pytest.mark.parametrize("n", [4, 6, 20, 100])
+def test_planar_cubic_graphs(n):
+    for s in range(3):
+        e = I.planar_cubic_graph(n, I.Rng(1000 * n + s))
+        assert len(e) == 3 * n // 2 and len(set(e)) == len(e) and all(a < b for a, b in e)
+        deg = [0] * n
+        adj = [[] for _ in range(n)]
+        for a, b in e:
+            deg[a] += 1
+            deg[b] += 1
+            adj[a].append(b)
+            adj[b].append(a)
+        assert deg == [3] * n
+        seen, stack = {0}, [0]
+        while stack:
+            for u in adj[stack.pop()]:
+                if u not in seen:
+                    seen.add(u)
+                    stack.append(u)
+        assert len(seen) == n   # the dual of a triangulation is connected

@@ -231,6 +231,16 @@ def test_cvc200_random_cubic_vs_oracle():
         assert tn.count(f, "community", flags=tn.FLAG_WIDE_RNS) == want
 
 
+def test_c3_1in3_vs_oracle():
+    # monotone 1-in-3 with uniform clauses at n = 200-250 (alpha 0.62-0.70)
+    for it in _gold("c3_1in3_counts.json")["items"]:
+        f = I.large_1in3(it["n"], it["alpha"], it["seed"])
+        want = int(it["count"])
+        for order in ("best", "partition"):
+            _say(f"1-in-3 n={it['n']} alpha={it['alpha']} seed={it['seed']} order={order}")
+            assert tn.count(f, order, seed=it["seed"]) == want, order
+
+
 def test_c3_roofline_instance_invariants():
     # the largest 1-in-3 instance measured (n = 300, alpha = 0.62, seed 1,
     # intermediates of rank 31): beyond a CPU oracle here, so the count must
@@ -251,3 +261,17 @@ def test_c3_roofline_instance_invariants():
     d = tn.count_plan(net, best)
     assert a == b == c == d
     assert 0 <= a < 2 ** 300
+
+
+def test_paper_1in3_family_vs_oracle():
+    # the paper's own 1-in-3 workload (Sec. 3.2): one variable per edge of a
+    # random cubic graph, one exactly-one clause per vertex; N = 90 to 300
+    # variables. The formulas come from the library's own generator
+    # (tn_gen_cubic_1in3), which draws the same graphs as the instances package.
+    for it in _gold("cubic_1in3_counts.json")["items"]:
+        nv, s = it["n_vertices"], it["seed"]
+        f = tn.gen_cubic_1in3(nv, I.instance_seed(I.FAMILY_CUBIC_1IN3, (nv << 20) | s))
+        want = int(it["count"])
+        for order in ("best", "community", "partition"):
+            _say(f"cubic 1-in-3 N={it['n_vars']} seed={s} order={order}")
+            assert tn.count(f, order, seed=s) == want, order
