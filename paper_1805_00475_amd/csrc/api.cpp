@@ -1,15 +1,18 @@
 // Host-side entry points of the C ABI: build, order, plan queries, primes,
 // CRT and status strings. The GPU entry points live in contract.hip.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <new>
+#include <thread>
 
 #include "internal.hpp"
 
 namespace tn {
 
-// randomized bisection trials the judge may try
+// randomized bisection trials the judge may try per search thread
 constexpr int kPartitionTrials = 16;
 // host microseconds of order search allowed per predicted device microsecond
 constexpr double kSearchRatio = 2.0;
@@ -20,7 +23,18 @@ constexpr double kSearchRatio = 2.0;
 constexpr double kRefineCapUs = 400000.0;
 constexpr double kRefineRatio = 0.5;
 
-tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out) {
+// Host threads for one order search: TN_ORDER_THREADS if set, else the
+// cores available (at most 16).
+int search_threads() {
+    if (const char* e = std::getenv("TN_ORDER_THREADS")) {
+        const int t = std::atoi(e);
+        if (t >= 1) return std::min(t, 64);
+    }
+    const unsigned hw = std::thread::hardware_concurrency();
+    return int(std::min(16u, std::max(1u, hw)));
+}
+
+tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out, int threads) {
     try {
         auto plan_of = [&](int32_t k, Plan& p) -> tn_status {
             switch (k) {
@@ -98,18 +112,66 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                                      TN_ORDER_PARTITION, p);
             consider(s2, p);
         };
+        // trials t0 .. t0 + n - 1 on `threads` host threads; each thread keeps
+        // its cheapest plan (lowest trial index on ties), then the judge sees
+        // them in thread order
+        auto parallel_trials = [&](int t0, int n) {
+            const int T = std::min(threads, n);
+            std::vector<Plan> best(static_cast<size_t>(T));
+            std::vector<double> bc(size_t(T), 0.0);
+            std::vector<int> bt(size_t(T), -1);
+            std::vector<tn_status> bs(size_t(T), TN_ERANK);
+            std::atomic<int> next{t0};
+            auto work = [&](int w) {
+                for (;;) {
+                    const int t = next.fetch_add(1);
+                    if (t >= t0 + n) break;
+                    Plan p;
+                    const tn_status s2 = make_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t)),
+                                                   TN_ORDER_PARTITION, p);
+                    if (s2 != TN_OK) {
+                        bs[size_t(w)] = bt[size_t(w)] < 0 ? s2 : bs[size_t(w)];
+                        continue;
+                    }
+                    const double c = plan_cost(p);
+                    if (bt[size_t(w)] < 0 || c < bc[size_t(w)] || (c == bc[size_t(w)] && t < bt[size_t(w)])) {
+                        best[size_t(w)] = std::move(p);
+                        bc[size_t(w)] = c;
+                        bt[size_t(w)] = t;
+                        bs[size_t(w)] = TN_OK;
+                    }
+                }
+            };
+            std::vector<std::thread> pool;
+            for (int w = 1; w < T; ++w) pool.emplace_back(work, w);
+            work(0);
+            for (auto& th : pool) th.join();
+            for (int w = 0; w < T; ++w) consider(bs[size_t(w)], best[size_t(w)]);
+        };
         {
             Plan p;
             consider(plan_of(TN_ORDER_GREEDY, p), p);
         }
-        partition_trial(0);
-        partition_trial(1);
-        for (int t = 2; t < 4 && !over_budget(); ++t) partition_trial(t);
-        if (!over_budget()) {
-            Plan p;
-            consider(plan_of(TN_ORDER_COMMUNITY, p), p);
+        if (threads <= 1) {
+            partition_trial(0);
+            partition_trial(1);
+            for (int t = 2; t < 4 && !over_budget(); ++t) partition_trial(t);
+            if (!over_budget()) {
+                Plan p;
+                consider(plan_of(TN_ORDER_COMMUNITY, p), p);
+            }
+            for (int t = 4; t < kPartitionTrials && !over_budget(); ++t) partition_trial(t);
+        } else {
+            // rounds of one trial per thread, Girvan-Newman after the first,
+            // while the search stays within its time budget
+            parallel_trials(0, threads);
+            if (!over_budget()) {
+                Plan p;
+                consider(plan_of(TN_ORDER_COMMUNITY, p), p);
+            }
+            for (int t = threads; t < kPartitionTrials * threads && !over_budget(); t += threads)
+                parallel_trials(t, threads);
         }
-        for (int t = 4; t < kPartitionTrials && !over_budget(); ++t) partition_trial(t);
         // local reconfiguration of the winner's contraction tree
         if (have && out.merges.size() > 2) {
             const double budget = std::min(kRefineCapUs, kRefineRatio * plan_cost(out));
@@ -201,7 +263,7 @@ tn_status tn_order(const tn_network* net, tn_order_kind kind, uint64_t seed, con
     *out = nullptr;
     tn_plan* h = new (std::nothrow) tn_plan;
     if (!h) return TN_ENOMEM;
-    tn_status st = make_order(net->net, kind, seed, model, h->plan);
+    tn_status st = make_order(net->net, kind, seed, model, h->plan, search_threads());
     if (st != TN_OK) {
         delete h;
         return st;

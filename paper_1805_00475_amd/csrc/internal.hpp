@@ -117,7 +117,10 @@ std::vector<std::pair<int32_t, int32_t>> refine_order(const Network& net,
 tn_status verify_plan(const Plan& plan);
 
 // api.cpp: order of any kind (with the judge for BEST / LEARNED) + plan
-tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out);
+// threads: host threads for the judge's randomized bisection trials (one
+// order search; the batch path runs one search per thread with threads = 1)
+tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out,
+                     int threads = 1);
 
 // contract.hip
 struct Resolved {
