@@ -12,7 +12,8 @@
 
 namespace tn {
 
-enum KernelClass { KC_GENERIC = 0, KC_STREAM = 1, KC_ROWDOT = 2, KC_MFMA = 3, KC_BATCH = 4, KC_DOT = 5, KC_DIGITS = 6 };
+enum KernelClass { KC_GENERIC = 0, KC_STREAM = 1, KC_ROWDOT = 2, KC_MFMA = 3, KC_BATCH = 4, KC_DOT = 5, KC_DIGITS = 6,
+                  KC_NARROW = 7 };
 
 struct Profiler {
     bool on = false;

@@ -256,3 +256,34 @@ def test_mfma8_output_rank_30_to_32_sampled():
     _check_big(26, 19, 7, 254, seed=33, samples=400)
     _check_big(27, 13, 5, 253, seed=34, samples=2000)
     _check_big(28, 28, 12, 255, seed=35, samples=100)
+
+
+NARROW = [
+    (12, 8, 6),     # 2^6 A rows (a partial tile), 2^2 B rows, K = 64 (one-MFMA chunks)
+    (13, 13, 7),    # 64 x 64, K = 128
+    (16, 11, 8),    # 2^8 rows x 8
+    (18, 15, 10),   # 2^8 rows x 32 (two B blocks)
+    (20, 10, 10),   # 2^10 rows x 1
+    (17, 17, 11),   # 64 x 64 at K = 2^11
+    (26, 21, 16),   # 2^10 rows x 32, K = 2^16: split over block rows
+]
+
+
+@pytest.mark.parametrize("rA,rB,s", NARROW)
+@pytest.mark.parametrize("m", [255, 254, 7])
+def test_narrow_kernel(rA, rB, s, m):
+    _check(rA, rB, s, "narrow", m, seed=rA * 7 + m, samples=None if rA + rB - 2 * s <= 12 else 1500)
+
+
+@pytest.mark.parametrize("kind", ["plus", "mixed"])
+def test_narrow_kernel_extremes_and_flush(kind):
+    # K = 2^17 at the largest products: the int32 sums are reduced after 2^16
+    _check(24, 21, 17, "narrow", 255, seed=41, kind=kind, samples=200)
+    _check(15, 12, 9, "narrow", 251, seed=42, kind=kind)
+
+
+def test_narrow_refuses_wide_b():
+    A = np.zeros(1 << 16, np.uint32)
+    B = np.zeros(1 << 16, np.uint32)
+    with pytest.raises(tn.TNError):
+        tn.step(A, 16, B, 16, 8, (1 << 8) - 1, prime=255, kernel="narrow")   # 2^8 B rows
