@@ -90,10 +90,11 @@ typedef enum {
     TN_ORDER_GREEDY = 0,     /* Sec. 3.1.1 tensor-greedy: smallest result rank first */
     TN_ORDER_PARTITION = 1,  /* Sec. 3.1.1 tensor-METIS: recursive best-of-2 bisection */
     TN_ORDER_COMMUNITY = 2,  /* Sec. 3.1.1 tensor-GN: Girvan-Newman split tree */
-    TN_ORDER_LEARNED = 3,    /* MLP pair scorer, judged against greedy and partition */
-    TN_ORDER_BEST = 4,       /* cheapest of greedy, community and up to 16 randomized partitions,
-                                searched while the host time spent stays below the best
-                                plan's predicted device time */
+    TN_ORDER_LEARNED = 3,    /* MLP pair scorer judged against greedy; plans predicted above
+                                50 ms go on to the full judge as its incumbent */
+    TN_ORDER_BEST = 4,       /* cheapest of greedy, community and randomized partitions (rounds
+                                of one per host thread), searched while the host time spent
+                                stays below twice the best plan's predicted device time */
     TN_ORDER_LEARNED_RAW = 5 /* the learned order alone, not judged (evaluation) */
 } tn_order_kind;
 
@@ -111,7 +112,7 @@ typedef struct {
     double log2_cost;              /* log2 of the predicted device time (us) used to judge orders */
     uint64_t peak_elems;           /* arena high-water mark in entries, one prime */
     int32_t chosen;                /* tn_order_kind that produced the plan */
-    int32_t fallback;              /* 1 when the learned order lost to the judge */
+    int32_t fallback;              /* TN_ORDER_LEARNED: 1 when the plan kept is not the learned one */
     int32_t refined;               /* 1 when local tree reconfiguration improved the plan */
 } tn_plan_stats;
 
@@ -313,9 +314,10 @@ tn_status tn_step(const void* A, int32_t rA, const void* B, int32_t rB, int32_t 
  * features (ranks, shared bonds, result rank, neighbour counts; see
  * order_learned.cpp): h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2),
  * y = w3 . h2 + b3 with hidden width 128, fp32. The learned order contracts
- * the best-scoring pair at every step; tn_order(TN_ORDER_LEARNED) then lets
- * the judge keep it only when its predicted cost beats greedy, partition and
- * community (the fallback, Sec. 4: portfolio and lazy evaluation).
+ * the best-scoring pair at every step; tn_order(TN_ORDER_LEARNED) keeps it
+ * when its predicted cost is at most greedy's, else greedy's plan, and hands
+ * the kept plan to the full judge as its incumbent when it is predicted to
+ * take more than 50 ms on the device (Sec. 4: portfolio and lazy evaluation).
  * Parameters are packed as W1 [128 x 10], b1 [128], W2 [128 x 128], b2 [128],
  * w3 [128], b3 (tn_model_param_count() floats). */
 int32_t tn_model_param_count(void);

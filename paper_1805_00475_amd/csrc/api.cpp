@@ -16,6 +16,11 @@ namespace tn {
 constexpr int kPartitionTrials = 16;
 // host microseconds of order search allowed per predicted device microsecond
 constexpr double kSearchRatio = 2.0;
+// predicted device microseconds above which the learned order's judged plan
+// is handed to the full judge as its incumbent: a parallel round of
+// bisection trials on 1-in-3 instances of n <= 250 costs at most about
+// 10 ms of host time, so plans predicted above 50 ms are worth a search
+constexpr double kEscalateUs = 50000.0;
 // most host time spent reconfiguring one plan, and its share of the
 // predicted device time (measured on n = 200 cubic vertex-cover batches:
 // 0.5 gives 45.1 counts/s against 44.2 at 2, 43.4 at 0.25 and 39.0 without
@@ -61,8 +66,10 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             // The learned order judged by the greedy order (Sec. 4: portfolio
             // with lazy cost prediction): both plans cost well under the
             // contraction they order, and the cheaper under the cost model is
-            // kept (fallback = 1 when greedy wins). Only when neither fits the
-            // rank cap does the full judge below run.
+            // kept (fallback = 1 when it is not the learned plan). When the
+            // kept plan's predicted device time exceeds what a round of the
+            // full judge's trials costs on the host, or neither fits the rank
+            // cap, the full judge below runs with it as the incumbent.
             bool ok = false;
             auto lm = order_learned(N, model, &ok);
             Plan lp, gp;
@@ -70,11 +77,13 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             const bool gok = make_plan(N, order_greedy(N), TN_ORDER_GREEDY, gp) == TN_OK;
             if (lok && (!gok || plan_cost(lp) <= plan_cost(gp))) {
                 out = std::move(lp);
-                return TN_OK;
-            }
-            if (gok) {
+                have = true;
+            } else if (gok) {
                 out = std::move(gp);
-                out.stats.fallback = 1;
+                have = true;
+            }
+            if (have && plan_cost(out) <= kEscalateUs) {
+                out.stats.fallback = out.stats.chosen != TN_ORDER_LEARNED;
                 return TN_OK;
             }
         }
@@ -148,7 +157,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             for (auto& th : pool) th.join();
             for (int w = 0; w < T; ++w) consider(bs[size_t(w)], best[size_t(w)]);
         };
-        {
+        if (kind != TN_ORDER_LEARNED) {
             Plan p;
             consider(plan_of(TN_ORDER_GREEDY, p), p);
         }
@@ -183,9 +192,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 out = std::move(p);
             }
         }
-        // (learned: reached only when neither the learned nor the greedy plan
-        // fits the rank cap)
-        if (kind == TN_ORDER_LEARNED && have) out.stats.fallback = 1;
+        if (kind == TN_ORDER_LEARNED && have) out.stats.fallback = out.stats.chosen != TN_ORDER_LEARNED;
         return have ? TN_OK : last;
     } catch (const std::bad_alloc&) {
         return TN_ENOMEM;

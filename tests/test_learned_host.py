@@ -1,12 +1,17 @@
 """Host-side checks of the learned order: features and labels of the
 library's traces against the oracle's recomputation, the host forward pass
 against float64, validity of learned orders and the judge's fallback."""
+import os
+
 import numpy as np
 import pytest
 
 import instances as I
 from oracle import cost, mlp, tensors
 from paper_1805_00475_amd import tn
+
+MODEL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1805_00475_amd", "models",
+                     "order_mlp.npy")
 
 
 def _labels(f):
@@ -81,3 +86,23 @@ def test_learned_without_model_is_the_judge():
     net = tn.Network(I.cvc(60, 1))
     lp = net.order("learned", seed=0)
     assert lp.stats["fallback"] and lp.stats["chosen"] in ("greedy", "partition", "community")
+
+
+def test_learned_hands_costly_plans_to_the_judge():
+    # held-out instance 40: the learned order exceeds the rank cap and
+    # greedy's plan is predicted at seconds; the judge, given it as the
+    # incumbent, must return a plan no costlier and flag the fallback
+    model = tn.Model.load_file(MODEL)
+    net = tn.Network(I.learned_instance(40, "heldout"))
+    g = net.order("greedy")
+    assert 2 ** g.stats["log2_cost"] > 50000.0
+    lp = net.order("learned", seed=40, model=model)
+    assert lp.verify()
+    assert lp.stats["log2_cost"] <= g.stats["log2_cost"] + 1e-9
+    assert 2 ** lp.stats["log2_cost"] < 2 ** g.stats["log2_cost"] / 10
+    assert lp.stats["fallback"] == (lp.stats["chosen"] != "learned")
+    # a cheap instance stays with the learned or greedy plan (no search)
+    small = tn.Network(I.learned_instance(1, "heldout"))
+    sp = small.order("learned", seed=1, model=model)
+    if 2 ** sp.stats["log2_cost"] <= 50000.0:
+        assert sp.stats["chosen"] in ("learned", "greedy")
