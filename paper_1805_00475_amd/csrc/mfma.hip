@@ -388,10 +388,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma(StepArgs a, MfmaExtra ex, 
 // buffers 2 and 3.
 //
 // LDS rows are 128 bytes (8 slots of 16 bytes; slot 4 d + q = bytes 16 q..
-// of plane d), slot c of row r stored at slot c ^ ((r / 2) % 8). A fragment
-// read has a quarter-wave on 16 consecutive rows at one logical slot: rows
-// of equal parity land on 8 distinct slots and the two parities on the two
-// halves of the 256-byte bank width, so all 64 banks are hit once.
+// of plane d), slot c of row r stored at slot c ^ (r % 8). A 16-byte read is
+// served eight lanes at a time, free of bank conflicts when they cover 128
+// distinct bytes modulo 128; a fragment read has eight consecutive lanes on
+// eight consecutive rows (128 bytes apart) at one logical slot, which the
+// XOR sends to eight distinct slots.
 constexpr int kSqM = 128, kSqN = 128, kSqRow = 128;
 constexpr int kSqBuf = (kSqM + kSqN) * kSqRow;  // 32 KiB
 constexpr int kSqBufs = 4;
@@ -479,15 +480,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_mfma_sq(StepArgs a, MfmaExtra e
     const uint64_t offLow = pdep64(uint64_t(4 * tid), TM);
     const uint32_t iLow = uint32_t(pext64(offLow, a.maskA)), jLow = uint32_t(pext64(offLow, a.maskB));
     // loads: lane l of wave w fills physical slot l % 8 of row 8 w + l / 8,
-    // i.e. logical slot c = (l % 8) ^ ((4 w + l / 16) % 8): bytes 16 c.. of
-    // the row's chunk (plane c / 4)
+    // i.e. logical slot c = (l % 8) ^ ((l / 8) % 8): bytes 16 c.. of the
+    // row's chunk (plane c / 4)
     const uint32_t ldRow = uint32_t(8 * w + (lane >> 3));
-    const uint32_t ldSlot = uint32_t((lane & 7) ^ ((4 * (w & 1) + (lane >> 4)) & 7));
+    const uint32_t ldSlot = uint32_t((lane & 7) ^ ((lane >> 3) & 7));
     const uint32_t voff = ldRow * uint32_t(rowBytes) + 16 * ldSlot;
     const uint64_t rows64 = 64 * rowBytes;
     uint8_t* const ldsW = lds + w * 1024;
     const int fr = lane & 15, q = lane >> 4;
-    const int sw[kDigits] = {((0 + q) ^ (fr >> 1)) * 16, ((4 + q) ^ (fr >> 1)) * 16};
+    const int sw[kDigits] = {((0 + q) ^ (fr & 7)) * 16, ((4 + q) ^ (fr & 7)) * 16};
     // output staging: the residue of tile-local (i, j) sits at word
     // stage_pos(i, j), a linear (XOR) map chosen on the host so that both the
     // MFMA-layout writes and the C-order reads of a wave hit 64 distinct banks

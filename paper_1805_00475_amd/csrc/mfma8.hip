@@ -21,9 +21,13 @@
 // stage's fragments while the current stage's MFMAs run.
 //
 // LDS rows: 4 slots of 16 bytes, slot c of row r stored at slot
-// c ^ ((r / 4) % 4). A fragment read has a quarter-wave on 16 consecutive
-// rows at one logical slot; the four rows of each 256-byte bank line land on
-// four distinct slots, so all 64 banks are hit once.
+// c ^ ((r / 2) % 4). A 16-byte read is served eight lanes at a time, and
+// eight lanes free of bank conflicts cover 128 distinct bytes modulo 128. A
+// fragment read has eight consecutive lanes on eight consecutive rows at one
+// logical slot: rows of one parity lie 128 bytes apart, and (r / 2) % 4 sends
+// the four rows of each parity to four distinct slots. (Measured on gfx950:
+// 212 B/clk per CU with this map, 124 B/clk with c ^ ((r / 4) % 4), whose
+// eight lanes meet in pairs.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -280,12 +284,14 @@ __global__ __launch_bounds__(G::THREADS, 1) void k_mfma8(StepArgs a, Mfma8Extra 
     // pressure
     lconst[tid] = lane_offset8<RA>(a, ex, wr, wc, lane);
     // loads: lane l of wave w, instruction i fills physical slot l % 4 of
-    // stage row GROUP i + 16 w + l / 4, i.e. logical slot (l % 4) ^ (l / 16):
-    // bytes 16 ((l % 4) ^ (l / 16)).. of that row's chunk
-    const uint32_t voff = uint32_t(16 * w + (lane >> 2)) * uint32_t(rowBytes) + 16u * uint32_t((lane & 3) ^ (lane >> 4));
+    // stage row r = GROUP i + 16 w + l / 4, i.e. logical slot
+    // (l % 4) ^ ((r / 2) % 4) = (l % 4) ^ ((l / 8) % 4): bytes 16 of that
+    // slot of the row's chunk
+    const uint32_t voff =
+        uint32_t(16 * w + (lane >> 2)) * uint32_t(rowBytes) + 16u * uint32_t((lane & 3) ^ ((lane >> 3) & 3));
     // fragment reads: row wr + fr (A) or WM + wc + fr (B) of a stage, at
     // logical slot q
-    const int sw = 16 * (q ^ (fr >> 2));
+    const int sw = 16 * (q ^ ((fr >> 1) & 3));
     const uint32_t rdA = uint32_t((wr + fr) * k8Row + sw), rdB = uint32_t((G::WM + wc + fr) * k8Row + sw);
     __syncthreads();
 
