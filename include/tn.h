@@ -51,7 +51,7 @@ typedef enum {
     TN_ETOOBIG = -4,       /* the plan's peak memory exceeds the workspace */
     TN_ERANK = -5,         /* a tensor rank exceeds TN_MAX_RANK */
     TN_EBUFSIZE = -6,      /* output buffer too small; the needed size is returned */
-    TN_EUNSUPPORTED = -7   /* a valid request this build does not handle */
+    TN_EUNSUPPORTED = -7   /* a valid request the library does not handle */
 } tn_status;
 
 /* Largest tensor rank the contraction kernels accept: 2^34 entries. */

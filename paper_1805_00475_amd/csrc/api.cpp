@@ -24,8 +24,9 @@ constexpr double kEscalateUs = 50000.0;
 // most host time spent reconfiguring one plan, and its share of the
 // predicted device time (measured on n = 200 cubic vertex-cover batches:
 // 0.5 gives 45.1 counts/s against 44.2 at 2, 43.4 at 0.25 and 39.0 without
-// reconfiguration)
-constexpr double kRefineCapUs = 400000.0;
+// reconfiguration; on the largest 1-in-3 configuration caps of 0.1 s and
+// 0.4 s give the same plans)
+constexpr double kRefineCapUs = 100000.0;
 constexpr double kRefineRatio = 0.5;
 
 // Host threads for one order search: TN_ORDER_THREADS if set, else the
@@ -88,16 +89,30 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             }
         }
         // candidates: greedy, community, and kPartitionTrials randomized
-        // recursive bisections (each itself best-of-2 per level)
+        // recursive bisections (each itself best-of-2 per level); the
+        // cheapest `keep` of them (distinct costs) stay for reconfiguration,
+        // out being the cheapest
+        const size_t keep = size_t(std::max(1, threads));
+        std::vector<Plan> pool;
         auto consider = [&](tn_status s2, Plan& p) {
             if (s2 != TN_OK) {
                 last = s2;
                 return;
             }
-            if (!have || plan_cost(p) < plan_cost(out)) {
+            const double c = plan_cost(p);
+            if (!have || c < plan_cost(out)) {
+                if (have) pool.push_back(std::move(out));
                 out = std::move(p);
                 have = true;
+            } else {
+                pool.push_back(std::move(p));
             }
+            std::sort(pool.begin(), pool.end(), [](const Plan& x, const Plan& y) { return plan_cost(x) < plan_cost(y); });
+            pool.erase(std::unique(pool.begin(), pool.end(),
+                                   [](const Plan& x, const Plan& y) { return plan_cost(x) == plan_cost(y); }),
+                       pool.end());
+            while (!pool.empty() && plan_cost(pool.front()) == plan_cost(out)) pool.erase(pool.begin());
+            if (pool.size() + 1 > keep) pool.resize(keep - 1);
         };
         // Candidates in increasing host cost: greedy, four randomized
         // bisections, Girvan-Newman, then more bisections. After the first
@@ -171,25 +186,51 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             }
             for (int t = 4; t < kPartitionTrials && !over_budget(); ++t) partition_trial(t);
         } else {
-            // rounds of one trial per thread, Girvan-Newman after the first,
-            // while the search stays within its time budget
+            // rounds of one trial per thread while the search stays within
+            // its time budget; Girvan-Newman runs beside the rounds on a
+            // thread of its own (on the largest 1-in-3 configuration it takes
+            // as long as ten rounds)
+            Plan gnp;
+            tn_status gns = TN_EINVAL;
+            std::thread gn([&]() { gns = plan_of(TN_ORDER_COMMUNITY, gnp); });
             parallel_trials(0, threads);
-            if (!over_budget()) {
-                Plan p;
-                consider(plan_of(TN_ORDER_COMMUNITY, p), p);
-            }
             for (int t = threads; t < kPartitionTrials * threads && !over_budget(); t += threads)
                 parallel_trials(t, threads);
+            gn.join();
+            consider(gns, gnp);
         }
-        // local reconfiguration of the winner's contraction tree
+        // local reconfiguration of the contraction trees of the winner and
+        // of the runners-up kept (one per host thread, in parallel, each
+        // with the same time budget); the cheapest result wins
         if (have && out.merges.size() > 2) {
             const double budget = std::min(kRefineCapUs, kRefineRatio * plan_cost(out));
-            Plan p;
-            const int32_t chosen = out.stats.chosen;
-            if (make_plan(N, refine_order(N, out.merges, budget), chosen, p) == TN_OK &&
-                plan_cost(p) < plan_cost(out)) {
-                p.stats.refined = 1;
-                out = std::move(p);
+            std::vector<const Plan*> cand{&out};
+            for (const Plan& p : pool) cand.push_back(&p);
+            std::vector<Plan> ref(cand.size());
+            std::vector<tn_status> rs(cand.size(), TN_EINVAL);
+            std::atomic<size_t> next{0};
+            auto work = [&]() {
+                for (;;) {
+                    const size_t i = next.fetch_add(1);
+                    if (i >= cand.size()) break;
+                    rs[i] = make_plan(N, refine_order(N, cand[i]->merges, budget), cand[i]->stats.chosen, ref[i]);
+                }
+            };
+            std::vector<std::thread> pool_threads;
+            const int T = std::min<int>(threads, int(cand.size()));
+            for (int t = 1; t < T; ++t) pool_threads.emplace_back(work);
+            work();
+            for (auto& th : pool_threads) th.join();
+            int bi = -1;
+            double bc = plan_cost(out);
+            for (size_t i = 0; i < ref.size(); ++i)
+                if (rs[i] == TN_OK && plan_cost(ref[i]) < bc) {
+                    bc = plan_cost(ref[i]);
+                    bi = int(i);
+                }
+            if (bi >= 0) {
+                ref[size_t(bi)].stats.refined = 1;
+                out = std::move(ref[size_t(bi)]);
             }
         }
         if (kind == TN_ORDER_LEARNED && have) out.stats.fallback = out.stats.chosen != TN_ORDER_LEARNED;
