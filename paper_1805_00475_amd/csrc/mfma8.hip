@@ -140,7 +140,10 @@ template <int RA, int CB, bool FOLD, bool PAIR, int P2, int P3>
 __device__ __forceinline__ void store16(const v4i (&acc)[RA][CB], int8_t* C, uint64_t baseC, const Mfma8Extra& ex,
                                         const ModSmall& ms, int lane) {
     typedef uint32_t u4 __attribute__((ext_vector_type(4)));
-    const uint32_t sel = ex.sel[lane & 1];
+    // (a select: indexing the argument array per lane would load it from
+    // memory, and that load's wait would also wait for every load and store
+    // in flight)
+    const uint32_t sel = (lane & 1) ? ex.sel[1] : ex.sel[0];
 #pragma unroll
     for (int g = 0; g < RA * CB; g += 4) {
         uint32_t w[4];
@@ -175,7 +178,10 @@ __device__ __forceinline__ void store_tile8(const v4i (&acc)[RA][CB], int8_t* C,
         case 6: return store16<RA, CB, FOLD, true, 0, 0>(acc, C, baseC, ex, ms, lane);
         default: break;
     }
-    const uint32_t sel = ex.sel[lane & 1];
+    // (a select: indexing the argument array per lane would load it from
+    // memory, and that load's wait would also wait for every load and store
+    // in flight)
+    const uint32_t sel = (lane & 1) ? ex.sel[1] : ex.sel[0];
     if (ex.mode != 2) {
 #pragma unroll
         for (int rb = 0; rb < RA; ++rb) {
@@ -489,9 +495,13 @@ __global__ __launch_bounds__(256) void k_mfma8_reduce(StepArgs a, const int8_t* 
 // rows consecutive in memory, so a wave's fragment load covers 16 whole rows)
 // -- 8 bytes at K offset 8 q, zero where 8 q >= K -- and one
 // v_mfma_i32_16x16x32_i8 per 16x16 block gives the exact sums (at most
-// 32 127^2 < 2^21). The next tile's fragments are loaded before the current
-// tile's outputs are stored.
-template <class G, int S>
+// 32 127^2 < 2^21). Such steps are bound by writing C. A wave takes U tiles
+// per round: their fragments are requested together (each set as soon as its
+// tile's products are issued) and one wait per round covers them. (Loads and
+// stores share one completion counter, so that wait also covers the stores
+// before it; measured on the largest 1-in-3 configuration, U = 2 and 4 are no
+// faster than U = 1.)
+template <class G, int S, int U = 1>
 __global__ __launch_bounds__(G::THREADS) void k_mfma8_short(StepArgs a, Mfma8Extra ex) {
     constexpr int RA = G::RA, CB = G::CB, K = 1 << S;
     const int g = blockIdx.z;
@@ -521,35 +531,43 @@ __global__ __launch_bounds__(G::THREADS) void k_mfma8_short(StepArgs a, Mfma8Ext
             return frag_t(*reinterpret_cast<const uint8_t*>(p));
         }
     };
-    frag_t fa[RA], fb[CB];
-    auto fetch = [&](uint32_t tile) {
+    frag_t fa[U][RA], fb[U][CB];
+    auto fetch = [&](uint32_t tile, int u) {
         uint32_t ta, tb;
         tile_coords_lg(tile, lgA, lgB, ta, tb);
         const int8_t* pA = A + uint64_t(ta) * G::WM * K + offA;
         const int8_t* pB = B + uint64_t(tb) * G::WN * K + offB;
 #pragma unroll
-        for (int rb = 0; rb < RA; ++rb) fa[rb] = load(pA + 16 * K * rb);
+        for (int rb = 0; rb < RA; ++rb) fa[u][rb] = load(pA + 16 * K * rb);
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) fb[cb] = load(pB + 16 * K * cb);
+        for (int cb = 0; cb < CB; ++cb) fb[u][cb] = load(pB + 16 * K * cb);
     };
+    const uint32_t stride = gridDim.x;
     uint32_t tile = blockIdx.x;
     if (tile >= T) return;
-    fetch(tile);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (tile + u * stride < T) fetch(tile + u * stride, u);
     for (;;) {
-        v4i acc[RA][CB];
 #pragma unroll
-        for (int rb = 0; rb < RA; ++rb)
+        for (int u = 0; u < U; ++u) {
+            const uint32_t t = tile + u * stride;
+            if (t >= T) break;
+            v4i acc[RA][CB];
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-                acc[rb][cb] = __builtin_amdgcn_mfma_i32_16x16x32_i8(fa[rb], fb[cb], v4i{0, 0, 0, 0}, 0, 0, 0);
-        const uint32_t next = tile + gridDim.x;
-        uint32_t ta, tb;
-        tile_coords_lg(tile, lgA, lgB, ta, tb);
-        if (next < T) fetch(next);
-        const uint64_t baseC = (pdep64(uint64_t(ta) * G::WM, a.maskA) | pdep64(uint64_t(tb) * G::WN, a.maskB)) | lc;
-        store_tile8<RA, CB, false>(acc, C, baseC, ex, ms, lane);
-        if (next >= T) break;
-        tile = next;
+            for (int rb = 0; rb < RA; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_i32_16x16x32_i8(fa[u][rb], fb[u][cb], v4i{0, 0, 0, 0}, 0, 0, 0);
+            const uint32_t next = t + U * stride;
+            if (next < T) fetch(next, u);
+            uint32_t ta, tb;
+            tile_coords_lg(t, lgA, lgB, ta, tb);
+            const uint64_t baseC = (pdep64(uint64_t(ta) * G::WM, a.maskA) | pdep64(uint64_t(tb) * G::WN, a.maskB)) | lc;
+            store_tile8<RA, CB, false>(acc, C, baseC, ex, ms, lane);
+        }
+        tile += U * stride;
+        if (tile >= T) break;
     }
 }
 
