@@ -9,9 +9,13 @@ intermediate rank (the lazy cost check of Sec. 4) lies in [30, 32]; its
 judged plan reaches rank 31 (2^31 residues per modulus). A step is one pass
 of the whole path over that formula: build the network, order it on the host,
 contract on the GPU in 42 small moduli, recombine by CRT. The timed region
-starts with the formula in host memory; every count is exact.
+starts with the formula in host memory; every count is exact. Steps are
+pipelined as a stream of counts would run: the host part of step k + 1
+(build and judged order) overlaps the contraction of step k; ``--serial``
+times them back to back, and the ``serial`` key gives the latency of one
+count from the warm-up steps.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--serial] [--no-extras] [--no-cpu-baseline]
 
 Prints one JSON line. ``roofline`` is the dominant kernel class (the int8
 matrix-core kernels), from hipEvents around every launch of the timed steps;
@@ -74,6 +78,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serial", action="store_true",
+                    help="headline steps one after the other (default: the host part of the next step overlaps "
+                         "the contraction of the current one)")
     ap.add_argument("--c4-batch", type=int, default=4096, help="instances of the mixed batch (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a plain copy kernel of known size, used to scale "
@@ -141,32 +148,66 @@ def c3_formula(I):
 
 
 def headline(tn, I, ws, args):
+    """Counts of the headline formula, one per step. Each step builds the
+    network, orders it (the judge, on the host's cores), contracts it on the
+    GPU and recombines by CRT. By default the steps are pipelined: the host
+    part of step k + 1 (build and order, on a worker thread; the library
+    releases the interpreter lock) runs while step k contracts on the GPU
+    from the main thread, as a stream of counts would run. ``--serial``
+    times the steps one after the other. The warm-up steps run serially and
+    give the latency of one count and its host share."""
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     f = c3_formula(I)
 
-    def one(flags=0):
+    def host_part():
+        t = time.perf_counter()
         net = tn.Network(f)
         plan = net.order("best", seed=C3["seed"])
-        return tn.count_plan(net, plan, workspace=ws, flags=flags), plan
+        return net, plan, time.perf_counter() - t
 
     ref = None
+    lat, host = [], []
     for w in range(args.warmup):
-        ref, plan = one()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        net, plan, h = host_part()
+        ref = tn.count_plan(net, plan, workspace=ws)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t)
+        host.append(h)
         log(f"warmup {w + 1}/{args.warmup} done")
     acc = Acc(tn)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     got = []
-    for k in range(args.steps):
-        c, plan = one(tn.FLAG_TIMING)
-        acc.add()
-        got.append(c)
-        log(f"timed step {k + 1}/{args.steps} done")
+    if args.serial:
+        for k in range(args.steps):
+            net, plan, _ = host_part()
+            got.append(tn.count_plan(net, plan, workspace=ws, flags=tn.FLAG_TIMING))
+            acc.add()
+            log(f"timed step {k + 1}/{args.steps} done")
+    else:
+        with ThreadPoolExecutor(1) as ex:
+            fut = ex.submit(host_part)
+            for k in range(args.steps):
+                net, plan, _ = fut.result()
+                if k + 1 < args.steps:
+                    fut = ex.submit(host_part)
+                got.append(tn.count_plan(net, plan, workspace=ws, flags=tn.FLAG_TIMING))
+                acc.add()
+                log(f"timed step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     if len(set(got)) != 1 or (ref is not None and got[0] != ref):
         raise SystemExit("counts changed between passes")
-    return f, plan, got[0], t1 - t0, acc
+    # the first warm-up step includes one-time set-up: latency from the others
+    tail = lat[1:] or lat
+    htail = host[1:] or host
+    serial = {"latency_ms_per_count": round(1000 * sum(tail) / len(tail), 1),
+              "host_ms_per_count": round(1000 * sum(htail) / len(htail), 1),
+              "samples": len(tail)} if lat else None
+    return f, plan, got[0], t1 - t0, acc, serial
 
 
 def cvc_rates(tn, I, ws):
@@ -392,8 +433,8 @@ def cpu_complete(I):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(how the path would shard over several GPUs is described in DESIGN.md)"}))
+        print(json.dumps({"error": "the library runs the path on one GPU: --gpus must be 1 "
+                          "(several GPUs would each take a share of the moduli; not implemented)"}))
         sys.exit(2)
     import torch
     import instances as I
@@ -410,7 +451,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    f, plan, count, sec, acc = headline(tn, I, ws, args)
+    f, plan, count, sec, acc, serial = headline(tn, I, ws, args)
     mods = tn.moduli(plan)
     value = args.steps / sec
     mf = acc.cls["mfma"]
@@ -436,10 +477,13 @@ def main():
                                 f"m={f.n_clauses} (alpha={C3['alpha']}), seed {C3['seed']}: the largest "
                                 f"configuration whose predicted max rank is in [30,32]; best order (max rank "
                                 f"{plan.stats['max_rank']}), {len(mods)} small moduli (centred int8 residues) + "
-                                f"CRT; one formula per step, whole path (build, order, contract, CRT)"),
+                                f"CRT; one formula per step, whole path (build, order, contract, CRT)"
+                                + ("" if args.serial else "; steps pipelined: the next step's build and order "
+                                   "run on the host while the current step contracts on the GPU")),
                    "n": C3["n"], "m": f.n_clauses, "alpha": C3["alpha"], "seed": C3["seed"],
                    "max_rank": plan.stats["max_rank"], "moduli": len(mods), "order": plan.stats["chosen"],
-                   "count_bits": count.bit_length()},
+                   "count_bits": count.bit_length(), "pipelined": not args.serial},
+        "serial": serial,
         "roofline": roof,
         "hbm_roofline": hbm_roofline(acc.launches),
         "kernel_classes": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)}
