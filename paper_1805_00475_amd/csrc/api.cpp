@@ -12,8 +12,10 @@
 
 namespace tn {
 
-// randomized bisection trials the judge may try per search thread
+// randomized bisection trials the judge may try per search thread: by the
+// default rule, and with an explicit host-time budget
 constexpr int kPartitionTrials = 16;
+constexpr int kMaxBudgetRounds = 256;
 // host microseconds of order search allowed per predicted device microsecond
 constexpr double kSearchRatio = 2.0;
 // predicted device microseconds above which the learned order's judged plan
@@ -40,7 +42,8 @@ int search_threads() {
     return int(std::min(16u, std::max(1u, hw)));
 }
 
-tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out, int threads) {
+tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out, int threads,
+                     double search_us) {
     try {
         auto plan_of = [&](int32_t k, Plan& p) -> tn_status {
             switch (k) {
@@ -128,8 +131,10 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         auto over_budget = [&]() {
             const double spent_us =
                 std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+            if (search_us > 0) return have && spent_us > search_us;
             return have && spent_us > kSearchRatio * plan_cost(out);
         };
+        const int rounds = search_us > 0 ? kMaxBudgetRounds : kPartitionTrials;
         auto partition_trial = [&](int t) {
             Plan p;
             tn_status s2 = make_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t)),
@@ -184,7 +189,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 Plan p;
                 consider(plan_of(TN_ORDER_COMMUNITY, p), p);
             }
-            for (int t = 4; t < kPartitionTrials && !over_budget(); ++t) partition_trial(t);
+            for (int t = 4; t < rounds && !over_budget(); ++t) partition_trial(t);
         } else {
             // rounds of one trial per thread while the search stays within
             // its time budget; Girvan-Newman runs beside the rounds on a
@@ -194,7 +199,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             tn_status gns = TN_EINVAL;
             std::thread gn([&]() { gns = plan_of(TN_ORDER_COMMUNITY, gnp); });
             parallel_trials(0, threads);
-            for (int t = threads; t < kPartitionTrials * threads && !over_budget(); t += threads)
+            for (int t = threads; t < rounds * threads && !over_budget(); t += threads)
                 parallel_trials(t, threads);
             gn.join();
             consider(gns, gnp);
@@ -307,11 +312,16 @@ tn_status tn_network_info(const tn_network* net, int32_t* n_tensors, int32_t* n_
 
 tn_status tn_order(const tn_network* net, tn_order_kind kind, uint64_t seed, const tn_model* model,
                    tn_plan** out, tn_plan_stats* stats) {
-    if (!net || !out) return TN_EINVAL;
+    return tn_order_budget(net, kind, seed, model, 0.0, out, stats);
+}
+
+tn_status tn_order_budget(const tn_network* net, tn_order_kind kind, uint64_t seed, const tn_model* model,
+                          double search_us, tn_plan** out, tn_plan_stats* stats) {
+    if (!net || !out || !(search_us >= 0.0)) return TN_EINVAL;
     *out = nullptr;
     tn_plan* h = new (std::nothrow) tn_plan;
     if (!h) return TN_ENOMEM;
-    tn_status st = make_order(net->net, kind, seed, model, h->plan, search_threads());
+    tn_status st = make_order(net->net, kind, seed, model, h->plan, search_threads(), search_us);
     if (st != TN_OK) {
         delete h;
         return st;

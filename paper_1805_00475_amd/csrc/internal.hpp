@@ -118,9 +118,11 @@ tn_status verify_plan(const Plan& plan);
 
 // api.cpp: order of any kind (with the judge for BEST / LEARNED) + plan
 // threads: host threads for the judge's randomized bisection trials (one
-// order search; the batch path runs one search per thread with threads = 1)
+// order search; the batch path runs one search per thread with threads = 1);
+// search_us > 0: the judge's trials continue until that much host time is
+// spent (at most kMaxBudgetRounds rounds) instead of the default rule
 tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out,
-                     int threads = 1);
+                     int threads = 1, double search_us = 0.0);
 
 // contract.hip
 struct Resolved {
