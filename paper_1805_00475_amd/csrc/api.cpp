@@ -15,7 +15,7 @@ namespace tn {
 // randomized bisection trials the judge may try per search thread: by the
 // default rule, and with an explicit host-time budget
 constexpr int kPartitionTrials = 16;
-constexpr int kMaxBudgetRounds = 256;
+constexpr int kMaxBudgetRounds = 48;
 // host microseconds of order search allowed per predicted device microsecond
 constexpr double kSearchRatio = 2.0;
 // predicted device microseconds above which the learned order's judged plan
