@@ -150,12 +150,15 @@ def _gold(name):
 
 
 def test_moduli_choice():
+    from math import prod
     f = I.cvc(200, 0)
-    plan = tn.Network(f).order("community")
+    net = tn.Network(f)
+    bits = net.ranks()[1]  # the count bound that sizes the residues
+    plan = net.order("community")
     small = tn.moduli(plan)
-    assert max(small) <= 255 and len(small) >= 25
+    assert max(small) <= 255 and prod(small) > 2 ** (bits + 1)
     wide = tn.moduli(plan, flags=tn.FLAG_WIDE_RNS)
-    assert wide == tn.primes(tn.primes_for(200))
+    assert wide == tn.primes(tn.primes_for(bits))
     assert tn.moduli(plan, n_primes=9) == tn.primes(9)
     assert tn.moduli(tn.Network(I.cvc(40, 0)).order("community")) == []
 
@@ -171,7 +174,7 @@ def test_wide_and_small_counts_agree():
         assert tn.count(f, "community", seed=it["seed"], flags=tn.FLAG_WIDE_RNS) == want
         assert tn.count(f, "community", seed=it["seed"], flags=tn.FLAG_WIDE_RNS | tn.FLAG_NO_MFMA) == want
         assert tn.count(f, "community", seed=it["seed"], flags=tn.FLAG_NO_MFMA) == want
-    # n = 200 (27 small moduli, 13 primes): the two modes agree
+    # n = 200 (int8 planes of small moduli, or 16-bit primes): the two modes agree
     f = I.cvc(200, 3)
     _say("cvc n=200 seed=3 both residue modes")
     assert tn.count(f, "community", seed=3) == tn.count(f, "community", seed=3, flags=tn.FLAG_WIDE_RNS)

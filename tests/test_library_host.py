@@ -182,22 +182,26 @@ def test_workspace_query_scales_with_prime_group():
 
 
 def test_small_moduli_choice():
-    # n = 200: the fewest of the greedy pairwise coprime integers <= 255
-    # (255, 254, 253, 251, ...) whose product exceeds 2^(n+1)
+    # vertex cover n = 200: the fewest of the greedy pairwise coprime integers
+    # <= 255 (255, 254, 253, 251, ...) whose product exceeds 2^(b+1), b the
+    # network's count bound (below n: the block bound)
     from math import gcd, prod
-    plan = tn.Network(I.cvc(200, 0)).order("community")
+    net = tn.Network(I.cvc(200, 0))
+    bits = net.ranks()[1]
+    assert 64 <= bits < 200
+    plan = net.order("community")
     mods = tn.moduli(plan)
     assert mods[:6] == [255, 254, 253, 251, 247, 241]
     assert all(2 <= m <= 255 for m in mods)
     assert all(gcd(a, b) == 1 for i, a in enumerate(mods) for b in mods[i + 1:])
-    assert prod(mods) > 2 ** 201 and prod(mods[:-1]) <= 2 ** 201
+    assert prod(mods) > 2 ** (bits + 1) and prod(mods[:-1]) <= 2 ** (bits + 1)
     # the greedy rule: each modulus is the largest integer below the previous
     # one that is coprime to all chosen so far
     for i in range(1, len(mods)):
         for c in range(mods[i] + 1, mods[i - 1]):
             assert any(gcd(c, d) > 1 for d in mods[:i])
     # 16-bit primes when asked for, by flag or by count; none for u64 counts
-    assert tn.moduli(plan, flags=tn.FLAG_WIDE_RNS) == tn.primes(tn.primes_for(200))
+    assert tn.moduli(plan, flags=tn.FLAG_WIDE_RNS) == tn.primes(tn.primes_for(bits))
     assert tn.moduli(plan, n_primes=7) == tn.primes(7)
     assert tn.moduli(tn.Network(I.cvc(60, 0)).order("community")) == []
     # beyond what the small moduli hold (about 335 bits): 16-bit primes

@@ -30,7 +30,7 @@ def _fits(net, plan, **kw):
 
 def test_noalloc_matches_contract_on_shrinking_inputs():
     assert tn.noalloc_max_bytes() == 64 << 20
-    # 1: vertex cover n=120, small moduli (27 int8 planes)
+    # 1: vertex cover n=120, small moduli (int8 planes)
     f1 = I.cvc(120, 0)
     n1 = tn.Network(f1)
     p1 = n1.order("best", seed=0)
