@@ -54,3 +54,57 @@ def test_bound_empty_clause_and_cover():
     _check(f)
     g = I.cvc(20, 0)
     _check(g)
+
+
+def _check_large(f, pad):
+    # at least 160 variables in all: blocks of up to 96, counted by
+    # elimination (or split again when too wide); the oracle counts the core
+    from oracle import elim
+    assert f.n_vars + pad >= 160
+    want = elim.count(f) << pad
+    bits = tn.Network(_padded(f, pad)).ranks()[1]
+    assert want <= 1 << bits, (want.bit_length(), bits)
+    return bits
+
+
+def test_bound_elimination_blocks():
+    rng = I.Rng(2024)
+    for _ in range(4):
+        _check_large(I.exactly_one_3(40, 26, rng), 130)
+    for _ in range(4):
+        f = I.random_mixed_formula(34, 30, rng, max_len=4)
+        f.clauses = [(k if rng.below(3) else I.XOR, c) for k, c in f.clauses]
+        _check_large(f, 130)
+    # the headline family at full size against the stored oracle counts
+    import json, os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c3_1in3_counts.json")))
+    for it in gold["items"][:6]:
+        f = I.large_1in3(it["n"], it["alpha"], it["seed"])
+        bits = tn.Network(f).ranks()[1]
+        assert int(it["count"]) <= 1 << bits and bits < it["n"]
+
+
+def test_bound_wide_blocks_split_again():
+    # dense parity systems of 90 variables: eliminating a block of them would
+    # need tables far past the width cap, so blocks are split again; the GF(2)
+    # rank formula counts them
+    from oracle import closed
+    rng = I.Rng(77)
+    for m in (60, 80, 100):
+        # a planted solution keeps the system satisfiable
+        x = [rng.coin() for _ in range(90)]
+        f = I.Formula(90)
+        for _ in range(m):
+            vs = []
+            while len(vs) < 3:
+                v = rng.below(90)
+                if v not in vs:
+                    vs.append(v)
+            lits = [v + 1 for v in vs]
+            if sum(x[v] for v in vs) % 2 == 0:
+                lits[0] = -lits[0]
+            f.clauses.append((I.XOR, lits))
+        want = closed.xorsat_count(f) << 80
+        assert want > 0
+        bits = tn.Network(_padded(f, 80)).ranks()[1]
+        assert want <= 1 << bits, (want.bit_length(), bits)
