@@ -3,33 +3,28 @@
 // product exceeds the bound (Sec. 2.1, the count as the full trace; Sec. 3.2
 // on exactness), so a tighter bound means fewer residue planes.
 //
-// The variables are split into blocks. For an assignment x every clause
-// value is 0 or 1, and a satisfied clause passes these tests on the
-// restriction of x to any block B: a clause lying inside B is satisfied
-// there, and an exactly-one clause that only partly lies in B has at most one
-// true literal there. Hence the product of the clause values is at most the
-// product over blocks of the indicator that x|B passes every test of B, and
-// summing over x, the count is at most the product over blocks of the number
-// of assignments of B passing its tests. Clauses that use a variable twice
-// are left out of the tests (a relaxation), and an empty clause makes the
-// count 0.
+// The count is the sum over assignments of the product of the clause tables
+// (0/1 valued). Variables are eliminated one at a time (fewest neighbours
+// first). When the tables that hold a variable v span at most ib other
+// variables, they are multiplied and v is summed out, as in exact
+// elimination. Otherwise they are split into mini-buckets of at most ib
+// other variables each: v is summed out of the product of the first and
+// maximised out of the product of each other one. For non-negative tables
+//   sum_v prod_j P_j(v, .) <= sum_v P_1(v, .) * prod_{j>1} max_v P_j(v, .),
+// so the result bounds the count from above. Clauses that use a variable
+// twice are left out (every table is at most 1, so dropping one only raises
+// the sum), and an empty clause makes the count 0.
 //
-// Blocks are grown greedily around the variables in most clauses, adding the
-// neighbour that completes most clauses. A block of at most 20 variables is
-// counted by bit slicing (64 assignments of its six lowest variables per
-// machine word); a larger one by variable elimination over its tests in
-// double precision (every table entry is a sum of products of 0/1 values;
-// with at most a few thousand roundings along any path, each of relative
-// size below 2^-53, the result is within a relative 1e-12 of the exact
-// count, and a margin of 1e-6 in log2 covers it). A block whose elimination
-// would need a table over more than kMaxWidth variables is split again into
-// blocks of half its size. Large formulas (from kBigFrom variables) use blocks of up to
-// kBigBlock variables, smaller ones blocks of 16, whose cost is a few
-// milliseconds at most.
+// Tables hold doubles; every new table is scaled by a power of two (exact)
+// so that its largest entry lies in [1, 2), the scale going into a running
+// log2 sum. Entries are sums, products and maxima of non-negative numbers,
+// so each carries a relative rounding error below (k + 2) 2^-53 per
+// elimination it went through (k tables per bucket); over at most n
+// eliminations this stays far below the margin of 1e-6 added in log2.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
-#include <functional>
+#include <set>
 #include <vector>
 
 #include "internal.hpp"
@@ -38,279 +33,144 @@ namespace tn {
 
 namespace {
 
-constexpr int kSmallBlock = 16;
-constexpr int kBigBlock = 96;
-constexpr int kBigFrom = 160;
-constexpr int kSliceMax = 20;
-constexpr int kMaxWidth = 20;
-
-struct Lit {
-    int32_t var;  // block-local
-    bool neg;
-};
-
-struct Test {
-    int kind;     // TN_CLAUSE_*
-    bool inside;  // every literal in the block (else: exactly-one, at most one true here)
-    std::vector<Lit> lits;
-};
-
-struct Formula {
-    const tn_formula* f;
-    std::vector<std::vector<int32_t>> cl_of;  // usable clauses of each variable
-    int32_t var(int64_t i) const { return std::abs(f->lits[i]) - 1; }
-};
-
-// Blocks of at most B variables among those with block_of = -1 (others are
-// placed already), grown from the unplaced variable in most clauses; new
-// block ids start at `first`.
-std::vector<std::vector<int32_t>> grow_blocks(const Formula& F, std::vector<int32_t>& block_of,
-                                              const std::vector<int32_t>& vars, int B, int32_t first) {
-    std::vector<int32_t> order(vars);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return F.cl_of[size_t(a)].size() > F.cl_of[size_t(b)].size();
-    });
-    std::vector<std::vector<int32_t>> blocks;
-    for (int32_t s : order) {
-        if (block_of[size_t(s)] != -1) continue;
-        const int32_t id = first + int32_t(blocks.size());
-        blocks.push_back({s});
-        block_of[size_t(s)] = id;
-        std::vector<int32_t>& blk = blocks.back();
-        while (int(blk.size()) < B) {
-            int32_t best = -1;
-            double bs = -1;
-            for (size_t bi = 0; bi < blk.size(); ++bi)
-                for (int32_t c : F.cl_of[size_t(blk[bi])])
-                    for (int32_t i = F.f->clause_ptr[c]; i < F.f->clause_ptr[c + 1]; ++i) {
-                        const int32_t u = F.var(i);
-                        if (block_of[size_t(u)] != -1) continue;
-                        double sc = 0;
-                        for (int32_t c2 : F.cl_of[size_t(u)]) {
-                            bool all = true, touch = false;
-                            for (int32_t j = F.f->clause_ptr[c2]; j < F.f->clause_ptr[c2 + 1]; ++j) {
-                                const int32_t w = F.var(j);
-                                const bool in = w == u || block_of[size_t(w)] == id;
-                                all = all && in;
-                                touch = touch || (w != u && in);
-                            }
-                            sc += all ? 1.0 : touch ? 0.5 : 0.0;
-                        }
-                        if (sc > bs || (sc == bs && u < best)) {
-                            bs = sc;
-                            best = u;
-                        }
-                    }
-            if (best < 0) break;
-            block_of[size_t(best)] = id;
-            blk.push_back(best);
-        }
-    }
-    return blocks;
-}
-
-// the tests of one block (variables numbered by their place in blk)
-std::vector<Test> block_tests(const Formula& F, const std::vector<int32_t>& block_of,
-                              const std::vector<int32_t>& blk) {
-    std::vector<Test> tests;
-    std::vector<int32_t> seen;
-    const int32_t id = block_of[size_t(blk[0])];
-    for (size_t j = 0; j < blk.size(); ++j)
-        for (int32_t c : F.cl_of[size_t(blk[j])]) {
-            if (std::find(seen.begin(), seen.end(), c) != seen.end()) continue;
-            seen.push_back(c);
-            Test t{F.f->kinds[c], true, {}};
-            for (int32_t i = F.f->clause_ptr[c]; i < F.f->clause_ptr[c + 1]; ++i) {
-                const int32_t w = F.var(i);
-                if (block_of[size_t(w)] != id) {
-                    t.inside = false;
-                    continue;
-                }
-                const int32_t p = int32_t(std::find(blk.begin(), blk.end(), w) - blk.begin());
-                t.lits.push_back({p, F.f->lits[i] < 0});
-            }
-            if (!t.inside && !(t.kind == TN_CLAUSE_EXACTLY_ONE && t.lits.size() >= 2)) continue;
-            tests.push_back(std::move(t));
-        }
-    return tests;
-}
-
-bool passes(const Test& t, int ones) {
-    if (t.kind == TN_CLAUSE_OR) return ones >= 1;
-    if (t.kind == TN_CLAUSE_EXACTLY_ONE) return t.inside ? ones == 1 : ones <= 1;
-    return ones & 1;  // parity
-}
-
-// lane patterns of the six lowest block variables over 64 assignments
-constexpr uint64_t kLane[6] = {0xAAAAAAAAAAAAAAAAull, 0xCCCCCCCCCCCCCCCCull, 0xF0F0F0F0F0F0F0F0ull,
-                               0xFF00FF00FF00FF00ull, 0xFFFF0000FFFF0000ull, 0xFFFFFFFF00000000ull};
-
-uint64_t count_sliced(int k, const std::vector<Test>& tests) {
-    const int low = std::min(k, 6);
-    const uint64_t lanes = low == 6 ? ~uint64_t(0) : ((uint64_t(1) << (1 << low)) - 1);
-    uint64_t word[kSliceMax];
-    uint64_t total = 0;
-    for (uint64_t h = 0; h < (uint64_t(1) << (k - low)); ++h) {
-        for (int j = 0; j < k; ++j) word[j] = j < 6 ? kLane[j] : (((h >> (j - 6)) & 1) ? ~uint64_t(0) : 0);
-        uint64_t ok = lanes;
-        for (const Test& t : tests) {
-            uint64_t one = 0, two = 0, any = 0;  // odd count, two or more, at least one
-            for (const Lit& l : t.lits) {
-                const uint64_t x = l.neg ? ~word[l.var] : word[l.var];
-                two |= one & x;
-                one ^= x;
-                any |= x;
-            }
-            if (t.kind == TN_CLAUSE_OR) ok &= any;
-            else if (t.kind == TN_CLAUSE_EXACTLY_ONE) ok &= t.inside ? (one & ~two) : ~two;
-            else ok &= one;
-            if (!ok) break;
-        }
-        total += uint64_t(__builtin_popcountll(ok));
-    }
-    return total;
-}
+// other variables of a mini-bucket: 15 (tables of up to 2^16 entries) from
+// kBigFrom variables on, 10 below, where the bound costs about 1.5 ms
+// instead of about 10 (vertex cover n = 120: 80 bits against 78)
+constexpr int kIBoundBig = 15, kIBoundSmall = 10, kBigFrom = 160;
 
 struct Table {
     std::vector<int32_t> vars;  // bit i of an index is the value of vars[i]
     std::vector<double> t;
+    bool alive = true;
 };
 
-// log2 of the block count by variable elimination (min-degree order), or NaN
-// when a table would span more than kMaxWidth variables
-double log2_eliminated(int k, const std::vector<Test>& tests) {
-    std::vector<Table> tabs;
-    for (const Test& t : tests) {
-        Table x;
-        for (const Lit& l : t.lits) x.vars.push_back(l.var);
-        const size_t w = x.vars.size();
-        x.t.resize(size_t(1) << w);
-        for (size_t a = 0; a < x.t.size(); ++a) {
-            int ones = 0;
-            for (size_t i = 0; i < w; ++i) ones += int(((a >> i) & 1) ^ (t.lits[i].neg ? 1 : 0));
-            x.t[a] = passes(t, ones) ? 1.0 : 0.0;
-        }
-        tabs.push_back(std::move(x));
+// multiply `src` (over its vars) into `dst`, a table over `scope` (a
+// superset), bit j of an index of dst being scope[j]
+void accumulate(const Table& src, const std::vector<int32_t>& scope, std::vector<double>& dst) {
+    std::vector<int> at(src.vars.size());
+    for (size_t i = 0; i < src.vars.size(); ++i)
+        at[i] = int(std::find(scope.begin(), scope.end(), src.vars[i]) - scope.begin());
+    for (size_t a = 0; a < dst.size(); ++a) {
+        size_t idx = 0;
+        for (size_t i = 0; i < at.size(); ++i) idx |= ((a >> at[i]) & 1) << i;
+        dst[a] *= src.t[idx];
     }
-    std::vector<char> alive(size_t(k), 1);
-    double log2sum = 0;
-    for (int step = 0; step < k; ++step) {
-        // the variable with the fewest neighbours (ties: lowest index)
-        int v = -1;
-        size_t deg = 0;
-        for (int u = 0; u < k; ++u) {
-            if (!alive[size_t(u)]) continue;
-            std::vector<int32_t> nb;
-            for (const Table& x : tabs)
-                if (std::find(x.vars.begin(), x.vars.end(), u) != x.vars.end())
-                    for (int32_t y : x.vars)
-                        if (y != u && std::find(nb.begin(), nb.end(), y) == nb.end()) nb.push_back(y);
-            if (v < 0 || nb.size() < deg) {
-                v = u;
-                deg = nb.size();
-            }
-        }
-        alive[size_t(v)] = 0;
-        std::vector<Table> bucket, rest;
-        for (Table& x : tabs)
-            (std::find(x.vars.begin(), x.vars.end(), v) != x.vars.end() ? bucket : rest).push_back(std::move(x));
-        if (bucket.empty()) {  // a variable in no test: both values pass
-            log2sum += 1.0;
-            tabs = std::move(rest);
-            continue;
-        }
-        std::vector<int32_t> scope;
-        for (const Table& x : bucket)
-            for (int32_t y : x.vars)
-                if (y != v && std::find(scope.begin(), scope.end(), y) == scope.end()) scope.push_back(y);
-        if (int(scope.size()) + 1 > kMaxWidth) return std::nan("");
-        // position of each table variable in (v, scope...)
-        std::vector<std::vector<int>> where(bucket.size());
-        for (size_t b = 0; b < bucket.size(); ++b)
-            for (int32_t y : bucket[b].vars)
-                where[b].push_back(y == v ? 0 : 1 + int(std::find(scope.begin(), scope.end(), y) - scope.begin()));
-        Table out;
-        out.vars = scope;
-        out.t.assign(size_t(1) << scope.size(), 0.0);
-        for (size_t a = 0; a < out.t.size(); ++a) {
-            double s = 0;
-            for (size_t xv = 0; xv < 2; ++xv) {
-                const size_t full = xv | (a << 1);
-                double p = 1;
-                for (size_t b = 0; b < bucket.size() && p != 0; ++b) {
-                    size_t idx = 0;
-                    for (size_t i = 0; i < where[b].size(); ++i) idx |= ((full >> where[b][i]) & 1) << i;
-                    p *= bucket[b].t[idx];
-                }
-                s += p;
-            }
-            out.t[a] = s;
-        }
-        rest.push_back(std::move(out));
-        tabs = std::move(rest);
-        // constant tables go into the running sum
-        for (size_t i = 0; i < tabs.size();) {
-            if (tabs[i].vars.empty()) {
-                if (tabs[i].t[0] <= 0) return -INFINITY;
-                log2sum += std::log2(tabs[i].t[0]);
-                tabs.erase(tabs.begin() + long(i));
-            } else {
-                ++i;
-            }
-        }
-    }
-    return log2sum;
 }
 
 }  // namespace
 
 int32_t count_bound_bits(const tn_formula* f) {
     const int32_t n = f->n_vars, m = f->n_clauses;
-    Formula F{f, std::vector<std::vector<int32_t>>(static_cast<size_t>(n))};
+    const int ib = n >= kBigFrom ? kIBoundBig : kIBoundSmall;
+    std::vector<Table> tabs;
+    std::vector<std::vector<int32_t>> holds(static_cast<size_t>(n));  // tables holding each variable
     for (int32_t c = 0; c < m; ++c) {
         const int32_t b = f->clause_ptr[c], e = f->clause_ptr[c + 1];
         if (b == e) return 0;  // an empty clause: the count is 0
+        Table x;
         bool usable = true;
-        for (int32_t i = b; i < e && usable; ++i)
-            for (int32_t j = b; j < i; ++j)
-                if (F.var(i) == F.var(j)) usable = false;
+        for (int32_t i = b; i < e; ++i) {
+            const int32_t v = std::abs(f->lits[i]) - 1;
+            if (std::find(x.vars.begin(), x.vars.end(), v) != x.vars.end()) usable = false;
+            x.vars.push_back(v);
+        }
         if (!usable) continue;
-        for (int32_t i = b; i < e; ++i) F.cl_of[size_t(F.var(i))].push_back(c);
+        const size_t w = x.vars.size();
+        x.t.resize(size_t(1) << w);
+        for (size_t a = 0; a < x.t.size(); ++a) {
+            int ones = 0;
+            for (size_t i = 0; i < w; ++i) ones += int(((a >> i) & 1) ^ (f->lits[b + int32_t(i)] < 0 ? 1 : 0));
+            const bool ok = f->kinds[c] == TN_CLAUSE_OR ? ones >= 1
+                            : f->kinds[c] == TN_CLAUSE_EXACTLY_ONE ? ones == 1
+                                                                  : (ones & 1) == 1;
+            x.t[a] = ok ? 1.0 : 0.0;
+        }
+        for (int32_t v : x.vars) holds[size_t(v)].push_back(int32_t(tabs.size()));
+        tabs.push_back(std::move(x));
     }
-    std::vector<int32_t> block_of(static_cast<size_t>(n), -1), all(static_cast<size_t>(n));
-    for (int32_t v = 0; v < n; ++v) all[size_t(v)] = v;
-    int32_t next_id = 0;
-    bool zero = false;
-    // bound over the variables `vars` (unplaced) in blocks of at most B; a
-    // block too wide to eliminate is split again into blocks of half the size
-    std::function<double(const std::vector<int32_t>&, int)> bound = [&](const std::vector<int32_t>& vars, int B) {
-        auto blocks = grow_blocks(F, block_of, vars, B, next_id);
-        next_id += int32_t(blocks.size());
-        double bits = 0;
-        for (const auto& blk : blocks) {
-            const int k = int(blk.size());
-            const auto tests = block_tests(F, block_of, blk);
-            if (k <= kSliceMax) {
-                const uint64_t cnt = count_sliced(k, tests);
-                if (cnt == 0) zero = true;
-                else bits += std::log2(double(cnt));
-                continue;
+    std::vector<std::set<int32_t>> adj(static_cast<size_t>(n));
+    for (const Table& x : tabs)
+        for (int32_t u : x.vars)
+            for (int32_t y : x.vars)
+                if (y != u) adj[size_t(u)].insert(y);
+    std::vector<char> alive(static_cast<size_t>(n), 1);
+    double bits = 0;
+    for (int32_t step = 0; step < n; ++step) {
+        int32_t v = -1;
+        size_t deg = 0;
+        for (int32_t u = 0; u < n; ++u)
+            if (alive[size_t(u)] && (v < 0 || adj[size_t(u)].size() < deg)) {
+                v = u;
+                deg = adj[size_t(u)].size();
             }
-            const double lb = log2_eliminated(k, tests);
-            if (lb == -INFINITY) {
-                zero = true;
-            } else if (!std::isnan(lb)) {
-                bits += lb + 1e-6;
-            } else {
-                for (int32_t v : blk) block_of[size_t(v)] = -1;
-                bits += bound(blk, std::max(kSmallBlock, B / 2));
+        alive[size_t(v)] = 0;
+        for (int32_t y : adj[size_t(v)]) adj[size_t(y)].erase(v);
+        std::vector<int32_t> bucket;
+        for (int32_t id : holds[size_t(v)])
+            if (tabs[size_t(id)].alive) bucket.push_back(id);
+        if (bucket.empty()) {  // in no table: both values count
+            bits += 1.0;
+            continue;
+        }
+        // mini-buckets, larger tables first, each into the first whose scope
+        // stays within v and ib others
+        std::stable_sort(bucket.begin(), bucket.end(), [&](int32_t a, int32_t b) {
+            return tabs[size_t(a)].vars.size() > tabs[size_t(b)].vars.size();
+        });
+        std::vector<std::vector<int32_t>> mb, mbscope;
+        for (int32_t id : bucket) {
+            tabs[size_t(id)].alive = false;
+            const auto& vs = tabs[size_t(id)].vars;
+            bool placed = false;
+            for (size_t j = 0; j < mb.size() && !placed; ++j) {
+                std::vector<int32_t> u = mbscope[j];
+                for (int32_t y : vs)
+                    if (std::find(u.begin(), u.end(), y) == u.end()) u.push_back(y);
+                if (int(u.size()) <= ib + 1) {
+                    mbscope[j] = u;
+                    mb[j].push_back(id);
+                    placed = true;
+                }
+            }
+            if (!placed) {
+                mb.push_back({id});
+                mbscope.push_back(vs);
             }
         }
-        return bits;
-    };
-    const double bits = bound(all, n >= kBigFrom ? kBigBlock : kSmallBlock);
-    if (zero) return 0;
-    return int32_t(std::min<double>(double(n), std::ceil(bits + 1e-9)));
+        for (size_t j = 0; j < mb.size(); ++j) {
+            // v first, then the others
+            std::vector<int32_t> scope{v};
+            for (int32_t y : mbscope[j])
+                if (y != v) scope.push_back(y);
+            std::vector<double> prod(size_t(1) << scope.size(), 1.0);
+            for (int32_t id : mb[j]) accumulate(tabs[size_t(id)], scope, prod);
+            Table out;
+            out.vars.assign(scope.begin() + 1, scope.end());
+            out.t.resize(prod.size() / 2);
+            double mx = 0;
+            for (size_t a = 0; a < out.t.size(); ++a) {
+                const double lo = prod[2 * a], hi = prod[2 * a + 1];
+                out.t[a] = j == 0 ? lo + hi : std::max(lo, hi);
+                mx = std::max(mx, out.t[a]);
+            }
+            if (mx <= 0) return 0;  // no assignment passes: the count is 0
+            int e = 0;
+            (void)std::frexp(mx, &e);  // mx in [2^(e-1), 2^e)
+            for (double& x : out.t) x = std::ldexp(x, 1 - e);
+            bits += double(e - 1);
+            if (out.vars.empty()) {
+                bits += std::log2(out.t[0]);
+                continue;
+            }
+            for (int32_t u : out.vars) {
+                holds[size_t(u)].push_back(int32_t(tabs.size()));
+                for (int32_t y : out.vars)
+                    if (y != u) adj[size_t(u)].insert(y);
+            }
+            tabs.push_back(std::move(out));
+        }
+    }
+    return int32_t(std::min<double>(double(n), std::ceil(bits + 1e-6)));
 }
 
 }  // namespace tn

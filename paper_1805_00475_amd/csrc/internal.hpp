@@ -117,7 +117,7 @@ std::vector<std::pair<int32_t, int32_t>> refine_order(const Network& net,
 tn_status verify_plan(const Plan& plan);
 
 // count_bound.cpp: ceil(log2) of an upper bound on the count of a boolean
-// formula (block products; at most n_vars; 0 when a clause is empty)
+// formula (mini-bucket elimination; at most n_vars; 0 when a clause is empty)
 int32_t count_bound_bits(const tn_formula* f);
 
 // api.cpp: order of any kind (with the judge for BEST / LEARNED) + plan

@@ -178,7 +178,7 @@ tn_status build_network(const tn_formula* f, Network& net) {
         }
         for (int32_t v = 0; v < f->n_vars; ++v)
             if (int(net.t[v].bonds.size()) > TN_MAX_INIT_RANK) return TN_ERANK;
-        // beyond 63 variables, the block bound (count_bound.cpp) sizes the
+        // beyond 63 variables, the elimination bound (count_bound.cpp) sizes the
         // residues; it is kept at 64 bits or more, so such formulas stay
         // with small moduli rather than 64-bit counts
         if (f->n_vars > 63) net.count_bits = std::max<int32_t>(64, count_bound_bits(f));
