@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--search-ms", type=float, default=None,
-                    help="host-time budget of the judge in the timed steps (default: 0.6 of a count's device "
+                    help="host-time budget of the judge in the timed steps (default: 0.7 of a count's device "
                          "time when pipelined, the default search when serial)")
     ap.add_argument("--serial", action="store_true",
                     help="headline steps one after the other (default: the host part of the next step overlaps "
@@ -159,7 +159,7 @@ def headline(tn, I, ws, args):
     from the main thread, as a stream of counts would run. ``--serial``
     times the steps one after the other. The warm-up steps run serially (the
     judge's default search) and give the latency of one count and its host
-    share; pipelined, the judge then searches for up to 0.6 of one count's
+    share; pipelined, the judge then searches for up to 0.7 of one count's
     device time (tn_order_budget), time that the contraction of the previous
     count hides."""
     import torch
@@ -186,13 +186,14 @@ def headline(tn, I, ws, args):
         host.append(h)
         log(f"warmup {w + 1}/{args.warmup} done")
     # pipelined, the judge's search overlaps the previous count's contraction:
-    # give it host time up to 0.6 of the device time of one count (measured
-    # in the warm-up steps), leaving room for its refinement and the build
+    # give it host time up to 0.7 of the device time of one count (measured
+    # in the warm-up steps; trial rounds and refinement), leaving room for
+    # the build
     if args.search_ms is not None:
         budget["ms"] = args.search_ms
     elif not args.serial and lat:
         dev = sum(x - y for x, y in zip(lat[1:] or lat, host[1:] or host)) / len(lat[1:] or lat)
-        budget["ms"] = round(600.0 * dev, 1)
+        budget["ms"] = round(700.0 * dev, 1)
     acc = Acc(tn)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -495,7 +496,7 @@ def main():
                                 f"{plan.stats['max_rank']}), {len(mods)} small moduli (centred int8 residues) + "
                                 f"CRT; one formula per step, whole path (build, order, contract, CRT)"
                                 + ("" if args.serial else "; steps pipelined: the next step's build and order "
-                                   "(judge searching for up to 0.6 of a count's device time) run on the host "
+                                   "(judge searching for up to 0.7 of a count's device time) run on the host "
                                    "while the current step contracts on the GPU")),
                    "n": C3["n"], "m": f.n_clauses, "alpha": C3["alpha"], "seed": C3["seed"],
                    "max_rank": plan.stats["max_rank"], "moduli": len(mods), "order": plan.stats["chosen"],

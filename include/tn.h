@@ -205,9 +205,10 @@ tn_status tn_order(const tn_network* net, tn_order_kind kind, uint64_t seed,
  * evaluation, spending search where the predicted contraction is costly):
  * with search_us > 0, TN_ORDER_BEST (and TN_ORDER_LEARNED when it hands its
  * plan to the judge) keeps trying randomized bisections, in rounds of one
- * per host thread, until search_us microseconds of host time are spent (at
- * most 48 rounds), instead of stopping at twice the best plan's predicted
- * device time or 16 rounds. search_us = 0 is tn_order; negative or NaN
+ * per host thread, until 0.75 search_us microseconds of host time are spent
+ * (at most 48 rounds), instead of stopping at twice the best plan's
+ * predicted device time or 16 rounds; the local reconfiguration of the best
+ * plans then takes at most the remaining quarter (and 0.1 s). search_us = 0 is tn_order; negative or NaN
  * budgets give TN_EINVAL. Useful when the search overlaps earlier device
  * work, as in a stream of counts. */
 tn_status tn_order_budget(const tn_network* net, tn_order_kind kind, uint64_t seed,

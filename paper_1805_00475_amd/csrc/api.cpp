@@ -16,6 +16,9 @@ namespace tn {
 // default rule, and with an explicit host-time budget
 constexpr int kPartitionTrials = 16;
 constexpr int kMaxBudgetRounds = 48;
+// with an explicit budget: its share for the trial rounds; the rest bounds
+// the reconfiguration of the best plans
+constexpr double kBudgetTrials = 0.75;
 // host microseconds of order search allowed per predicted device microsecond
 constexpr double kSearchRatio = 2.0;
 // predicted device microseconds above which the learned order's judged plan
@@ -131,7 +134,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         auto over_budget = [&]() {
             const double spent_us =
                 std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
-            if (search_us > 0) return have && spent_us > search_us;
+            if (search_us > 0) return have && spent_us > kBudgetTrials * search_us;
             return have && spent_us > kSearchRatio * plan_cost(out);
         };
         const int rounds = search_us > 0 ? kMaxBudgetRounds : kPartitionTrials;
@@ -208,7 +211,8 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         // of the runners-up kept (one per host thread, in parallel, each
         // with the same time budget); the cheapest result wins
         if (have && out.merges.size() > 2) {
-            const double budget = std::min(kRefineCapUs, kRefineRatio * plan_cost(out));
+            const double budget = search_us > 0 ? std::min(kRefineCapUs, (1.0 - kBudgetTrials) * search_us)
+                                                : std::min(kRefineCapUs, kRefineRatio * plan_cost(out));
             std::vector<const Plan*> cand{&out};
             for (const Plan& p : pool) cand.push_back(&p);
             std::vector<Plan> ref(cand.size());

@@ -45,16 +45,17 @@ struct Table {
 };
 
 // multiply `src` (over its vars) into `dst`, a table over `scope` (a
-// superset), bit j of an index of dst being scope[j]
+// superset of at most 24 variables), bit j of an index of dst being
+// scope[j]; the index into src is a bit selection, looked up per byte
 void accumulate(const Table& src, const std::vector<int32_t>& scope, std::vector<double>& dst) {
-    std::vector<int> at(src.vars.size());
-    for (size_t i = 0; i < src.vars.size(); ++i)
-        at[i] = int(std::find(scope.begin(), scope.end(), src.vars[i]) - scope.begin());
-    for (size_t a = 0; a < dst.size(); ++a) {
-        size_t idx = 0;
-        for (size_t i = 0; i < at.size(); ++i) idx |= ((a >> at[i]) & 1) << i;
-        dst[a] *= src.t[idx];
+    uint32_t look[3][256] = {};
+    for (size_t i = 0; i < src.vars.size(); ++i) {
+        const int at = int(std::find(scope.begin(), scope.end(), src.vars[i]) - scope.begin());
+        for (uint32_t b = 0; b < 256; ++b)
+            if ((b >> (at % 8)) & 1) look[at / 8][b] |= uint32_t(1) << i;
     }
+    for (size_t a = 0; a < dst.size(); ++a)
+        dst[a] *= src.t[look[0][a & 255] | look[1][(a >> 8) & 255] | look[2][(a >> 16) & 255]];
 }
 
 }  // namespace
