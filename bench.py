@@ -78,9 +78,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--search-ms", type=float, default=None,
-                    help="host-time budget of the judge in the timed steps (default: 0.7 of a count's device "
-                         "time when pipelined, the default search when serial)")
+    ap.add_argument("--search-rounds", type=int, default=0,
+                    help="rounds of bisection trials of the judge (tn_order_rounds; default 0: its own rule, "
+                         "16 rounds on this instance)")
     ap.add_argument("--serial", action="store_true",
                     help="headline steps one after the other (default: the host part of the next step overlaps "
                          "the contraction of the current one)")
@@ -158,20 +158,17 @@ def headline(tn, I, ws, args):
     releases the interpreter lock) runs while step k contracts on the GPU
     from the main thread, as a stream of counts would run. ``--serial``
     times the steps one after the other. The warm-up steps run serially (the
-    judge's default search) and give the latency of one count and its host
-    share; pipelined, the judge then searches for up to 0.7 of one count's
-    device time (tn_order_budget), time that the contraction of the previous
-    count hides."""
+    judge's search) and give the latency of one count and its host share.
+    The plan depends only on the seed and the host's thread count, so every
+    step contracts the same plan."""
     import torch
     from concurrent.futures import ThreadPoolExecutor
     f = c3_formula(I)
 
-    budget = {"ms": 0.0}
-
     def host_part():
         t = time.perf_counter()
         net = tn.Network(f)
-        plan = net.order("best", seed=C3["seed"], search_ms=budget["ms"])
+        plan = net.order("best", seed=C3["seed"], rounds=args.search_rounds)
         return net, plan, time.perf_counter() - t
 
     ref = None
@@ -185,15 +182,6 @@ def headline(tn, I, ws, args):
         lat.append(time.perf_counter() - t)
         host.append(h)
         log(f"warmup {w + 1}/{args.warmup} done")
-    # pipelined, the judge's search overlaps the previous count's contraction:
-    # give it host time up to 0.7 of the device time of one count (measured
-    # in the warm-up steps; trial rounds and refinement), leaving room for
-    # the build
-    if args.search_ms is not None:
-        budget["ms"] = args.search_ms
-    elif not args.serial and lat:
-        dev = sum(x - y for x, y in zip(lat[1:] or lat, host[1:] or host)) / len(lat[1:] or lat)
-        budget["ms"] = round(700.0 * dev, 1)
     acc = Acc(tn)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -223,7 +211,7 @@ def headline(tn, I, ws, args):
     htail = host[1:] or host
     serial = {"latency_ms_per_count": round(1000 * sum(tail) / len(tail), 1),
               "host_ms_per_count": round(1000 * sum(htail) / len(htail), 1),
-              "samples": len(tail), "search_ms_pipelined": budget["ms"]} if lat else None
+              "samples": len(tail)} if lat else None
     return f, plan, got[0], t1 - t0, acc, serial
 
 
@@ -496,8 +484,7 @@ def main():
                                 f"{plan.stats['max_rank']}), {len(mods)} small moduli (centred int8 residues) + "
                                 f"CRT; one formula per step, whole path (build, order, contract, CRT)"
                                 + ("" if args.serial else "; steps pipelined: the next step's build and order "
-                                   "(judge searching for up to 0.7 of a count's device time) run on the host "
-                                   "while the current step contracts on the GPU")),
+                                   "run on the host while the current step contracts on the GPU")),
                    "n": C3["n"], "m": f.n_clauses, "alpha": C3["alpha"], "seed": C3["seed"],
                    "max_rank": plan.stats["max_rank"], "moduli": len(mods), "order": plan.stats["chosen"],
                    "count_bits": count.bit_length(), "pipelined": not args.serial},

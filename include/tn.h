@@ -201,18 +201,15 @@ tn_status tn_network_info(const tn_network* net, int32_t* n_tensors, int32_t* n_
  * order falls back to the judge's choice). */
 tn_status tn_order(const tn_network* net, tn_order_kind kind, uint64_t seed,
                    const tn_model* model, tn_plan** out, tn_plan_stats* stats);
-/* tn_order with an explicit host-time budget for the judge (Sec. 4: lazy
- * evaluation, spending search where the predicted contraction is costly):
- * with search_us > 0, TN_ORDER_BEST (and TN_ORDER_LEARNED when it hands its
- * plan to the judge) keeps trying randomized bisections, in rounds of one
- * per host thread, until 0.75 search_us microseconds of host time are spent
- * (at most 48 rounds), instead of stopping at twice the best plan's
- * predicted device time or 16 rounds; the local reconfiguration of the best
- * plans then takes at most the remaining quarter (and 0.1 s). search_us = 0 is tn_order; negative or NaN
- * budgets give TN_EINVAL. Useful when the search overlaps earlier device
- * work, as in a stream of counts. */
-tn_status tn_order_budget(const tn_network* net, tn_order_kind kind, uint64_t seed,
-                          const tn_model* model, double search_us, tn_plan** out,
+/* tn_order with a fixed search (Sec. 4: lazy evaluation, spending search where
+ * the predicted contraction is costly): with rounds > 0, TN_ORDER_BEST (and
+ * TN_ORDER_LEARNED when it hands its plan to the judge) runs exactly that
+ * many rounds of randomized bisections, one per host thread, instead of
+ * stopping at twice the best plan's predicted device time or 16 rounds; the
+ * plan then depends only on the seed and the number of host threads.
+ * rounds = 0 is tn_order; rounds outside [0, 256] give TN_EINVAL. */
+tn_status tn_order_rounds(const tn_network* net, tn_order_kind kind, uint64_t seed,
+                          const tn_model* model, int32_t rounds, tn_plan** out,
                           tn_plan_stats* stats);
 void tn_plan_free(tn_plan* plan);
 /* Copy the merges of a plan: pairs[2k], pairs[2k+1] are the tensor ids of

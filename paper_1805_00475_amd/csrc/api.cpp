@@ -15,10 +15,8 @@ namespace tn {
 // randomized bisection trials the judge may try per search thread: by the
 // default rule, and with an explicit host-time budget
 constexpr int kPartitionTrials = 16;
-constexpr int kMaxBudgetRounds = 48;
-// with an explicit budget: its share for the trial rounds; the rest bounds
-// the reconfiguration of the best plans
-constexpr double kBudgetTrials = 0.75;
+// most rounds a caller may ask for (tn_order_rounds)
+constexpr int kMaxRounds = 256;
 // host microseconds of order search allowed per predicted device microsecond
 constexpr double kSearchRatio = 2.0;
 // predicted device microseconds above which the learned order's judged plan
@@ -46,7 +44,7 @@ int search_threads() {
 }
 
 tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out, int threads,
-                     double search_us) {
+                     int rounds_asked) {
     try {
         auto plan_of = [&](int32_t k, Plan& p) -> tn_status {
             switch (k) {
@@ -134,10 +132,10 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         auto over_budget = [&]() {
             const double spent_us =
                 std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
-            if (search_us > 0) return have && spent_us > kBudgetTrials * search_us;
+            if (rounds_asked > 0) return false;  // a fixed number of rounds
             return have && spent_us > kSearchRatio * plan_cost(out);
         };
-        const int rounds = search_us > 0 ? kMaxBudgetRounds : kPartitionTrials;
+        const int rounds = rounds_asked > 0 ? std::min(rounds_asked, kMaxRounds) : kPartitionTrials;
         auto partition_trial = [&](int t) {
             Plan p;
             tn_status s2 = make_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t)),
@@ -211,8 +209,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         // of the runners-up kept (one per host thread, in parallel, each
         // with the same time budget); the cheapest result wins
         if (have && out.merges.size() > 2) {
-            const double budget = search_us > 0 ? std::min(kRefineCapUs, (1.0 - kBudgetTrials) * search_us)
-                                                : std::min(kRefineCapUs, kRefineRatio * plan_cost(out));
+            const double budget = std::min(kRefineCapUs, kRefineRatio * plan_cost(out));
             std::vector<const Plan*> cand{&out};
             for (const Plan& p : pool) cand.push_back(&p);
             std::vector<Plan> ref(cand.size());
@@ -316,16 +313,16 @@ tn_status tn_network_info(const tn_network* net, int32_t* n_tensors, int32_t* n_
 
 tn_status tn_order(const tn_network* net, tn_order_kind kind, uint64_t seed, const tn_model* model,
                    tn_plan** out, tn_plan_stats* stats) {
-    return tn_order_budget(net, kind, seed, model, 0.0, out, stats);
+    return tn_order_rounds(net, kind, seed, model, 0, out, stats);
 }
 
-tn_status tn_order_budget(const tn_network* net, tn_order_kind kind, uint64_t seed, const tn_model* model,
-                          double search_us, tn_plan** out, tn_plan_stats* stats) {
-    if (!net || !out || !(search_us >= 0.0)) return TN_EINVAL;
+tn_status tn_order_rounds(const tn_network* net, tn_order_kind kind, uint64_t seed, const tn_model* model,
+                          int32_t rounds, tn_plan** out, tn_plan_stats* stats) {
+    if (!net || !out || rounds < 0 || rounds > kMaxRounds) return TN_EINVAL;
     *out = nullptr;
     tn_plan* h = new (std::nothrow) tn_plan;
     if (!h) return TN_ENOMEM;
-    tn_status st = make_order(net->net, kind, seed, model, h->plan, search_threads(), search_us);
+    tn_status st = make_order(net->net, kind, seed, model, h->plan, search_threads(), rounds);
     if (st != TN_OK) {
         delete h;
         return st;

@@ -123,10 +123,10 @@ int32_t count_bound_bits(const tn_formula* f);
 // api.cpp: order of any kind (with the judge for BEST / LEARNED) + plan
 // threads: host threads for the judge's randomized bisection trials (one
 // order search; the batch path runs one search per thread with threads = 1);
-// search_us > 0: the judge's trials continue until that much host time is
-// spent (at most kMaxBudgetRounds rounds) instead of the default rule
+// rounds > 0: the judge runs exactly that many rounds of trials (no time
+// rule), so that the plan depends only on the seed and the thread count
 tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_model* model, Plan& out,
-                     int threads = 1, double search_us = 0.0);
+                     int threads = 1, int rounds = 0);
 
 // contract.hip
 struct Resolved {

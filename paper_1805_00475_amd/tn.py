@@ -85,7 +85,7 @@ _SIGS = {
     "tn_network_info": ([ctypes.c_void_p, _P(ctypes.c_int32), _P(ctypes.c_int32)], ctypes.c_int),
     "tn_order": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, _P(ctypes.c_void_p),
                   _P(PlanStats_c)], ctypes.c_int),
-    "tn_order_budget": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_double,
+    "tn_order_rounds": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int32,
                          _P(ctypes.c_void_p), _P(PlanStats_c)], ctypes.c_int),
     "tn_plan_free": ([ctypes.c_void_p], None),
     "tn_plan_verify": ([ctypes.c_void_p], ctypes.c_int),
@@ -233,10 +233,10 @@ class Network:
         _check(load().tn_network_info(self.h, ctypes.byref(nt), ctypes.byref(nb)), "tn_network_info")
         return nt.value, nb.value
 
-    def order(self, kind: str = "greedy", seed: int = 0, model=None, search_ms: float = 0.0) -> "Plan":
-        """tn_order; with search_ms > 0, tn_order_budget (the judge searches
-        for that much host time)."""
-        return Plan(self, kind, seed, model, search_ms)
+    def order(self, kind: str = "greedy", seed: int = 0, model=None, rounds: int = 0) -> "Plan":
+        """tn_order; with rounds > 0, tn_order_rounds (the judge runs that
+        many rounds of trials)."""
+        return Plan(self, kind, seed, model, rounds)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -247,15 +247,15 @@ class Network:
 class Plan:
     """Handle of an order + plan (tn_order)."""
 
-    def __init__(self, net: Network, kind: str, seed: int, model=None, search_ms: float = 0.0):
+    def __init__(self, net: Network, kind: str, seed: int, model=None, rounds: int = 0):
         lib = load()
         self.net = net
         h = ctypes.c_void_p()
         st = PlanStats_c()
         mh = model.h if model is not None else None
-        if search_ms:
-            _check(lib.tn_order_budget(net.h, ORDERS[kind], seed, mh, 1000.0 * search_ms, ctypes.byref(h),
-                                       ctypes.byref(st)), "tn_order_budget")
+        if rounds:
+            _check(lib.tn_order_rounds(net.h, ORDERS[kind], seed, mh, rounds, ctypes.byref(h), ctypes.byref(st)),
+                   "tn_order_rounds")
         else:
             _check(lib.tn_order(net.h, ORDERS[kind], seed, mh, ctypes.byref(h), ctypes.byref(st)), "tn_order")
         self.h = h

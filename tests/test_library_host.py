@@ -288,17 +288,20 @@ def test_csp_build_validation_and_bounds():
     assert k.info() == (5, 0)
 
 
-def test_order_budget():
-    # the judge with an explicit host-time budget: a valid plan, at least as
-    # cheap as greedy's; negative budgets are rejected
+def test_order_rounds():
+    # the judge with a fixed number of trial rounds: a valid plan, at least
+    # as cheap as greedy's, the same plan on a second call; out-of-range
+    # round counts are rejected
     import ctypes
     f = I.cvc(60, 2)
     net = tn.Network(f)
     g = net.order("greedy")
-    b = net.order("best", seed=3, search_ms=20.0)
+    b = net.order("best", seed=3, rounds=4)
     assert b.verify() and b.stats["log2_cost"] <= g.stats["log2_cost"] + 1e-9
+    assert net.order("best", seed=3, rounds=4).steps() == b.steps()
     lib = tn.load()
     h = ctypes.c_void_p()
     st = tn.PlanStats_c()
-    assert lib.tn_order_budget(net.h, tn.ORDERS["best"], 0, None, -1.0, ctypes.byref(h), ctypes.byref(st)) == \
-        -1  # TN_EINVAL
+    for bad in (-1, 257):
+        assert lib.tn_order_rounds(net.h, tn.ORDERS["best"], 0, None, bad, ctypes.byref(h), ctypes.byref(st)) == \
+            -1  # TN_EINVAL
