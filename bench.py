@@ -21,8 +21,9 @@ Prints one JSON line. ``roofline`` is the dominant kernel class (the int8
 matrix-core kernels), from hipEvents around every launch of the timed steps;
 ``hbm_roofline`` covers the memory-bound launches (arithmetic intensity
 below the machine balance) whose working set is at least 1 GiB. Extra keys
-measure the other workloads (vertex cover n = 200, the n = 20 1-in-3 set,
-the mixed 4096-instance batch, learned vs greedy orders) and the CPU oracle.
+measure the other workloads (vertex cover n = 60, 120, 200, the paper's own
+1-in-3 family at 300 variables, the n = 20 1-in-3 set, the mixed
+4096-instance batch, learned vs greedy orders) and the CPU oracle.
 """
 from __future__ import annotations
 
@@ -236,6 +237,29 @@ def cvc_rates(tn, I, ws):
                         "ms_per_pass": round(1000 * dt, 2)}
     log("cvc done")
     return out
+
+
+def paper_family(tn, I, ws):
+    """The paper's own 1-in-3 family (Sec. 3.2, Eq. 6 on random cubic graphs:
+    a variable per edge, an exactly-one clause per vertex) at its largest
+    size, 200 vertices = 300 variables, 16 instances counted as one batch
+    with the judged order, whole path per pass; the paper reports a median
+    of the order of 10^2 s per instance there (Fig. 3, one CPU core)."""
+    import torch
+    fs = [I.cubic_1in3(200, i) for i in range(16)]
+    first = tn.count_batch(fs, "best", seed=0, workspace=ws)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        if tn.count_batch(fs, "best", seed=0, workspace=ws) != first:
+            raise SystemExit("paper-family counts changed between passes")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    log("paper family done")
+    return {"workload": "1-in-3 on random cubic graphs (the paper's family), 200 vertices = 300 variables, "
+                        "instances 0..15, judged order, one batch per pass",
+            "counts_per_s": round(len(fs) / dt, 2), "ms_per_instance": round(1000 * dt / len(fs), 2)}
 
 
 def c1_rates(tn, I, ws):
@@ -498,6 +522,7 @@ def main():
     if not args.no_extras:
         t = time.time()
         out["cvc"] = cvc_rates(tn, I, ws)
+        out["paper_family"] = paper_family(tn, I, ws)
         out["c1"] = c1_rates(tn, I, ws)
         log(f"  ({time.time() - t:.1f}s)")
         if args.c4_batch:
