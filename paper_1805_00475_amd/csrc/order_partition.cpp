@@ -7,13 +7,15 @@
 // merge.
 //
 // The bisection is this library's own multilevel scheme in the spirit of
-// METIS: heavy-edge matching to coarsen, greedy graph growing from a random
-// vertex for the initial cut, Fiduccia-Mattheyses refinement while
+// METIS: heavy-edge matching to coarsen, for the initial cut every split of
+// the coarsest graph when it has at most 12 vertices, else greedy graph
+// growing from random vertices, Fiduccia-Mattheyses refinement while
 // uncoarsening. Before partitioning, tensors of rank <= 2 are absorbed into
 // a neighbour (this never raises a rank); vertex weight 1 per remaining
 // tensor, edge weight = number of bonds shared.
 #include <algorithm>
 #include <numeric>
+#include <queue>
 
 #include "graph.hpp"
 #include "internal.hpp"
@@ -136,6 +138,8 @@ void fm_refine(const WGraph& g, std::vector<uint8_t>& side, int max_passes) {
     const int64_t W = g.total_vw();
     std::vector<int64_t> gain(g.n);
     std::vector<uint8_t> locked(g.n);
+    bool unit = true;
+    for (int32_t v = 0; v < g.n; ++v) unit = unit && g.vw[v] == 1;
     for (int pass = 0; pass < max_passes; ++pass) {
         for (int32_t v = 0; v < g.n; ++v) {
             int64_t gv = 0;
@@ -148,16 +152,36 @@ void fm_refine(const WGraph& g, std::vector<uint8_t>& side, int max_passes) {
         size_t best_k = 0;
         int64_t best_dev = std::llabs(2 * w0 - W);
         int64_t cw0 = w0;
+        // with unit vertex weights every vertex of a side is allowed or not
+        // alike, so the best candidate is the top of one of two heaps
+        // (largest gain, then lowest index; stale entries skipped)
+        std::priority_queue<std::pair<int64_t, int32_t>> heap[2];
+        if (unit)
+            for (int32_t v = 0; v < g.n; ++v) heap[side[v]].push({gain[v], -v});
+        auto allowed = [&](int64_t wv, int from) {
+            const int64_t nw0 = from == 0 ? cw0 - wv : cw0 + wv;
+            // a move out of an unbalanced state toward balance is allowed
+            return (nw0 >= bal.lo && nw0 <= bal.hi) || std::llabs(2 * nw0 - W) < std::llabs(2 * cw0 - W);
+        };
         for (int32_t it = 0; it < g.n; ++it) {
             int32_t pick = -1;
-            for (int32_t v = 0; v < g.n; ++v) {
-                if (locked[v]) continue;
-                int64_t nw0 = side[v] == 0 ? cw0 - g.vw[v] : cw0 + g.vw[v];
-                bool ok = nw0 >= bal.lo && nw0 <= bal.hi;
-                // a move out of an unbalanced state toward balance is allowed
-                if (!ok && std::llabs(2 * nw0 - W) < std::llabs(2 * cw0 - W)) ok = true;
-                if (!ok) continue;
-                if (pick < 0 || gain[v] > gain[pick]) pick = v;
+            if (unit) {
+                for (int sd = 0; sd < 2; ++sd) {
+                    auto& h = heap[sd];
+                    while (!h.empty()) {
+                        const int32_t v = -h.top().second;
+                        if (locked[v] || side[v] != sd || h.top().first != gain[v]) h.pop();
+                        else break;
+                    }
+                    if (h.empty() || !allowed(1, sd)) continue;
+                    const int32_t v = -h.top().second;
+                    if (pick < 0 || gain[v] > gain[pick] || (gain[v] == gain[pick] && v < pick)) pick = v;
+                }
+            } else {
+                for (int32_t v = 0; v < g.n; ++v) {
+                    if (locked[v] || !allowed(g.vw[v], side[v])) continue;
+                    if (pick < 0 || gain[v] > gain[pick]) pick = v;
+                }
             }
             if (pick < 0) break;
             cur -= gain[pick];
@@ -170,6 +194,7 @@ void fm_refine(const WGraph& g, std::vector<uint8_t>& side, int max_passes) {
                 int32_t u = g.adj[e];
                 // edge (pick,u) changed from cut to uncut or back
                 gain[u] += side[u] == side[pick] ? -2 * g.ew[e] : 2 * g.ew[e];
+                if (unit && !locked[u]) heap[side[u]].push({gain[u], -u});
             }
             int64_t dev = std::llabs(2 * cw0 - W);
             bool inb = cw0 >= bal.lo && cw0 <= bal.hi;
@@ -197,34 +222,70 @@ std::vector<uint8_t> grow(const WGraph& g, SplitMix& rng) {
     std::vector<uint8_t> side(g.n, 1);
     const int64_t W = g.total_vw();
     int32_t seed = int32_t(rng.below(uint32_t(g.n)));
-    side[seed] = 0;
+    // gain of moving each side-1 vertex to side 0 (edges to side 0 minus
+    // edges to side 1) and whether it touches side 0, kept up to date as
+    // vertices move
+    std::vector<int64_t> gv(g.n, 0);
+    std::vector<uint8_t> boundary(g.n, 0);
+    for (int32_t v = 0; v < g.n; ++v)
+        for (int32_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e) gv[v] -= g.ew[e];
+    auto move = [&](int32_t p) {
+        side[p] = 0;
+        for (int32_t e = g.xadj[p]; e < g.xadj[p + 1]; ++e) {
+            gv[g.adj[e]] += 2 * g.ew[e];
+            boundary[g.adj[e]] = 1;
+        }
+    };
+    move(seed);
     int64_t w0 = g.vw[seed];
     while (2 * w0 < W) {
         int32_t pick = -1;
         int64_t pg = 0;
         for (int32_t v = 0; v < g.n; ++v) {
             if (side[v] == 0) continue;
-            int64_t gv = 0;
-            bool boundary = false;
-            for (int32_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e) {
-                if (side[g.adj[e]] == 0) {
-                    gv += g.ew[e];
-                    boundary = true;
-                } else {
-                    gv -= g.ew[e];
-                }
-            }
-            if (!boundary) gv -= 1 << 20;  // prefer staying connected
-            if (pick < 0 || gv > pg) {
+            const int64_t key = boundary[v] ? gv[v] : gv[v] - (1 << 20);  // prefer staying connected
+            if (pick < 0 || key > pg) {
                 pick = v;
-                pg = gv;
+                pg = key;
             }
         }
         if (pick < 0) break;
-        side[pick] = 0;
+        move(pick);
         w0 += g.vw[pick];
     }
     return side;
+}
+
+// graphs up to this many vertices are bisected by trying every split
+constexpr int32_t kExactBisect = 12;
+
+// Exhaustive balanced bisection of a small graph: vertex 0 stays on side 0
+// (the sides are interchangeable and the balance window is symmetric) and
+// the other vertices run through every split in Gray-code order, one vertex
+// changing side per step so that the cut and the weight update in O(degree).
+// The lightest cut within the window wins, then the split closer to even,
+// then the earlier one. Empty when no split is within the window.
+std::vector<uint8_t> exact_bisect(const WGraph& g) {
+    const Balance bal = balance_of(g);
+    const int64_t W = g.total_vw();
+    std::vector<uint8_t> side(g.n, 0), best;
+    int64_t w0 = W, c = 0, bestc = -1, bestdev = 0;
+    for (uint32_t i = 0; i < (uint32_t(1) << (g.n - 1)); ++i) {
+        if (i > 0) {
+            const int32_t v = 1 + __builtin_ctz(i);
+            for (int32_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e) c += side[g.adj[e]] == side[v] ? g.ew[e] : -g.ew[e];
+            w0 += side[v] == 0 ? -g.vw[v] : g.vw[v];
+            side[v] ^= 1;
+        }
+        if (w0 < bal.lo || w0 > bal.hi) continue;
+        const int64_t dev = std::llabs(2 * w0 - W);
+        if (bestc < 0 || c < bestc || (c == bestc && dev < bestdev)) {
+            bestc = c;
+            bestdev = dev;
+            best = side;
+        }
+    }
+    return best;
 }
 
 // One level of heavy-edge matching; cmap maps fine -> coarse vertex.
@@ -308,7 +369,9 @@ std::vector<uint8_t> bisect(const WGraph& g, SplitMix& rng, int64_t* cut) {
     const WGraph& top = levels.back();
     std::vector<uint8_t> best;
     int64_t bestcut = -1;
-    for (int t = 0; t < 6; ++t) {
+    if (top.n <= kExactBisect) best = exact_bisect(top);
+    const int grow_trials = best.empty() ? 6 : 0;
+    for (int t = 0; t < grow_trials; ++t) {
         std::vector<uint8_t> side = grow(top, rng);
         fm_refine(top, side, 8);
         int64_t c = cut_of(top, side);
