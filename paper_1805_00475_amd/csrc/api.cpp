@@ -12,9 +12,12 @@
 
 namespace tn {
 
-// randomized bisection trials the judge may try per search thread: by the
-// default rule, and with an explicit host-time budget
+// randomized bisection trials of the judge's default rule on one host
+// thread, and rounds of one trial per thread on several (on the 1-in-3
+// configurations of n = 250-300 more rounds than 8 find no better plans
+// once the runners-up are reconfigured too; fewer than 8 find worse ones)
 constexpr int kPartitionTrials = 16;
+constexpr int kParallelRounds = 8;
 // most rounds a caller may ask for (tn_order_rounds)
 constexpr int kMaxRounds = 256;
 // host microseconds of order search allowed per predicted device microsecond
@@ -24,13 +27,20 @@ constexpr double kSearchRatio = 2.0;
 // bisection trials on 1-in-3 instances of n <= 250 costs at most about
 // 10 ms of host time, so plans predicted above 50 ms are worth a search
 constexpr double kEscalateUs = 50000.0;
-// most host time spent reconfiguring one plan, and its share of the
-// predicted device time (measured on n = 200 cubic vertex-cover batches:
-// 0.5 gives 45.1 counts/s against 44.2 at 2, 43.4 at 0.25 and 39.0 without
-// reconfiguration; on the largest 1-in-3 configuration caps of 0.1 s and
-// 0.4 s give the same plans)
+// most host time spent reconfiguring plans, and its share of the predicted
+// device time (measured on n = 200 cubic vertex-cover batches: 0.5 gives
+// 45.1 counts/s against 44.2 at 2, 43.4 at 0.25 and 39.0 without
+// reconfiguration). The time goes to kRefineWaves waves of one plan per
+// host thread, each plan with its share of it: reconfiguration settles
+// within 15-22 ms on the 1-in-3 configurations of n = 300, and where it
+// settles depends on the starting plan more than on the time, so two plans
+// per thread beat one (predicted device time over six seeds 28 % lower at
+// n = 300, alpha = 0.62, seed 1 and at n = 250, 7 % at n = 300, seed 4;
+// vertex cover n = 200 10 % lower); four or eight plans per thread leave
+// too little time each on the vertex-cover instances
 constexpr double kRefineCapUs = 100000.0;
 constexpr double kRefineRatio = 0.5;
+constexpr int kRefineWaves = 2;
 
 // Host threads for one order search: TN_ORDER_THREADS if set, else the
 // cores available (at most 16).
@@ -92,11 +102,11 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 return TN_OK;
             }
         }
-        // candidates: greedy, community, and kPartitionTrials randomized
-        // recursive bisections (each itself best-of-2 per level); the
-        // cheapest `keep` of them (distinct costs) stay for reconfiguration,
+        // candidates: greedy, community, and randomized recursive
+        // bisections (each itself best-of-2 per level); the cheapest `keep`
+        // of them (distinct costs) stay for reconfiguration,
         // out being the cheapest
-        const size_t keep = size_t(std::max(1, threads));
+        const size_t keep = size_t(std::max(1, threads)) * size_t(kRefineWaves);
         std::vector<Plan> pool;
         auto consider = [&](tn_status s2, Plan& p) {
             if (s2 != TN_OK) {
@@ -135,7 +145,9 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             if (rounds_asked > 0) return false;  // a fixed number of rounds
             return have && spent_us > kSearchRatio * plan_cost(out);
         };
-        const int rounds = rounds_asked > 0 ? std::min(rounds_asked, kMaxRounds) : kPartitionTrials;
+        const int rounds = rounds_asked > 0        ? std::min(rounds_asked, kMaxRounds)
+                           : threads <= 1 ? kPartitionTrials
+                                          : kParallelRounds;
         auto partition_trial = [&](int t) {
             Plan p;
             tn_status s2 = make_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t)),
@@ -206,10 +218,11 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             consider(gns, gnp);
         }
         // local reconfiguration of the contraction trees of the winner and
-        // of the runners-up kept (one per host thread, in parallel, each
-        // with the same time budget); the cheapest result wins
+        // of the runners-up kept (kRefineWaves per host thread, in
+        // parallel, each with the same share of the time budget); the
+        // cheapest result wins
         if (have && out.merges.size() > 2) {
-            const double budget = std::min(kRefineCapUs, kRefineRatio * plan_cost(out));
+            const double budget = std::min(kRefineCapUs, kRefineRatio * plan_cost(out)) / kRefineWaves;
             std::vector<const Plan*> cand{&out};
             for (const Plan& p : pool) cand.push_back(&p);
             std::vector<Plan> ref(cand.size());

@@ -64,6 +64,7 @@ struct Plan {
     int64_t arena_elems = 0;                   // arena size for one prime (elements), plan order
     int64_t warena_elems = 0;                  // arena size when steps run in waves by level
     int32_t root = -1;                         // id of the final scalar
+    double cost_us = -1;                       // plan_cost, kept by make_plan (-1: not yet)
     tn_plan_stats stats{};
 };
 

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -43,8 +44,28 @@ constexpr int kMaxFrontier = 8;
 thread_local int g_rank_cap = 64;
 thread_local int g_mode = RM_SMALL;
 
+// step_cost_model by table for operands of rank below kTabRank (the DP
+// evaluates it thousands of times per subtree), built once per mode
+constexpr int kTabRank = 48;
+const double* cost_table(int mode) {
+    static std::once_flag once[3];
+    static std::vector<double> tab[3];
+    std::call_once(once[mode], [mode]() {
+        std::vector<double>& t = tab[mode];
+        t.assign(size_t(kTabRank) * kTabRank * kTabRank, 0.0);
+        for (int ra = 0; ra < kTabRank; ++ra)
+            for (int rb = 0; rb < kTabRank; ++rb)
+                for (int s = 0; s <= std::min(ra, rb); ++s)
+                    t[(size_t(ra) * kTabRank + rb) * kTabRank + s] = step_cost_model(ra, rb, s, ra + rb - 2 * s, mode);
+    });
+    return tab[mode].data();
+}
+thread_local const double* g_tab = nullptr;
+
 double merge_cost(int ra, int rb, int rc) {
-    const double c = step_cost_model(ra, rb, (ra + rb - rc) / 2, rc, g_mode);
+    const int s = (ra + rb - rc) / 2;
+    const double c = ra < kTabRank && rb < kTabRank ? g_tab[(size_t(ra) * kTabRank + rb) * kTabRank + s]
+                                                    : step_cost_model(ra, rb, s, rc, g_mode);
     return rc > g_rank_cap ? c + 1e15 : c;
 }
 
@@ -188,6 +209,7 @@ std::vector<std::pair<int32_t, int32_t>> refine_order(const Network& net,
     for (int32_t v = 0; v < n; ++v) maxr = std::max(maxr, t.rank(v));
     g_rank_cap = maxr;  // keep peak memory: never raise the largest rank
     g_mode = default_residue_mode(net.count_bits);
+    g_tab = cost_table(g_mode);
     std::vector<char> is_frontier(n, 0);
     for (int sweep = 0; sweep < 4; ++sweep) {
         bool any = false;

@@ -138,6 +138,7 @@ double step_cost_model(int rA, int rB, int s, int rC, int mode) {
 }
 
 double plan_cost(const Plan& plan) {
+    if (plan.cost_us >= 0) return plan.cost_us;
     constexpr int kPlanesPerLaunch = 16;  // residue planes of one launch
     constexpr double kLaunchUs = 5.0;
     const int mode = default_residue_mode(plan.count_bits);
@@ -302,7 +303,8 @@ tn_status make_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>>
         plan.stats.entries = entries;
         plan.stats.macs = macs;
         plan.stats.peak_elems = uint64_t(plan.arena_elems + plan.init_elems);
-        double c = plan_cost(plan);
+        const double c = plan_cost(plan);
+        plan.cost_us = c;
         plan.stats.log2_cost = c > 0 ? std::log2(c) : 0.0;
         plan.stats.chosen = chosen;
         plan.stats.fallback = 0;
