@@ -9,8 +9,9 @@
 // subsets of the frontier (k <= 8), without changing the rest of the plan or
 // the count. The cost of a merge is the plan's cost model; the frontier is
 // grown from the subtree's root by opening the highest-rank internal node
-// first. Sweeps over all internal nodes repeat while they improve the
-// plan, within a time budget.
+// first. The first sweep visits every internal node, later ones only the
+// nodes whose window a change can have reached, until none is left or the
+// time budget is spent.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -37,6 +38,7 @@ struct Tree {
 };
 
 constexpr int kMaxFrontier = 8;
+constexpr int kMaxSweeps = 6;
 
 // set per refinement (per thread: orders are searched on worker threads):
 // no intermediate may exceed the plan's largest rank; steps are priced in
@@ -83,8 +85,9 @@ void collect_internal(Tree& t, int32_t v, const std::vector<char>& is_frontier, 
     collect_internal(t, t.right[v], is_frontier, out);
 }
 
-// Try to improve the subtree rooted at v; returns true when it changed.
-bool reconfigure(Tree& t, int32_t v, std::vector<char>& is_frontier) {
+// Try to improve the subtree rooted at v; returns true when it changed,
+// the ids of the internal nodes it rebuilt (v among them) in `rebuilt`.
+bool reconfigure(Tree& t, int32_t v, std::vector<char>& is_frontier, std::vector<int32_t>& rebuilt) {
     if (t.left[v] < 0) return false;
     // grow the frontier from v's children, opening the highest-rank
     // internal node first
@@ -174,6 +177,7 @@ bool reconfigure(Tree& t, int32_t v, std::vector<char>& is_frontier) {
         } bld{t, fr, split, sb, pool};
         bld.make(full, v);
         changed = true;
+        rebuilt = old_internal;
     }
     for (int32_t x : fr) is_frontier[x] = 0;
     return changed;
@@ -211,22 +215,38 @@ std::vector<std::pair<int32_t, int32_t>> refine_order(const Network& net,
     g_mode = default_residue_mode(net.count_bits);
     g_tab = cost_table(g_mode);
     std::vector<char> is_frontier(n, 0);
-    for (int sweep = 0; sweep < 4; ++sweep) {
-        bool any = false;
-        // largest tensors first: their subtrees dominate the cost
+    // Sweeps over the internal nodes still marked, largest tensors first
+    // (their subtrees dominate the cost). A node is marked at the start and
+    // again when a change can reach its window: the window of a node holds
+    // nodes at most kMaxFrontier - 1 levels below it, and the bonds of a
+    // node depend only on its leaves, so a rebuild at v can only change the
+    // windows of the nodes it rebuilt and of v's ancestors within those
+    // levels. Once nothing is marked, no window can improve.
+    std::vector<char> marked(n, 0);
+    for (int32_t v = n0; v < n; ++v) marked[v] = 1;
+    std::vector<int32_t> rebuilt;
+    bool stop = false;
+    for (int sweep = 0; sweep < kMaxSweeps && !stop; ++sweep) {
         std::vector<int32_t> nodes;
-        for (int32_t v = n0; v < n; ++v) nodes.push_back(v);
+        for (int32_t v = n0; v < n; ++v)
+            if (marked[v]) nodes.push_back(v);
+        if (nodes.empty()) break;
         std::sort(nodes.begin(), nodes.end(), [&](int32_t x, int32_t y) { return t.rank(x) > t.rank(y); });
         for (int32_t v : nodes) {
-            any |= reconfigure(t, v, is_frontier);
+            if (!marked[v]) continue;
+            marked[v] = 0;
+            if (reconfigure(t, v, is_frontier, rebuilt)) {
+                for (int32_t x : rebuilt) marked[x] = 1;
+                int32_t a = t.parent[v];
+                for (int d = 0; d < kMaxFrontier - 1 && a >= 0; ++d, a = t.parent[a]) marked[a] = 1;
+            }
             const double spent =
                 std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
             if (spent > budget_us) {
-                any = false;
+                stop = true;
                 break;
             }
         }
-        if (!any) break;
     }
     // post-order from the root; new merge ids are assigned in that order
     std::vector<std::pair<int32_t, int32_t>> out;
