@@ -53,10 +53,12 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
+def measured_traffic(alg_bytes):
     """Counter-derived HBM bytes per matrix-core launch on the headline
     workload, or None when the kernel source changed since the counters were
-    taken (or no record exists)."""
+    taken, when the launches counted were others than this run's (another
+    plan: algorithmic bytes per launch more than 0.5 % apart), or when no
+    record exists."""
     import hashlib
     try:
         rec = {}
@@ -66,6 +68,9 @@ def measured_traffic():
                 rec[key.strip()] = val.strip()
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
         if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+            return None
+        counted = float(rec["algorithmic_bytes_per_launch (same run, bench.py)"])
+        if abs(counted - alg_bytes) > 0.005 * counted:
             return None
         return float(rec["traffic_bytes_per_launch"])
     except (OSError, ValueError, KeyError):
@@ -115,7 +120,7 @@ def roofline_mfma(d, mode="small"):
             "avg_launch_us": round(1e6 * sec / max(1, d["launches"]), 3), "bound": "mfma",
             "achieved": round(tops, 2), "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
             "frac": round(tops / INT8_PEAK_TOPS, 4),
-            "traffic": measured_traffic() if mode == "small" else None,
+            "traffic": measured_traffic(d["bytes"] / max(1, d["launches"])) if mode == "small" else None,
             "algorithmic_ops_per_launch": d["macs"] * 2 * INT8_PRODUCTS_PER_MODMAC[mode] / max(1, d["launches"]),
             "algorithmic_bytes_per_launch": d["bytes"] / max(1, d["launches"])}
 
