@@ -33,16 +33,18 @@ constexpr double kEscalateUs = 50000.0;
 // device time (measured on n = 200 cubic vertex-cover batches: 0.5 gives
 // 45.1 counts/s against 44.2 at 2, 43.4 at 0.25 and 39.0 without
 // reconfiguration). The time goes to kRefineWaves waves of one plan per
-// host thread, each plan with its share of it: reconfiguration settles
-// within 15-22 ms on the 1-in-3 configurations of n = 300, and where it
-// settles depends on the starting plan more than on the time, so two plans
-// per thread beat one (predicted device time over six seeds 28 % lower at
-// n = 300, alpha = 0.62, seed 1 and at n = 250, 7 % at n = 300, seed 4;
-// vertex cover n = 200 10 % lower); four or eight plans per thread leave
-// too little time each on the vertex-cover instances
+// host thread, each plan with its share of it, when the shares are long
+// enough for reconfiguration to settle: where it settles depends on the
+// starting plan more than on the time, so two plans per thread beat one
+// (predicted device time over six seeds 28 % lower on 1-in-3 at n = 300,
+// alpha = 0.62, seed 1 and at n = 250, 7 % at n = 300, seed 4)
 constexpr double kRefineCapUs = 100000.0;
 constexpr double kRefineRatio = 0.5;
 constexpr int kRefineWaves = 2;
+// host time in which reconfiguration settles: 4-7 ms on plans of vertex
+// cover n = 200, 8-11 ms on 1-in-3 n = 300; with less time per plan than
+// this, one wave
+constexpr double kSettleUs = 12000.0;
 
 // Host threads for one order search: TN_ORDER_THREADS if set, else the
 // cores available (at most 16).
@@ -224,9 +226,13 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         // parallel, each with the same share of the time budget); the
         // cheapest result wins
         if (have && out.merges.size() > 2) {
-            const double budget = std::min(kRefineCapUs, kRefineRatio * plan_cost(out)) / kRefineWaves;
+            // several waves only when each plan still gets the time to settle
+            const double total = std::min(kRefineCapUs, kRefineRatio * plan_cost(out));
+            const int waves = total >= kRefineWaves * kSettleUs ? kRefineWaves : 1;
+            const double budget = total / waves;
             std::vector<const Plan*> cand{&out};
-            for (const Plan& p : pool) cand.push_back(&p);
+            for (const Plan& p : pool)
+                if (cand.size() < size_t(std::max(1, threads)) * size_t(waves)) cand.push_back(&p);
             std::vector<Plan> ref(cand.size());
             std::vector<tn_status> rs(cand.size(), TN_EINVAL);
             std::atomic<size_t> next{0};
