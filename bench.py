@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--search-rounds", type=int, default=0,
                     help="rounds of bisection trials of the judge (tn_order_rounds; default 0: its own rule, "
-                         "8 rounds on this instance)")
+                         "24 rounds on this instance)")
     ap.add_argument("--serial", action="store_true",
                     help="headline steps one after the other (default: the host part of the next step overlaps "
                          "the contraction of the current one)")

@@ -205,9 +205,10 @@ tn_status tn_order(const tn_network* net, tn_order_kind kind, uint64_t seed,
  * the predicted contraction is costly): with rounds > 0, TN_ORDER_BEST (and
  * TN_ORDER_LEARNED when it hands its plan to the judge) runs exactly that
  * many rounds of randomized bisections, one per host thread, instead of
- * stopping at twice the best plan's predicted device time or 8 rounds (16
- * trials on one thread); the
- * plan then depends only on the seed and the number of host threads.
+ * stopping at twice the best plan's predicted device time or 24 rounds (16
+ * trials on one thread), and reconfigures the best quarter of them. The plan
+ * then depends only on the seed and the number of host threads, unless
+ * reconfiguring a plan outlasts its time budget (a share of at most 0.1 s).
  * rounds = 0 is tn_order; rounds outside [0, 256] give TN_EINVAL. */
 tn_status tn_order_rounds(const tn_network* net, tn_order_kind kind, uint64_t seed,
                           const tn_model* model, int32_t rounds, tn_plan** out,

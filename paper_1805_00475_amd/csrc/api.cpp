@@ -13,13 +13,13 @@
 namespace tn {
 
 // randomized bisection trials of the judge's default rule on one host
-// thread, and rounds of one trial per thread on several (1-in-3, n = 300,
-// six seeds, eight threads: 4 rounds give plans predicted 70 % slower than
-// 8; 32 rounds with four reconfigured plans per thread 15 % faster for
-// three times the host time, which callers can ask for with
-// tn_order_rounds)
+// thread, and rounds of one trial per thread on several. On 1-in-3 at
+// n = 300, alpha = 0.62 (six seeds, sixteen threads, the best quarter of the
+// trials reconfigured) 24 rounds give plans predicted 25 % cheaper than 8
+// (157 against 211 ms), 16 rounds 15 %, 32 no more than 24; smaller
+// instances stop earlier, by the time budget below.
 constexpr int kPartitionTrials = 16;
-constexpr int kParallelRounds = 8;
+constexpr int kParallelRounds = 24;
 // most rounds a caller may ask for (tn_order_rounds)
 constexpr int kMaxRounds = 256;
 // host microseconds of order search allowed per predicted device microsecond
@@ -110,7 +110,10 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         // bisections (each itself best-of-2 per level); the cheapest `keep`
         // of them (distinct costs) stay for reconfiguration,
         // out being the cheapest
-        const size_t keep = size_t(std::max(1, threads)) * size_t(kRefineWaves);
+        const int rounds = rounds_asked > 0        ? std::min(rounds_asked, kMaxRounds)
+                           : threads <= 1 ? kPartitionTrials
+                                          : kParallelRounds;
+        const size_t keep = size_t(std::max(1, threads)) * size_t(std::max(kRefineWaves, rounds / 4));
         std::vector<Plan> pool;
         auto consider = [&](tn_status s2, Plan& p) {
             if (s2 != TN_OK) {
@@ -149,50 +152,33 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             if (rounds_asked > 0) return false;  // a fixed number of rounds
             return have && spent_us > kSearchRatio * plan_cost(out);
         };
-        const int rounds = rounds_asked > 0        ? std::min(rounds_asked, kMaxRounds)
-                           : threads <= 1 ? kPartitionTrials
-                                          : kParallelRounds;
         auto partition_trial = [&](int t) {
             Plan p;
             tn_status s2 = make_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t)),
                                      TN_ORDER_PARTITION, p);
             consider(s2, p);
         };
-        // trials t0 .. t0 + n - 1 on `threads` host threads; each thread keeps
-        // its cheapest plan (lowest trial index on ties), then the judge sees
-        // them in thread order
+        // trials t0 .. t0 + n - 1 on `threads` host threads; the judge sees
+        // every plan, in trial order, so that which thread ran which trial
+        // does not matter
         auto parallel_trials = [&](int t0, int n) {
             const int T = std::min(threads, n);
-            std::vector<Plan> best(static_cast<size_t>(T));
-            std::vector<double> bc(size_t(T), 0.0);
-            std::vector<int> bt(size_t(T), -1);
-            std::vector<tn_status> bs(size_t(T), TN_ERANK);
-            std::atomic<int> next{t0};
-            auto work = [&](int w) {
+            std::vector<Plan> plans(static_cast<size_t>(n));
+            std::vector<tn_status> st(static_cast<size_t>(n), TN_ERANK);
+            std::atomic<int> next{0};
+            auto work = [&]() {
                 for (;;) {
-                    const int t = next.fetch_add(1);
-                    if (t >= t0 + n) break;
-                    Plan p;
-                    const tn_status s2 = make_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t)),
-                                                   TN_ORDER_PARTITION, p);
-                    if (s2 != TN_OK) {
-                        bs[size_t(w)] = bt[size_t(w)] < 0 ? s2 : bs[size_t(w)];
-                        continue;
-                    }
-                    const double c = plan_cost(p);
-                    if (bt[size_t(w)] < 0 || c < bc[size_t(w)] || (c == bc[size_t(w)] && t < bt[size_t(w)])) {
-                        best[size_t(w)] = std::move(p);
-                        bc[size_t(w)] = c;
-                        bt[size_t(w)] = t;
-                        bs[size_t(w)] = TN_OK;
-                    }
+                    const int i = next.fetch_add(1);
+                    if (i >= n) break;
+                    st[size_t(i)] = make_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t0 + i)),
+                                              TN_ORDER_PARTITION, plans[size_t(i)]);
                 }
             };
             std::vector<std::thread> pool;
-            for (int w = 1; w < T; ++w) pool.emplace_back(work, w);
-            work(0);
+            for (int w = 1; w < T; ++w) pool.emplace_back(work);
+            work();
             for (auto& th : pool) th.join();
-            for (int w = 0; w < T; ++w) consider(bs[size_t(w)], best[size_t(w)]);
+            for (int i = 0; i < n; ++i) consider(st[size_t(i)], plans[size_t(i)]);
         };
         if (kind != TN_ORDER_LEARNED) {
             Plan p;
@@ -226,10 +212,14 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         // parallel, each with the same share of the time budget); the
         // cheapest result wins
         if (have && out.merges.size() > 2) {
-            // several waves only when each plan still gets the time to settle
+            // several waves only when each plan still gets the time to
+            // settle: the best quarter of the trials (kRefineWaves plans per
+            // thread by default, more when more rounds are asked), each
+            // within a kRefineWaves-th of the budget
             const double total = std::min(kRefineCapUs, kRefineRatio * plan_cost(out));
-            const int waves = total >= kRefineWaves * kSettleUs ? kRefineWaves : 1;
-            const double budget = total / waves;
+            const bool settle = total >= kRefineWaves * kSettleUs;
+            const int waves = settle ? std::max(kRefineWaves, rounds / 4) : 1;
+            const double budget = settle ? total / kRefineWaves : total;
             std::vector<const Plan*> cand{&out};
             for (const Plan& p : pool)
                 if (cand.size() < size_t(std::max(1, threads)) * size_t(waves)) cand.push_back(&p);
