@@ -60,8 +60,10 @@ WGraph reduced_graph(const Reduced& r, bool unit_weights) {
     return g;
 }
 
-std::vector<std::vector<int32_t>> components(const WGraph& g, const std::vector<int32_t>& verts) {
-    std::vector<int32_t> mark(g.n, -2);
+// Connected components of the subgraph induced by verts; mark has g.n
+// entries, -2 on entry and again on return (only verts' entries are touched).
+std::vector<std::vector<int32_t>> components(const WGraph& g, const std::vector<int32_t>& verts,
+                                             std::vector<int32_t>& mark) {
     for (int32_t v : verts) mark[v] = -1;
     std::vector<std::vector<int32_t>> comps;
     for (int32_t v : verts) {
@@ -81,13 +83,20 @@ std::vector<std::vector<int32_t>> components(const WGraph& g, const std::vector<
         std::sort(comp.begin(), comp.end());
         comps.push_back(std::move(comp));
     }
+    for (int32_t v : verts) mark[v] = -2;
     return comps;
+}
+
+std::vector<std::vector<int32_t>> components(const WGraph& g, const std::vector<int32_t>& verts) {
+    std::vector<int32_t> mark(g.n, -2);
+    return components(g, verts, mark);
 }
 
 namespace {
 
+// the subgraph induced by verts, vertex i being verts[i]; local has g.n
+// entries, -1 on entry and again on return
 WGraph induced(const WGraph& g, const std::vector<int32_t>& verts, std::vector<int32_t>& local) {
-    local.assign(g.n, -1);
     for (int32_t i = 0; i < int32_t(verts.size()); ++i) local[verts[i]] = i;
     WGraph h;
     h.n = int32_t(verts.size());
@@ -102,6 +111,7 @@ WGraph induced(const WGraph& g, const std::vector<int32_t>& verts, std::vector<i
             }
         h.xadj[i + 1] = int32_t(h.adj.size());
     }
+    for (int32_t v : verts) local[v] = -1;
     return h;
 }
 
@@ -437,7 +447,8 @@ struct PartitionBuilder {
     const WGraph& g;
     SplitMix rng;
     Tree tree;
-    PartitionBuilder(const WGraph& g_, uint64_t seed) : g(g_), rng(seed) {}
+    std::vector<int32_t> mark, local;  // scratch over g's vertices (components, induced)
+    PartitionBuilder(const WGraph& g_, uint64_t seed) : g(g_), rng(seed), mark(g_.n, -2), local(g_.n, -1) {}
 
     // join subtrees left to right (outer products of independent parts)
     int32_t chain(const std::vector<int32_t>& nodes) {
@@ -448,7 +459,7 @@ struct PartitionBuilder {
 
     int32_t build(const std::vector<int32_t>& verts) {
         if (verts.size() == 1) return ~verts[0];
-        auto comps = components(g, verts);
+        auto comps = components(g, verts, mark);
         if (comps.size() > 1) {
             std::sort(comps.begin(), comps.end(),
                       [](const std::vector<int32_t>& a, const std::vector<int32_t>& b) {
@@ -458,7 +469,6 @@ struct PartitionBuilder {
             for (const auto& c : comps) nodes.push_back(build(c));
             return chain(nodes);
         }
-        std::vector<int32_t> local;
         WGraph h = induced(g, verts, local);
         // best of two bisections (Sec. 3.1.1)
         int64_t c1 = 0, c2 = 0;
