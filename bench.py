@@ -174,8 +174,9 @@ def headline(tn, I, ws, args):
     def host_part():
         t = time.perf_counter()
         net = tn.Network(f)
+        tb = time.perf_counter()
         plan = net.order("best", seed=C3["seed"], rounds=args.search_rounds)
-        return net, plan, time.perf_counter() - t
+        return net, plan, (tb - t, time.perf_counter() - tb)
 
     ref = None
     lat, host = [], []
@@ -214,9 +215,11 @@ def headline(tn, I, ws, args):
         raise SystemExit("counts changed between passes")
     # the first warm-up step includes one-time set-up: latency from the others
     tail = lat[1:] or lat
-    htail = host[1:] or host
+    htail = [b + o for b, o in (host[1:] or host)]
+    btail = [b for b, _ in (host[1:] or host)]
     serial = {"latency_ms_per_count": round(1000 * sum(tail) / len(tail), 1),
               "host_ms_per_count": round(1000 * sum(htail) / len(htail), 1),
+              "build_ms_per_count": round(1000 * sum(btail) / len(btail), 1),
               "samples": len(tail)} if lat else None
     return f, plan, got[0], t1 - t0, acc, serial
 
