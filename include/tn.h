@@ -93,8 +93,8 @@ typedef enum {
     TN_ORDER_LEARNED = 3,    /* MLP pair scorer judged against greedy; plans predicted above
                                 50 ms go on to the full judge as its incumbent */
     TN_ORDER_BEST = 4,       /* cheapest of greedy, community and randomized partitions (rounds
-                                of one per host thread), searched while the host time spent
-                                stays below twice the best plan's predicted device time */
+                                of 16 over the host threads), searched while the host time
+                                spent stays below twice the best plan's predicted device time */
     TN_ORDER_LEARNED_RAW = 5 /* the learned order alone, not judged (evaluation) */
 } tn_order_kind;
 
@@ -204,11 +204,11 @@ tn_status tn_order(const tn_network* net, tn_order_kind kind, uint64_t seed,
 /* tn_order with a fixed search (Sec. 4: lazy evaluation, spending search where
  * the predicted contraction is costly): with rounds > 0, TN_ORDER_BEST (and
  * TN_ORDER_LEARNED when it hands its plan to the judge) runs exactly that
- * many rounds of randomized bisections, one per host thread, instead of
- * stopping at twice the best plan's predicted device time or 24 rounds (16
- * trials on one thread), and reconfigures the best quarter of them. The plan
- * then depends only on the seed and the number of host threads, unless
- * reconfiguring a plan outlasts its time budget (a share of at most 0.1 s).
+ * many rounds of 16 randomized bisections (spread over the host threads),
+ * instead of stopping at twice the best plan's predicted device time or 24
+ * rounds (one on a single thread), and reconfigures the best quarter of
+ * them until each settles, with no time budget: the plan then depends only
+ * on the seed.
  * rounds = 0 is tn_order; rounds outside [0, 256] give TN_EINVAL. */
 tn_status tn_order_rounds(const tn_network* net, tn_order_kind kind, uint64_t seed,
                           const tn_model* model, int32_t rounds, tn_plan** out,

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <thread>
 
@@ -12,14 +13,17 @@
 
 namespace tn {
 
-// randomized bisection trials of the judge's default rule on one host
-// thread, and rounds of one trial per thread on several. On 1-in-3 at
-// n = 300, alpha = 0.62 (six seeds, sixteen threads, the best quarter of the
-// trials reconfigured) 24 rounds give plans predicted 25 % cheaper than 8
-// (157 against 211 ms), 16 rounds 15 %, 32 no more than 24; smaller
-// instances stop earlier, by the time budget below.
-constexpr int kPartitionTrials = 16;
+// randomized bisection trials of the judge: rounds of 16, one round by
+// default on one host thread, kParallelRounds on several. On 1-in-3 at
+// n = 300, alpha = 0.62 (six seeds, the best quarter of the trials
+// reconfigured) 24 rounds give plans predicted 25 % cheaper than 8 (157
+// against 211 ms), 16 rounds 15 %, 32 no more than 24; smaller instances
+// stop earlier, by the time budget below.
+constexpr int kTrialsPerRound = 16;
 constexpr int kParallelRounds = 24;
+// trials handed to the host threads at a time after the first round (the
+// time budget is checked between them)
+constexpr int kTrialsPerChunk = 64;
 // most rounds a caller may ask for (tn_order_rounds)
 constexpr int kMaxRounds = 256;
 // host microseconds of order search allowed per predicted device microsecond
@@ -110,10 +114,12 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         // bisections (each itself best-of-2 per level); the cheapest `keep`
         // of them (distinct costs) stay for reconfiguration,
         // out being the cheapest
-        const int rounds = rounds_asked > 0        ? std::min(rounds_asked, kMaxRounds)
-                           : threads <= 1 ? kPartitionTrials
-                                          : kParallelRounds;
-        const size_t keep = size_t(std::max(1, threads)) * size_t(std::max(kRefineWaves, rounds / 4));
+        // rounds of kTrialsPerRound bisection trials whatever the number of
+        // threads, so that the plan does not depend on it; the best quarter
+        // of the trials is kept for reconfiguration
+        const int rounds = rounds_asked > 0 ? std::min(rounds_asked, kMaxRounds) : threads <= 1 ? 1 : kParallelRounds;
+        const int trials = rounds * kTrialsPerRound;
+        const size_t keep = size_t(std::max(kRefineWaves, trials / 4));
         std::vector<Plan> pool;
         auto consider = [&](tn_status s2, Plan& p) {
             if (s2 != TN_OK) {
@@ -192,18 +198,18 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 Plan p;
                 consider(plan_of(TN_ORDER_COMMUNITY, p), p);
             }
-            for (int t = 4; t < rounds && !over_budget(); ++t) partition_trial(t);
+            for (int t = 4; t < trials && !over_budget(); ++t) partition_trial(t);
         } else {
-            // rounds of one trial per thread while the search stays within
-            // its time budget; Girvan-Newman runs beside the rounds on a
-            // thread of its own (on the largest 1-in-3 configuration it takes
-            // as long as ten rounds)
+            // a first round, then chunks of kTrialsPerChunk trials while the
+            // search stays within its time budget; Girvan-Newman runs beside
+            // them on a thread of its own (on the largest 1-in-3
+            // configuration it takes as long as ten rounds)
             Plan gnp;
             tn_status gns = TN_EINVAL;
             std::thread gn([&]() { gns = plan_of(TN_ORDER_COMMUNITY, gnp); });
-            parallel_trials(0, threads);
-            for (int t = threads; t < rounds * threads && !over_budget(); t += threads)
-                parallel_trials(t, threads);
+            parallel_trials(0, kTrialsPerRound);
+            for (int t = kTrialsPerRound; t < trials && !over_budget(); t += kTrialsPerChunk)
+                parallel_trials(t, std::min(kTrialsPerChunk, trials - t));
             gn.join();
             consider(gns, gnp);
         }
@@ -212,17 +218,20 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         // parallel, each with the same share of the time budget); the
         // cheapest result wins
         if (have && out.merges.size() > 2) {
-            // several waves only when each plan still gets the time to
-            // settle: the best quarter of the trials (kRefineWaves plans per
-            // thread by default, more when more rounds are asked), each
-            // within a kRefineWaves-th of the budget
+            // every plan kept, each within a kRefineWaves-th of the budget,
+            // when that still gives it the time to settle; else one plan per
+            // thread, each within the whole budget. A fixed number of rounds
+            // reconfigures every plan kept until it settles (at most six
+            // sweeps), so that the plan depends on nothing else.
             const double total = std::min(kRefineCapUs, kRefineRatio * plan_cost(out));
-            const bool settle = total >= kRefineWaves * kSettleUs;
-            const int waves = settle ? std::max(kRefineWaves, rounds / 4) : 1;
-            const double budget = settle ? total / kRefineWaves : total;
+            const bool fixed = rounds_asked > 0;
+            const bool settle = fixed || total >= kRefineWaves * kSettleUs;
+            const size_t ncand = settle ? keep : size_t(std::max(1, threads));
+            const double budget = fixed ? std::numeric_limits<double>::infinity()
+                                        : settle ? total / kRefineWaves : total;
             std::vector<const Plan*> cand{&out};
             for (const Plan& p : pool)
-                if (cand.size() < size_t(std::max(1, threads)) * size_t(waves)) cand.push_back(&p);
+                if (cand.size() < ncand) cand.push_back(&p);
             std::vector<Plan> ref(cand.size());
             std::vector<tn_status> rs(cand.size(), TN_EINVAL);
             std::atomic<size_t> next{0};

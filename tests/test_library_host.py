@@ -288,6 +288,18 @@ def test_csp_build_validation_and_bounds():
     assert k.info() == (5, 0)
 
 
+def test_order_rounds_thread_independent(monkeypatch):
+    # rounds hold a fixed number of trials whatever the number of host
+    # threads, so a fixed search gives the same plan on one thread and on
+    # four (1-in-3 at n = 300: every kept plan is reconfigured to the end)
+    net = tn.Network(I.large_1in3(300, 0.62, 1))
+    plans = []
+    for t in ("1", "4"):
+        monkeypatch.setenv("TN_ORDER_THREADS", t)
+        plans.append(net.order("best", seed=1, rounds=1))
+    assert plans[0].verify() and plans[0].steps() == plans[1].steps()
+
+
 def test_order_rounds():
     # the judge with a fixed number of trial rounds: a valid plan, at least
     # as cheap as greedy's, the same plan on a second call; out-of-range
