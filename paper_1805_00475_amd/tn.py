@@ -182,6 +182,48 @@ class _FormulaArrays:
         self.c = Formula_c(formula.n_vars, formula.n_clauses, self.ptr, self.lits, self.kinds)
 
 
+class _FormulaBatch:
+    """The ctypes view of many formulas at once: three flat arrays (clause
+    offsets restarting at 0 per formula, literals, kinds) and one Formula_c
+    per formula pointing into them, filled with numpy rather than per-clause
+    ctypes conversions."""
+
+    def __init__(self, formulas):
+        import numpy as np
+        from itertools import chain
+        n = len(formulas)
+        m = np.fromiter((len(f.clauses) for f in formulas), dtype=np.int64, count=n)
+        clauses = [cl for f in formulas for _, cl in f.clauses]
+        lens = np.fromiter(map(len, clauses), dtype=np.int64, count=len(clauses))
+        self.lits = np.fromiter(chain.from_iterable(clauses), dtype=np.int32, count=int(lens.sum()))
+        self.kinds = np.fromiter((k for f in formulas for k, _ in f.clauses), dtype=np.uint8, count=len(clauses))
+        off = np.concatenate(([0], np.cumsum(lens)))            # literal offset of every clause boundary
+        first = np.concatenate(([0], np.cumsum(m)))[:-1]         # first clause of every formula
+        cnt = m + 1                                               # clause_ptr entries per formula
+        pstart = np.concatenate(([0], np.cumsum(cnt)))[:-1]
+        fid = np.repeat(np.arange(n), cnt)
+        within = np.arange(int(cnt.sum())) - np.repeat(pstart, cnt)
+        self.ptr = (off[first[fid] + within] - off[first[fid]]).astype(np.int32)
+        # keep the arrays non-empty so that every pointer is valid
+        if self.lits.size == 0:
+            self.lits = np.zeros(1, dtype=np.int32)
+        if self.kinds.size == 0:
+            self.kinds = np.zeros(1, dtype=np.uint8)
+        # the Formula_c records themselves, filled as one numpy record array
+        # with the same layout (two int32, three pointers)
+        rec = np.zeros(max(1, n), dtype=[("n_vars", "<i4"), ("n_clauses", "<i4"), ("ptr", "<u8"), ("lits", "<u8"),
+                                         ("kinds", "<u8")])
+        assert rec.dtype.itemsize == ctypes.sizeof(Formula_c)
+        pa, la, ka = self.ptr.ctypes.data, self.lits.ctypes.data, self.kinds.ctypes.data
+        rec["n_vars"][:n] = np.fromiter((f.n_vars for f in formulas), dtype=np.int32, count=n)
+        rec["n_clauses"][:n] = m
+        rec["ptr"][:n] = pa + 4 * pstart
+        rec["lits"][:n] = la + 4 * off[first]
+        rec["kinds"][:n] = ka + np.minimum(first, self.kinds.size - 1)
+        self.rec = rec
+        self.c = (Formula_c * max(1, n)).from_buffer(rec)
+
+
 def _stats_dict(s: PlanStats_c) -> dict:
     return {"n_steps": s.n_steps, "max_rank": s.max_rank, "entries": s.entries, "macs": s.macs,
             "log2_cost": s.log2_cost, "peak_elems": int(s.peak_elems), "chosen": ORDER_NAMES.get(s.chosen, s.chosen),
@@ -395,8 +437,8 @@ def count_batch(formulas: Sequence, order: str = "greedy", seed: int = 0, arith=
     """Batched counting (tn_count_batch) of many formulas."""
     lib = load()
     n = len(formulas)
-    arrs = [_FormulaArrays(f) for f in formulas]
-    fs = (Formula_c * max(1, n))(*[a.c for a in arrs])
+    batch = _FormulaBatch(formulas)
+    fs = batch.c
     ws = workspace or default_workspace()
     ptr, nb = ws.get(workspace_bytes_)
     o = _opts(arith, n_primes, ptr, nb, current_stream_handle(), 0, flags)

@@ -288,6 +288,23 @@ def test_csp_build_validation_and_bounds():
     assert k.info() == (5, 0)
 
 
+def test_formula_batch_marshalling():
+    # the flat-array view that count_batch hands to tn_count_batch holds
+    # every formula exactly as its own arrays do (formulas with no clause
+    # and with an empty clause included)
+    from instances.gen import Formula
+    fs = [I.batch_instance(i) for i in range(40)]
+    fs += [Formula(5, []), Formula(3, [(0, [1, -2]), (0, []), (1, [2, 3, -1])]), I.small_1in3(3)]
+    b = tn._FormulaBatch(fs)
+    for i, f in enumerate(fs):
+        ptr, lits, kinds = f.arrays()
+        c = b.c[i]
+        assert (c.n_vars, c.n_clauses) == (f.n_vars, f.n_clauses)
+        assert [c.clause_ptr[k] for k in range(len(ptr))] == ptr
+        assert [c.lits[k] for k in range(len(lits))] == lits
+        assert [c.kinds[k] for k in range(len(kinds))] == kinds
+
+
 def test_order_rounds_thread_independent(monkeypatch):
     # rounds hold a fixed number of trials whatever the number of host
     # threads, so a fixed search gives the same plan on one thread and on
