@@ -15,7 +15,6 @@
 // tensor, edge weight = number of bonds shared.
 #include <algorithm>
 #include <numeric>
-#include <queue>
 
 #include "graph.hpp"
 #include "internal.hpp"
@@ -146,8 +145,14 @@ void fm_refine(const WGraph& g, std::vector<uint8_t>& side, int max_passes) {
     for (int32_t v = 0; v < g.n; ++v)
         if (side[v] == 0) w0 += g.vw[v];
     const int64_t W = g.total_vw();
-    std::vector<int64_t> gain(g.n);
-    std::vector<uint8_t> locked(g.n);
+    // buffers kept per thread across calls (a trial refines hundreds of
+    // small graphs)
+    thread_local std::vector<int64_t> gain;
+    thread_local std::vector<uint8_t> locked;
+    thread_local std::vector<int32_t> moves;
+    thread_local std::vector<std::pair<int64_t, int32_t>> heap[2];
+    gain.assign(size_t(g.n), 0);
+    locked.assign(size_t(g.n), 0);
     bool unit = true;
     for (int32_t v = 0; v < g.n; ++v) unit = unit && g.vw[v] == 1;
     for (int pass = 0; pass < max_passes; ++pass) {
@@ -157,17 +162,23 @@ void fm_refine(const WGraph& g, std::vector<uint8_t>& side, int max_passes) {
             gain[v] = gv;
         }
         std::fill(locked.begin(), locked.end(), 0);
-        std::vector<int32_t> moves;
+        moves.clear();
         int64_t cur = 0, best = 0;
         size_t best_k = 0;
         int64_t best_dev = std::llabs(2 * w0 - W);
         int64_t cw0 = w0;
         // with unit vertex weights every vertex of a side is allowed or not
         // alike, so the best candidate is the top of one of two heaps
-        // (largest gain, then lowest index; stale entries skipped)
-        std::priority_queue<std::pair<int64_t, int32_t>> heap[2];
+        // (largest gain, then lowest index; stale entries skipped): binary
+        // max-heaps over (gain, -index)
+        auto push = [&](int sd, int64_t gv, int32_t v) {
+            heap[sd].push_back({gv, -v});
+            std::push_heap(heap[sd].begin(), heap[sd].end());
+        };
+        heap[0].clear();
+        heap[1].clear();
         if (unit)
-            for (int32_t v = 0; v < g.n; ++v) heap[side[v]].push({gain[v], -v});
+            for (int32_t v = 0; v < g.n; ++v) push(side[v], gain[v], v);
         auto allowed = [&](int64_t wv, int from) {
             const int64_t nw0 = from == 0 ? cw0 - wv : cw0 + wv;
             // a move out of an unbalanced state toward balance is allowed
@@ -179,12 +190,16 @@ void fm_refine(const WGraph& g, std::vector<uint8_t>& side, int max_passes) {
                 for (int sd = 0; sd < 2; ++sd) {
                     auto& h = heap[sd];
                     while (!h.empty()) {
-                        const int32_t v = -h.top().second;
-                        if (locked[v] || side[v] != sd || h.top().first != gain[v]) h.pop();
-                        else break;
+                        const int32_t v = -h.front().second;
+                        if (locked[v] || side[v] != sd || h.front().first != gain[v]) {
+                            std::pop_heap(h.begin(), h.end());
+                            h.pop_back();
+                        } else {
+                            break;
+                        }
                     }
                     if (h.empty() || !allowed(1, sd)) continue;
-                    const int32_t v = -h.top().second;
+                    const int32_t v = -h.front().second;
                     if (pick < 0 || gain[v] > gain[pick] || (gain[v] == gain[pick] && v < pick)) pick = v;
                 }
             } else {
@@ -204,7 +219,7 @@ void fm_refine(const WGraph& g, std::vector<uint8_t>& side, int max_passes) {
                 int32_t u = g.adj[e];
                 // edge (pick,u) changed from cut to uncut or back
                 gain[u] += side[u] == side[pick] ? -2 * g.ew[e] : 2 * g.ew[e];
-                if (unit && !locked[u]) heap[side[u]].push({gain[u], -u});
+                if (unit && !locked[u]) push(side[u], gain[u], u);
             }
             int64_t dev = std::llabs(2 * cw0 - W);
             bool inb = cw0 >= bal.lo && cw0 <= bal.hi;
@@ -329,33 +344,45 @@ WGraph coarsen(const WGraph& g, SplitMix& rng, std::vector<int32_t>& cmap) {
             cmap[match[v]] = nc;
             ++nc;
         }
+    // coarse adjacency, one coarse vertex at a time (its one or two fine
+    // members in index order): neighbours and summed weights gathered through
+    // a position table, then sorted by neighbour
     WGraph c;
     c.n = nc;
     c.vw.assign(nc, 0);
-    std::vector<std::vector<std::pair<int32_t, int32_t>>> al(nc);
-    for (int32_t v = 0; v < g.n; ++v) {
-        c.vw[cmap[v]] += g.vw[v];
-        for (int32_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e) {
-            int32_t a = cmap[v], b = cmap[g.adj[e]];
-            if (a == b) continue;
-            bool found = false;
-            for (auto& pr : al[a])
-                if (pr.first == b) {
-                    pr.second += g.ew[e];
-                    found = true;
-                    break;
-                }
-            if (!found) al[a].push_back({b, g.ew[e]});
-        }
-    }
     c.xadj.assign(nc + 1, 0);
-    for (int32_t a = 0; a < nc; ++a) {
-        std::sort(al[a].begin(), al[a].end());
-        for (const auto& pr : al[a]) {
+    c.adj.reserve(g.adj.size());
+    c.ew.reserve(g.adj.size());
+    std::vector<int32_t> pos(nc, -1);
+    std::vector<std::pair<int32_t, int32_t>> row;
+    int32_t a = 0;
+    for (int32_t v = 0; v < g.n; ++v) {
+        if (cmap[v] != a) continue;  // v is not the first member of a new coarse vertex
+        const int32_t members[2] = {v, match[v]};
+        const int nm = match[v] == v ? 1 : 2;
+        row.clear();
+        for (int k = 0; k < nm; ++k) {
+            const int32_t u = members[k];
+            c.vw[a] += g.vw[u];
+            for (int32_t e = g.xadj[u]; e < g.xadj[u + 1]; ++e) {
+                const int32_t b = cmap[g.adj[e]];
+                if (b == a) continue;
+                if (pos[b] < 0) {
+                    pos[b] = int32_t(row.size());
+                    row.push_back({b, g.ew[e]});
+                } else {
+                    row[size_t(pos[b])].second += g.ew[e];
+                }
+            }
+        }
+        std::sort(row.begin(), row.end());
+        for (const auto& pr : row) {
             c.adj.push_back(pr.first);
             c.ew.push_back(pr.second);
+            pos[pr.first] = -1;
         }
         c.xadj[a + 1] = int32_t(c.adj.size());
+        ++a;
     }
     return c;
 }
