@@ -91,7 +91,13 @@ bool reconfigure(Tree& t, int32_t v, std::vector<char>& is_frontier, std::vector
     if (t.left[v] < 0) return false;
     // grow the frontier from v's children, opening the highest-rank
     // internal node first
-    std::vector<int32_t> fr = {t.left[v], t.right[v]};
+    // buffers kept per thread across calls (a refinement makes about a
+    // thousand of them)
+    thread_local std::vector<int32_t> fr, old_internal, pool;
+    thread_local std::vector<uint64_t> sb;
+    thread_local std::vector<int> sr, split;
+    thread_local std::vector<double> cost;
+    fr.assign({t.left[v], t.right[v]});
     while (int(fr.size()) < kMaxFrontier) {
         int best = -1, br = -1;
         for (int i = 0; i < int(fr.size()); ++i)
@@ -108,15 +114,15 @@ bool reconfigure(Tree& t, int32_t v, std::vector<char>& is_frontier, std::vector
     if (k <= 2) return false;
     for (int32_t x : fr) is_frontier[x] = 1;
     const double old_cost = subtree_cost(t, v, is_frontier);
-    std::vector<int32_t> old_internal;
+    old_internal.clear();
     collect_internal(t, v, is_frontier, old_internal);
     // DP over subsets of the frontier
     const int S = 1 << k;
     const int W = t.words;
-    std::vector<uint64_t> sb(size_t(S) * W, 0);
-    std::vector<int> sr(S, 0);
-    std::vector<double> cost(S, 0.0);
-    std::vector<int> split(S, 0);
+    sb.assign(size_t(S) * W, 0);
+    sr.assign(size_t(S), 0);
+    cost.assign(size_t(S), 0.0);
+    split.assign(size_t(S), 0);
     for (int m = 1; m < S; ++m) {
         const int low = __builtin_ctz(m);
         const int rest = m & (m - 1);
@@ -145,7 +151,7 @@ bool reconfigure(Tree& t, int32_t v, std::vector<char>& is_frontier, std::vector
     bool changed = false;
     if (cost[full] < old_cost * (1.0 - 1e-9)) {
         // rebuild: reuse the k-1 internal node ids (v stays the root)
-        std::vector<int32_t> pool;
+        pool.clear();
         for (int32_t x : old_internal)
             if (x != v) pool.push_back(x);
         // recursive assembly
