@@ -162,8 +162,8 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         };
         auto partition_trial = [&](int t) {
             Plan p;
-            tn_status s2 = make_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t)),
-                                     TN_ORDER_PARTITION, p);
+            tn_status s2 = sketch_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t)),
+                                       TN_ORDER_PARTITION, p);
             consider(s2, p);
         };
         // trials t0 .. t0 + n - 1 on `threads` host threads; the judge sees
@@ -178,8 +178,8 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 for (;;) {
                     const int i = next.fetch_add(1);
                     if (i >= n) break;
-                    st[size_t(i)] = make_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t0 + i)),
-                                              TN_ORDER_PARTITION, plans[size_t(i)]);
+                    st[size_t(i)] = sketch_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t0 + i)),
+                                                TN_ORDER_PARTITION, plans[size_t(i)]);
                 }
             };
             std::vector<std::thread> pool;
@@ -241,7 +241,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 for (;;) {
                     const size_t i = next.fetch_add(1);
                     if (i >= cand.size()) break;
-                    rs[i] = make_plan(N, refine_order(N, cand[i]->merges, budget), cand[i]->stats.chosen, ref[i]);
+                    rs[i] = sketch_plan(N, refine_order(N, cand[i]->merges, budget), cand[i]->stats.chosen, ref[i]);
                 }
             };
             std::vector<std::thread> pool_threads;
@@ -260,6 +260,14 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 ref[size_t(bi)].stats.refined = 1;
                 out = std::move(ref[size_t(bi)]);
             }
+        }
+        // trials and reconfigured plans are sketches (merges and cost): the
+        // winner gets its layouts, steps and arena
+        if (have && out.sketch) {
+            const int32_t refined = out.stats.refined;
+            const tn_status s2 = make_plan(N, out.merges, out.stats.chosen, out);
+            if (s2 != TN_OK) return s2;
+            out.stats.refined = refined;
         }
         if (kind == TN_ORDER_LEARNED && have) out.stats.fallback = out.stats.chosen != TN_ORDER_LEARNED;
         return have ? TN_OK : last;

@@ -65,6 +65,7 @@ struct Plan {
     int64_t warena_elems = 0;                  // arena size when steps run in waves by level
     int32_t root = -1;                         // id of the final scalar
     double cost_us = -1;                       // plan_cost, kept by make_plan (-1: not yet)
+    bool sketch = false;                       // merges, cost and stats only (sketch_plan)
     tn_plan_stats stats{};
 };
 
@@ -98,6 +99,11 @@ Reduced absorb_small(const Network& net);
 // plan.cpp
 tn_status make_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>> merges,
                     int32_t chosen, Plan& plan);
+// The same checks and predicted cost as make_plan, without layouts, steps
+// or arena: merges, cost_us and stats (n_steps, max_rank, log2_cost,
+// chosen); make_plan of the same merges gives the full plan of equal cost.
+tn_status sketch_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>> merges, int32_t chosen,
+                      Plan& plan);
 // Residue arithmetic a contraction uses by default for counts of at most
 // 2^count_bits: 64-bit wrapping counts (count_bits <= 63), small moduli
 // (int8 residues) when their product holds the count, else 16-bit primes;

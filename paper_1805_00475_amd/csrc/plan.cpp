@@ -137,17 +137,100 @@ double step_cost_model(int rA, int rB, int s, int rC, int mode) {
     return 1e6 * t;
 }
 
+namespace {
+
+// A plan's predicted device time, accumulated one step at a time in plan
+// order (every residue plane, launches included); make_plan and
+// sketch_plan both sum through it, so that a sketch's cost is the full
+// plan's to the last bit.
+struct CostSum {
+    static constexpr int kPlanesPerLaunch = 16;  // residue planes of one launch
+    static constexpr double kLaunchUs = 5.0;
+    int mode;
+    int32_t planes;
+    double launches;
+    double t = 0;
+    explicit CostSum(int32_t count_bits)
+        : mode(default_residue_mode(count_bits)),
+          planes(default_planes(count_bits)),
+          launches(double((planes + kPlanesPerLaunch - 1) / kPlanesPerLaunch)) {}
+    void add(int rA, int rB, int s, int rC) { t += planes * step_cost_model(rA, rB, s, rC, mode) + launches * kLaunchUs; }
+};
+
+}  // namespace
+
 double plan_cost(const Plan& plan) {
     if (plan.cost_us >= 0) return plan.cost_us;
-    constexpr int kPlanesPerLaunch = 16;  // residue planes of one launch
-    constexpr double kLaunchUs = 5.0;
-    const int mode = default_residue_mode(plan.count_bits);
-    const int32_t planes = default_planes(plan.count_bits);
-    const double launches = double((planes + kPlanesPerLaunch - 1) / kPlanesPerLaunch);
-    double t = 0;
-    for (const Step& st : plan.steps)
-        t += planes * step_cost_model(st.rA, st.rB, st.s, st.rC, mode) + launches * kLaunchUs;
-    return t;
+    CostSum c(plan.count_bits);
+    for (const Step& st : plan.steps) c.add(st.rA, st.rB, st.s, st.rC);
+    return c.t;
+}
+
+tn_status sketch_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>> merges, int32_t chosen,
+                      Plan& plan) {
+    try {
+        const int32_t n_init = int32_t(net.t.size());
+        const int32_t n_ids = n_init + int32_t(merges.size());
+        const int32_t W = int32_t((net.bond_end.size() + 63) / 64) + 1;
+        // bond sets as bit sets: C's bonds are A's and B's less the shared ones
+        std::vector<uint64_t> bits(size_t(n_ids) * size_t(W), 0);
+        std::vector<int32_t> rank(size_t(n_ids), 0);
+        std::vector<int8_t> state(size_t(n_ids), 0);  // 0 unborn, 1 live, 2 consumed
+        int32_t maxr = 0;
+        for (int32_t i = 0; i < n_init; ++i) {
+            uint64_t* b = bits.data() + size_t(i) * W;
+            for (int32_t bnd : net.t[i].bonds) {
+                if ((b[bnd >> 6] >> (bnd & 63)) & 1) return TN_EINVAL;
+                b[bnd >> 6] |= uint64_t(1) << (bnd & 63);
+            }
+            rank[i] = int32_t(net.t[i].bonds.size());
+            maxr = std::max(maxr, rank[i]);
+            state[i] = 1;
+        }
+        CostSum cost(net.count_bits);
+        for (int32_t k = 0; k < int32_t(merges.size()); ++k) {
+            const int32_t a = merges[k].first, b = merges[k].second, c = n_init + k;
+            if (a < 0 || b < 0 || a >= c || b >= c || a == b) return TN_EINVAL;
+            if (state[a] != 1 || state[b] != 1) return TN_EINVAL;
+            state[a] = state[b] = 2;
+            state[c] = 1;
+            const uint64_t *ba = bits.data() + size_t(a) * W, *bb = bits.data() + size_t(b) * W;
+            uint64_t* bc = bits.data() + size_t(c) * W;
+            int32_t rC = 0;
+            for (int32_t w = 0; w < W; ++w) {
+                bc[w] = ba[w] ^ bb[w];
+                rC += __builtin_popcountll(bc[w]);
+            }
+            if (rC > TN_MAX_RANK) return TN_ERANK;
+            rank[c] = rC;
+            cost.add(rank[a], rank[b], (rank[a] + rank[b] - rC) / 2, rC);
+            maxr = std::max(maxr, rC);
+        }
+        int32_t live = 0, root = -1;
+        for (int32_t i = 0; i < n_ids; ++i)
+            if (state[i] == 1) {
+                ++live;
+                root = i;
+            }
+        if (n_ids > 0 && live != 1) return TN_EINVAL;
+        if (root >= 0 && rank[root] != 0) return TN_EINVAL;  // open bonds left
+        plan = Plan{};
+        plan.n_init = n_init;
+        plan.n_vars = net.n_vars;
+        plan.count_bits = net.count_bits;
+        plan.max_entry = net.max_entry;
+        plan.merges = std::move(merges);
+        plan.root = root;
+        plan.sketch = true;
+        plan.cost_us = cost.t;
+        plan.stats.n_steps = int32_t(plan.merges.size());
+        plan.stats.max_rank = maxr;
+        plan.stats.log2_cost = cost.t > 0 ? std::log2(cost.t) : 0.0;
+        plan.stats.chosen = chosen;
+    } catch (const std::bad_alloc&) {
+        return TN_ENOMEM;
+    }
+    return TN_OK;
 }
 
 tn_status make_plan(const Network& net, std::vector<std::pair<int32_t, int32_t>> merges, int32_t chosen,
