@@ -36,12 +36,14 @@ constexpr double kEscalateUs = 50000.0;
 // most host time spent reconfiguring plans, and its share of the predicted
 // device time (measured on n = 200 cubic vertex-cover batches: 0.5 gives
 // 45.1 counts/s against 44.2 at 2, 43.4 at 0.25 and 39.0 without
-// reconfiguration). The time goes to kRefineWaves waves of one plan per
-// host thread, each plan with its share of it, when the shares are long
-// enough for reconfiguration to settle: where it settles depends on the
-// starting plan more than on the time, so two plans per thread beat one
-// (predicted device time over six seeds 28 % lower on 1-in-3 at n = 300,
-// alpha = 0.62, seed 1 and at n = 250, 7 % at n = 300, seed 4)
+// reconfiguration). Every plan kept (the best quarter of the trials) is
+// reconfigured within a kRefineWaves-th of that time when such a share is
+// long enough for reconfiguration to settle (kSettleUs), else one plan per
+// thread within the whole of it. Where a plan settles depends on the
+// starting plan more than on the time given, so reconfiguring many plans
+// pays (with 8 rounds, two plans per thread instead of one: predicted
+// device time over six seeds 28 % lower on 1-in-3 at n = 300, alpha =
+// 0.62, seed 1 and at n = 250, 7 % at n = 300, seed 4)
 constexpr double kRefineCapUs = 100000.0;
 constexpr double kRefineRatio = 0.5;
 constexpr int kRefineWaves = 2;
