@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <thread>
 
@@ -21,9 +22,6 @@ namespace tn {
 // stop earlier, by the time budget below.
 constexpr int kTrialsPerRound = 16;
 constexpr int kParallelRounds = 24;
-// trials handed to the host threads at a time after the first round (the
-// time budget is checked between them)
-constexpr int kTrialsPerChunk = 64;
 // most rounds a caller may ask for (tn_order_rounds)
 constexpr int kMaxRounds = 256;
 // host microseconds of order search allowed per predicted device microsecond
@@ -168,27 +166,47 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                                        TN_ORDER_PARTITION, p);
             consider(s2, p);
         };
-        // trials t0 .. t0 + n - 1 on `threads` host threads; the judge sees
+        // trials first .. first + n - 1 on `threads` host threads; the judge sees
         // every plan, in trial order, so that which thread ran which trial
         // does not matter
-        auto parallel_trials = [&](int t0, int n) {
+        auto parallel_trials = [&](int first, int n) {
             const int T = std::min(threads, n);
             std::vector<Plan> plans(static_cast<size_t>(n));
             std::vector<tn_status> st(static_cast<size_t>(n), TN_ERANK);
             std::atomic<int> next{0};
+            // under the time budget, the threads stop taking trials once the
+            // time spent exceeds kSearchRatio times the cheapest plan found
+            // so far (the incumbent's or a finished trial's); the trials
+            // taken are always a prefix of the range and all complete
+            std::atomic<bool> stop{false};
+            std::mutex mu;
+            double cheapest = have ? plan_cost(out) : std::numeric_limits<double>::infinity();
             auto work = [&]() {
                 for (;;) {
+                    if (stop.load(std::memory_order_relaxed)) break;
                     const int i = next.fetch_add(1);
                     if (i >= n) break;
-                    st[size_t(i)] = sketch_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t0 + i)),
-                                                TN_ORDER_PARTITION, plans[size_t(i)]);
+                    Plan& p = plans[size_t(i)];
+                    st[size_t(i)] = sketch_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(first + i)),
+                                                TN_ORDER_PARTITION, p);
+                    if (rounds_asked > 0) continue;
+                    double c;
+                    {
+                        std::lock_guard<std::mutex> lk(mu);
+                        if (st[size_t(i)] == TN_OK) cheapest = std::min(cheapest, plan_cost(p));
+                        c = cheapest;
+                    }
+                    const double spent_us =
+                        std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+                    if (spent_us > kSearchRatio * c) stop.store(true, std::memory_order_relaxed);
                 }
             };
             std::vector<std::thread> pool;
             for (int w = 1; w < T; ++w) pool.emplace_back(work);
             work();
             for (auto& th : pool) th.join();
-            for (int i = 0; i < n; ++i) consider(st[size_t(i)], plans[size_t(i)]);
+            const int done = std::min(n, next.load());
+            for (int i = 0; i < done; ++i) consider(st[size_t(i)], plans[size_t(i)]);
         };
         if (kind != TN_ORDER_LEARNED) {
             Plan p;
@@ -204,16 +222,15 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             }
             for (int t = 4; t < trials && !over_budget(); ++t) partition_trial(t);
         } else {
-            // a first round, then chunks of kTrialsPerChunk trials while the
-            // search stays within its time budget; Girvan-Newman runs beside
-            // them on a thread of its own (on the largest 1-in-3
-            // configuration it takes as long as ten rounds)
+            // a first round, then the other trials in one go, the threads
+            // stopping by the time budget; Girvan-Newman runs beside them on
+            // a thread of its own (on the largest 1-in-3 configuration it
+            // takes as long as ten rounds)
             Plan gnp;
             tn_status gns = TN_EINVAL;
             std::thread gn([&]() { gns = plan_of(TN_ORDER_COMMUNITY, gnp); });
             parallel_trials(0, kTrialsPerRound);
-            for (int t = kTrialsPerRound; t < trials && !over_budget(); t += kTrialsPerChunk)
-                parallel_trials(t, std::min(kTrialsPerChunk, trials - t));
+            if (trials > kTrialsPerRound && !over_budget()) parallel_trials(kTrialsPerRound, trials - kTrialsPerRound);
             gn.join();
             consider(gns, gnp);
         }
