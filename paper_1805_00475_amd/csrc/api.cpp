@@ -169,21 +169,22 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         // trials first .. first + n - 1 on `threads` host threads; the judge sees
         // every plan, in trial order, so that which thread ran which trial
         // does not matter
-        auto parallel_trials = [&](int first, int n) {
+        auto parallel_trials = [&](int first, int n, int at_least) {
             const int T = std::min(threads, n);
             std::vector<Plan> plans(static_cast<size_t>(n));
             std::vector<tn_status> st(static_cast<size_t>(n), TN_ERANK);
             std::atomic<int> next{0};
-            // under the time budget, the threads stop taking trials once the
-            // time spent exceeds kSearchRatio times the cheapest plan found
-            // so far (the incumbent's or a finished trial's); the trials
-            // taken are always a prefix of the range and all complete
+            // under the time budget, the threads stop taking trials (after
+            // the first at_least) once the time spent exceeds kSearchRatio
+            // times the cheapest plan found so far (the incumbent's or a
+            // finished trial's); a trial taken always completes, so the
+            // trials done are a prefix of the range
             std::atomic<bool> stop{false};
             std::mutex mu;
             double cheapest = have ? plan_cost(out) : std::numeric_limits<double>::infinity();
             auto work = [&]() {
                 for (;;) {
-                    if (stop.load(std::memory_order_relaxed)) break;
+                    if (stop.load() && next.load() >= at_least) break;
                     const int i = next.fetch_add(1);
                     if (i >= n) break;
                     Plan& p = plans[size_t(i)];
@@ -198,7 +199,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                     }
                     const double spent_us =
                         std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
-                    if (spent_us > kSearchRatio * c) stop.store(true, std::memory_order_relaxed);
+                    if (spent_us > kSearchRatio * c) stop.store(true);
                 }
             };
             std::vector<std::thread> pool;
@@ -222,15 +223,14 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             }
             for (int t = 4; t < trials && !over_budget(); ++t) partition_trial(t);
         } else {
-            // a first round, then the other trials in one go, the threads
-            // stopping by the time budget; Girvan-Newman runs beside them on
-            // a thread of its own (on the largest 1-in-3 configuration it
-            // takes as long as ten rounds)
+            // every trial in one pass: at least a round, then as many as the
+            // time budget allows; Girvan-Newman runs beside them on a thread
+            // of its own (on the largest 1-in-3 configuration it takes as
+            // long as ten rounds)
             Plan gnp;
             tn_status gns = TN_EINVAL;
             std::thread gn([&]() { gns = plan_of(TN_ORDER_COMMUNITY, gnp); });
-            parallel_trials(0, kTrialsPerRound);
-            if (trials > kTrialsPerRound && !over_budget()) parallel_trials(kTrialsPerRound, trials - kTrialsPerRound);
+            parallel_trials(0, trials, kTrialsPerRound);
             gn.join();
             consider(gns, gnp);
         }
