@@ -264,7 +264,8 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 }
             };
             std::vector<std::thread> pool_threads;
-            const int T = std::min<int>(threads, int(cand.size()));
+            // (with several threads, Girvan-Newman's is free again by now)
+            const int T = std::min<int>(threads > 1 ? threads + 1 : 1, int(cand.size()));
             for (int t = 1; t < T; ++t) pool_threads.emplace_back(work);
             work();
             for (auto& th : pool_threads) th.join();
