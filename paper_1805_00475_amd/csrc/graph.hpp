@@ -55,9 +55,10 @@ struct SplitMix {
     uint32_t below(uint32_t n) { return uint32_t(next() % n); }
 };
 
-// Balanced min-cut bisection (multilevel: heavy-edge coarsening, greedy
-// graph growing, Fiduccia-Mattheyses refinement). Returns side 0/1 per
-// vertex and the cut weight.
+// Balanced min-cut bisection (multilevel: heavy-edge coarsening, every
+// split of a coarsest graph of at most 12 vertices or else greedy graph
+// growing, Fiduccia-Mattheyses refinement). Returns side 0/1 per vertex and
+// the cut weight.
 std::vector<uint8_t> bisect(const WGraph& g, SplitMix& rng, int64_t* cut);
 
 // A binary contraction tree over vertex indices 0..n-1 of some graph:
