@@ -112,13 +112,11 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 return TN_OK;
             }
         }
-        // candidates: greedy, community, and randomized recursive
-        // bisections (each itself best-of-2 per level); the cheapest `keep`
-        // of them (distinct costs) stay for reconfiguration,
-        // out being the cheapest
-        // rounds of kTrialsPerRound bisection trials whatever the number of
-        // threads, so that the plan does not depend on it; the best quarter
-        // of the trials is kept for reconfiguration
+        // Candidates: greedy, community, and randomized recursive bisections
+        // (each itself best-of-2 per level), in rounds of kTrialsPerRound
+        // whatever the number of threads, so that the plan does not depend
+        // on it. The cheapest `keep` of them (distinct costs, a quarter of
+        // the trials) stay for reconfiguration, out being the cheapest.
         const int rounds = rounds_asked > 0 ? std::min(rounds_asked, kMaxRounds) : threads <= 1 ? 1 : kParallelRounds;
         const int trials = rounds * kTrialsPerRound;
         const size_t keep = size_t(std::max(kRefineWaves, trials / 4));
@@ -143,9 +141,10 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             while (!pool.empty() && plan_cost(pool.front()) == plan_cost(out)) pool.erase(pool.begin());
             if (pool.size() + 1 > keep) pool.resize(keep - 1);
         };
-        // Candidates in increasing host cost: greedy, four randomized
-        // bisections, Girvan-Newman, then more bisections. After the first
-        // three, stop once the host time spent on this search exceeds
+        // Time budget: on one thread the candidates come in increasing host
+        // cost (greedy, four bisections, Girvan-Newman, more bisections), on
+        // several the bisections of the first round always run; after that
+        // the search stops once the host time spent on it exceeds
         // kSearchRatio times the predicted device time of the best plan so
         // far (all residue planes). The device cannot start before the first
         // plan of a batch is ready, so search time beyond the device time it
