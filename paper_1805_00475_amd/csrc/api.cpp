@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <limits>
@@ -45,6 +46,10 @@ constexpr double kEscalateUs = 50000.0;
 constexpr double kRefineCapUs = 100000.0;
 constexpr double kRefineRatio = 0.5;
 constexpr int kRefineWaves = 2;
+// predicted device microseconds from which the judge waits for the tighter
+// count bound it computes beside the trials (about 0.1 s of one host thread
+// at n = 300; one residue plane fewer saves a twelfth of the device time)
+constexpr double kTightBoundUs = 50000.0;
 // host time in which reconfiguration settles: 4-7 ms on plans of vertex
 // cover n = 200, 8-11 ms on 1-in-3 n = 300; with less time per plan than
 // this, one wave
@@ -112,6 +117,39 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 return TN_OK;
             }
         }
+        // The tighter count bound (count_bound.cpp) of a boolean formula of
+        // more than 64 bits' bound, on a thread of its own beside the
+        // trials; joined (or cancelled) whatever way this function ends.
+        struct TightBound {
+            std::thread th;
+            std::atomic<bool> cancel{false};
+            int32_t bits = -1;
+            std::vector<int32_t> ptr, lits;
+            std::vector<uint8_t> kinds;
+            void start(const Network& net) {
+                if (net.f_ptr.empty() || net.n_vars <= 63 || net.count_bits <= 64) return;
+                ptr = net.f_ptr;
+                lits = net.f_lits;
+                kinds = net.f_kinds;
+                const int32_t nv = net.n_vars;
+                th = std::thread([this, nv]() {
+                    const tn_formula f{nv, int32_t(kinds.size()), ptr.data(), lits.data(), kinds.data()};
+                    bits = count_bound_bits_tight(&f, &cancel);
+                });
+            }
+            int32_t finish(bool wait) {
+                if (!th.joinable()) return -1;
+                if (!wait) cancel = true;
+                th.join();
+                return bits;
+            }
+            ~TightBound() {
+                if (th.joinable()) {
+                    cancel = true;
+                    th.join();
+                }
+            }
+        } tight;
         // Candidates: greedy, community, and randomized recursive bisections
         // (each itself best-of-2 per level), in rounds of kTrialsPerRound
         // whatever the number of threads, so that the plan does not depend
@@ -229,6 +267,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             Plan gnp;
             tn_status gns = TN_EINVAL;
             std::thread gn([&]() { gns = plan_of(TN_ORDER_COMMUNITY, gnp); });
+            tight.start(N);
             parallel_trials(0, trials, kTrialsPerRound);
             gn.join();
             consider(gns, gnp);
@@ -287,6 +326,19 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             const tn_status s2 = make_plan(N, out.merges, out.stats.chosen, out);
             if (s2 != TN_OK) return s2;
             out.stats.refined = refined;
+        }
+        // the tighter bound: waited for when the plan is costly enough for
+        // a residue plane to matter (always with a fixed number of rounds,
+        // so that the plan depends on nothing else), else used only if done
+        {
+            const bool wait = rounds_asked > 0 || (have && plan_cost(out) >= kTightBoundUs);
+            const int32_t tb = tight.finish(wait);
+            if (have && tb >= 0 && out.count_bits > 64 && tb < out.count_bits) {
+                out.count_bits = std::max<int32_t>(64, tb);
+                out.cost_us = -1;
+                out.cost_us = plan_cost(out);
+                out.stats.log2_cost = out.cost_us > 0 ? std::log2(out.cost_us) : 0.0;
+            }
         }
         if (kind == TN_ORDER_LEARNED && have) out.stats.fallback = out.stats.chosen != TN_ORDER_LEARNED;
         return have ? TN_OK : last;

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <array>
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <utility>
@@ -31,6 +32,10 @@ struct Network {
     uint64_t max_entry = 2;   // largest entry of an initial tensor
     std::vector<InitTensor> t;                   // variables first, then clauses, then split pieces
     std::vector<std::array<int32_t, 2>> bond_end;  // the two tensors of every bond
+    // the formula a boolean network was built from (clause offsets,
+    // literals, kinds; empty for constraint networks)
+    std::vector<int32_t> f_ptr, f_lits;
+    std::vector<uint8_t> f_kinds;
 };
 
 // One pairwise contraction C = A (x) B in the layout convention of the plan:
@@ -126,6 +131,13 @@ tn_status verify_plan(const Plan& plan);
 // count_bound.cpp: ceil(log2) of an upper bound on the count of a boolean
 // formula (mini-bucket elimination; at most n_vars; 0 when a clause is empty)
 int32_t count_bound_bits(const tn_formula* f);
+// the tighter, costlier variant (Hoelder norms per mini-bucket, larger
+// mini-buckets, least-fill order)
+// -1 when *cancel turns true before it ends
+int32_t count_bound_bits_tight(const tn_formula* f, const std::atomic<bool>* cancel = nullptr);
+// the elimination behind both, any mini-bucket size (checks use small ones)
+int32_t count_bound_bits_with(const tn_formula* f, int ib, bool weighted, int fill_cands,
+                              const std::atomic<bool>* cancel = nullptr);
 
 // api.cpp: order of any kind (with the judge for BEST / LEARNED) + plan
 // threads: host threads for the judge's randomized bisection trials (one

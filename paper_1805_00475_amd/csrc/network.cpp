@@ -182,6 +182,10 @@ tn_status build_network(const tn_formula* f, Network& net) {
         // residues; it is kept at 64 bits or more, so such formulas stay
         // with small moduli rather than 64-bit counts
         if (f->n_vars > 63) net.count_bits = std::max<int32_t>(64, count_bound_bits(f));
+        // the formula itself, for the order search's tighter bound
+        net.f_ptr.assign(f->clause_ptr, f->clause_ptr + (f->n_clauses > 0 ? f->n_clauses + 1 : 0));
+        net.f_lits.assign(f->lits, f->lits + nl);
+        net.f_kinds.assign(f->kinds, f->kinds + f->n_clauses);
     } catch (const std::bad_alloc&) {
         return TN_ENOMEM;
     }

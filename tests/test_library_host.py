@@ -305,6 +305,21 @@ def test_formula_batch_marshalling():
         assert [c.kinds[k] for k in range(len(kinds))] == kinds
 
 
+def test_judged_plan_carries_the_tighter_bound():
+    # the judge computes the tighter count bound beside its trials and the
+    # plan it returns carries it: on the largest 1-in-3 configuration (the
+    # network's bound is 93 bits, 12 small moduli) the judged plan needs 11
+    # moduli (the tighter bound is 85 bits); plans of a single order keep
+    # the network's bound
+    from math import prod
+    net = tn.Network(I.large_1in3(300, 0.62, 1))
+    assert net.ranks()[1] == 93
+    judged = tn.moduli(net.order("best", seed=1, rounds=1))
+    plain = tn.moduli(net.order("partition", seed=1))
+    assert len(plain) == 12 and len(judged) == 11 and judged == plain[:11]
+    assert prod(judged) > 2 ** 86
+
+
 def test_order_rounds_thread_independent(monkeypatch):
     # rounds hold a fixed number of trials whatever the number of host
     # threads, so a fixed search gives the same plan on one thread and on
