@@ -110,10 +110,17 @@ int32_t count_bound_bits_with(const tn_formula* f, int ib, bool weighted, int fi
         tabs.push_back(std::move(x));
     }
     std::vector<std::set<int32_t>> adj(static_cast<size_t>(n));
+    // the same adjacency as bit rows, kept for the least-fill order
+    const size_t words = size_t(n + 63) / 64;
+    std::vector<uint64_t> rows(fill_cands > 0 ? size_t(n) * words : 0, 0);
+    auto link = [&](int32_t u, int32_t y) {
+        adj[size_t(u)].insert(y);
+        if (fill_cands > 0) rows[size_t(u) * words + size_t(y) / 64] |= uint64_t(1) << (y % 64);
+    };
     for (const Table& x : tabs)
         for (int32_t u : x.vars)
             for (int32_t y : x.vars)
-                if (y != u) adj[size_t(u)].insert(y);
+                if (y != u) link(u, y);
     std::vector<char> alive(static_cast<size_t>(n), 1);
     double bits = 0;
     for (int32_t step = 0; step < n; ++step) {
@@ -131,11 +138,16 @@ int32_t count_bound_bits_with(const tn_formula* f, int ib, bool weighted, int fi
             std::sort(cands.begin(), cands.end());
             long best_fill = -1;
             for (const auto& cu : cands) {
-                const std::set<int32_t>& nb = adj[size_t(cu.second)];
+                // pairs of neighbours not yet adjacent: each neighbour's
+                // non-neighbours among the others, counted from both ends
+                const uint64_t* ru = rows.data() + size_t(cu.second) * words;
                 long fill = 0;
-                for (auto a = nb.begin(); a != nb.end(); ++a)
-                    for (auto b = std::next(a); b != nb.end(); ++b)
-                        if (!adj[size_t(*a)].count(*b)) ++fill;
+                for (int32_t a : adj[size_t(cu.second)]) {
+                    const uint64_t* ra = rows.data() + size_t(a) * words;
+                    for (size_t w = 0; w < words; ++w) fill += __builtin_popcountll(ru[w] & ~ra[w]);
+                    --fill;  // a itself
+                }
+                fill /= 2;
                 if (best_fill < 0 || fill < best_fill) {
                     best_fill = fill;
                     v = cu.second;
@@ -150,7 +162,10 @@ int32_t count_bound_bits_with(const tn_formula* f, int ib, bool weighted, int fi
                 }
         }
         alive[size_t(v)] = 0;
-        for (int32_t y : adj[size_t(v)]) adj[size_t(y)].erase(v);
+        for (int32_t y : adj[size_t(v)]) {
+            adj[size_t(y)].erase(v);
+            if (fill_cands > 0) rows[size_t(y) * words + size_t(v) / 64] &= ~(uint64_t(1) << (v % 64));
+        }
         std::vector<int32_t> bucket;
         for (int32_t id : holds[size_t(v)])
             if (tabs[size_t(id)].alive) bucket.push_back(id);
@@ -220,7 +235,7 @@ int32_t count_bound_bits_with(const tn_formula* f, int ib, bool weighted, int fi
             for (int32_t u : out.vars) {
                 holds[size_t(u)].push_back(int32_t(tabs.size()));
                 for (int32_t y : out.vars)
-                    if (y != u) adj[size_t(u)].insert(y);
+                    if (y != u) link(u, y);
             }
             tabs.push_back(std::move(out));
         }
