@@ -47,7 +47,7 @@ constexpr double kRefineCapUs = 100000.0;
 constexpr double kRefineRatio = 0.5;
 constexpr int kRefineWaves = 2;
 // predicted device microseconds from which the judge waits for the tighter
-// count bound it computes beside the trials (about 0.1 s of one host thread
+// count bound it computes beside the trials (about 40 ms of one host thread
 // at n = 300; one residue plane fewer saves a twelfth of the device time)
 constexpr double kTightBoundUs = 50000.0;
 // host time in which reconfiguration settles: 4-7 ms on plans of vertex

@@ -20,8 +20,8 @@
 //   sum_v prod_j P_j(v, .) <= prod_j (sum_v P_j(v, .)^k)^(1/k),
 // one k-norm per mini-bucket (k = 1 is the exact sum); it takes
 // mini-buckets of up to 17 other variables and eliminates by least fill
-// among the 16 variables of fewest neighbours. It costs about ten times as
-// much (about 0.1 s at n = 300) and saves one residue plane on the largest
+// among the 16 variables of fewest neighbours. It costs about four times as
+// much (about 40 ms at n = 300) and saves one residue plane on the largest
 // configurations (1-in-3 n = 300: 85 bits against 93; the norms alone at
 // 15 other variables give 90).
 //
