@@ -11,6 +11,7 @@
 #include <new>
 #include <thread>
 
+#include "graph.hpp"
 #include "internal.hpp"
 
 namespace tn {
@@ -158,6 +159,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         const int rounds = rounds_asked > 0 ? std::min(rounds_asked, kMaxRounds) : threads <= 1 ? 1 : kParallelRounds;
         const int trials = rounds * kTrialsPerRound;
         const size_t keep = size_t(std::max(kRefineWaves, trials / 4));
+        const PartitionInput pin = partition_input(N);  // shared by every trial
         std::vector<Plan> pool;
         auto consider = [&](tn_status s2, Plan& p) {
             if (s2 != TN_OK) {
@@ -199,7 +201,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
         };
         auto partition_trial = [&](int t) {
             Plan p;
-            tn_status s2 = sketch_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(t)),
+            tn_status s2 = sketch_plan(N, order_partition(pin, seed * 0x9E3779B97F4A7C15ull + uint64_t(t)),
                                        TN_ORDER_PARTITION, p);
             consider(s2, p);
         };
@@ -225,7 +227,7 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                     const int i = next.fetch_add(1);
                     if (i >= n) break;
                     Plan& p = plans[size_t(i)];
-                    st[size_t(i)] = sketch_plan(N, order_partition(N, seed * 0x9E3779B97F4A7C15ull + uint64_t(first + i)),
+                    st[size_t(i)] = sketch_plan(N, order_partition(pin, seed * 0x9E3779B97F4A7C15ull + uint64_t(first + i)),
                                                 TN_ORDER_PARTITION, p);
                     if (rounds_asked > 0) continue;
                     double c;

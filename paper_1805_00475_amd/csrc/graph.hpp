@@ -79,6 +79,16 @@ inline int32_t tree_node(Tree& t, int32_t l, int32_t r) {
 // reduced vertices (leaf v stands for tensor r.id[v]).
 std::vector<std::pair<int32_t, int32_t>> merges_from_tree(const Reduced& r, const Tree& t, int32_t root);
 
+// The partition order's input, the same for every trial of an order
+// search: the network with its tensors of rank <= 2 absorbed, as a
+// weighted graph.
+struct PartitionInput {
+    Reduced r;
+    WGraph g;
+};
+PartitionInput partition_input(const Network& net);
+std::vector<std::pair<int32_t, int32_t>> order_partition(const PartitionInput& in, uint64_t seed);
+
 WGraph reduced_graph(const Reduced& r, bool unit_weights);
 std::vector<std::vector<int32_t>> components(const WGraph& g, const std::vector<int32_t>& verts);
 

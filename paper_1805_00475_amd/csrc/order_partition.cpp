@@ -510,15 +510,24 @@ struct PartitionBuilder {
 
 }  // namespace
 
-std::vector<std::pair<int32_t, int32_t>> order_partition(const Network& net, uint64_t seed) {
-    Reduced r = absorb_small(net);
-    if (r.id.size() <= 1) return r.merges;
-    WGraph g = reduced_graph(r, false);
-    PartitionBuilder pb(g, seed ^ 0x5EEDB15EC7ull);
-    std::vector<int32_t> all(g.n);
+PartitionInput partition_input(const Network& net) {
+    PartitionInput in;
+    in.r = absorb_small(net);
+    if (in.r.id.size() > 1) in.g = reduced_graph(in.r, false);
+    return in;
+}
+
+std::vector<std::pair<int32_t, int32_t>> order_partition(const PartitionInput& in, uint64_t seed) {
+    if (in.r.id.size() <= 1) return in.r.merges;
+    PartitionBuilder pb(in.g, seed ^ 0x5EEDB15EC7ull);
+    std::vector<int32_t> all(in.g.n);
     std::iota(all.begin(), all.end(), 0);
     int32_t root = pb.build(all);
-    return merges_from_tree(r, pb.tree, root);
+    return merges_from_tree(in.r, pb.tree, root);
+}
+
+std::vector<std::pair<int32_t, int32_t>> order_partition(const Network& net, uint64_t seed) {
+    return order_partition(partition_input(net), seed);
 }
 
 }  // namespace tn
