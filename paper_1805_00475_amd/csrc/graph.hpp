@@ -58,8 +58,9 @@ struct SplitMix {
 // Balanced min-cut bisection (multilevel: heavy-edge coarsening, every
 // split of a coarsest graph of at most 12 vertices or else greedy graph
 // growing, Fiduccia-Mattheyses refinement). Returns side 0/1 per vertex and
-// the cut weight.
-std::vector<uint8_t> bisect(const WGraph& g, SplitMix& rng, int64_t* cut);
+// the cut weight; *deterministic (if given) tells whether the result used
+// no random draw (every split of the graph itself was tried).
+std::vector<uint8_t> bisect(const WGraph& g, SplitMix& rng, int64_t* cut, bool* deterministic = nullptr);
 
 // A binary contraction tree over vertex indices 0..n-1 of some graph:
 // children of internal node k are kids[k]; leaves are encoded as ~vertex.

@@ -389,9 +389,11 @@ WGraph coarsen(const WGraph& g, SplitMix& rng, std::vector<int32_t>& cmap) {
 
 }  // namespace
 
-std::vector<uint8_t> bisect(const WGraph& g, SplitMix& rng, int64_t* cut) {
+std::vector<uint8_t> bisect(const WGraph& g, SplitMix& rng, int64_t* cut, bool* deterministic) {
+    if (deterministic) *deterministic = false;
     if (g.n <= 1) {
         if (cut) *cut = 0;
+        if (deterministic) *deterministic = true;
         return std::vector<uint8_t>(g.n, 0);
     }
     std::vector<WGraph> levels{g};
@@ -407,6 +409,8 @@ std::vector<uint8_t> bisect(const WGraph& g, SplitMix& rng, int64_t* cut) {
     std::vector<uint8_t> best;
     int64_t bestcut = -1;
     if (top.n <= kExactBisect) best = exact_bisect(top);
+    // every split of the graph itself tried, no random draw made
+    if (deterministic) *deterministic = !best.empty() && maps.empty();
     const int grow_trials = best.empty() ? 6 : 0;
     for (int t = 0; t < grow_trials; ++t) {
         std::vector<uint8_t> side = grow(top, rng);
@@ -497,11 +501,13 @@ struct PartitionBuilder {
             return chain(nodes);
         }
         WGraph h = induced(g, verts, local);
-        // best of two bisections (Sec. 3.1.1)
+        // best of two bisections (Sec. 3.1.1); when the first tried every
+        // split without a random draw, the second would repeat it
         int64_t c1 = 0, c2 = 0;
-        std::vector<uint8_t> s1 = bisect(h, rng, &c1);
-        std::vector<uint8_t> s2 = bisect(h, rng, &c2);
-        const std::vector<uint8_t>& s = c2 < c1 ? s2 : s1;
+        bool same = false;
+        std::vector<uint8_t> s1 = bisect(h, rng, &c1, &same);
+        std::vector<uint8_t> s2 = same ? std::vector<uint8_t>() : bisect(h, rng, &c2);
+        const std::vector<uint8_t>& s = !same && c2 < c1 ? s2 : s1;
         std::vector<int32_t> L, R;
         for (int32_t i = 0; i < h.n; ++i) (s[i] == 0 ? L : R).push_back(verts[i]);
         return tree_node(tree, build(L), build(R));
