@@ -135,7 +135,11 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 const int32_t nv = net.n_vars;
                 th = std::thread([this, nv]() {
                     const tn_formula f{nv, int32_t(kinds.size()), ptr.data(), lits.data(), kinds.data()};
-                    bits = count_bound_bits_tight(&f, &cancel);
+                    try {
+                        bits = count_bound_bits_tight(&f, &cancel);
+                    } catch (const std::bad_alloc&) {
+                        bits = -1;  // no tighter bound: the network's stays
+                    }
                 });
             }
             int32_t finish(bool wait) {
@@ -227,8 +231,13 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                     const int i = next.fetch_add(1);
                     if (i >= n) break;
                     Plan& p = plans[size_t(i)];
-                    st[size_t(i)] = sketch_plan(N, order_partition(pin, seed * 0x9E3779B97F4A7C15ull + uint64_t(first + i)),
-                                                TN_ORDER_PARTITION, p);
+                    try {
+                        st[size_t(i)] = sketch_plan(
+                            N, order_partition(pin, seed * 0x9E3779B97F4A7C15ull + uint64_t(first + i)),
+                            TN_ORDER_PARTITION, p);
+                    } catch (const std::bad_alloc&) {
+                        st[size_t(i)] = TN_ENOMEM;
+                    }
                     if (rounds_asked > 0) continue;
                     double c;
                     {
@@ -268,7 +277,13 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
             // long as ten rounds)
             Plan gnp;
             tn_status gns = TN_EINVAL;
-            std::thread gn([&]() { gns = plan_of(TN_ORDER_COMMUNITY, gnp); });
+            std::thread gn([&]() {
+                try {
+                    gns = plan_of(TN_ORDER_COMMUNITY, gnp);
+                } catch (const std::bad_alloc&) {
+                    gns = TN_ENOMEM;
+                }
+            });
             tight.start(N);
             parallel_trials(0, trials, kTrialsPerRound);
             gn.join();
@@ -300,7 +315,11 @@ tn_status make_order(const Network& N, int32_t kind, uint64_t seed, const tn_mod
                 for (;;) {
                     const size_t i = next.fetch_add(1);
                     if (i >= cand.size()) break;
-                    rs[i] = sketch_plan(N, refine_order(N, cand[i]->merges, budget), cand[i]->stats.chosen, ref[i]);
+                    try {
+                        rs[i] = sketch_plan(N, refine_order(N, cand[i]->merges, budget), cand[i]->stats.chosen, ref[i]);
+                    } catch (const std::bad_alloc&) {
+                        rs[i] = TN_ENOMEM;
+                    }
                 }
             };
             std::vector<std::thread> pool_threads;
