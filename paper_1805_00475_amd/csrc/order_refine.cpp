@@ -116,9 +116,38 @@ bool reconfigure(Tree& t, int32_t v, std::vector<char>& is_frontier, std::vector
     const double old_cost = subtree_cost(t, v, is_frontier);
     old_internal.clear();
     collect_internal(t, v, is_frontier, old_internal);
-    // DP over subsets of the frontier
+    // DP over subsets of the frontier, on bond sets restricted to the bonds
+    // the frontier nodes hold (every subset's result lies within them): at
+    // most 8 x 64 bonds, so a few words instead of one bit per bond of the
+    // network
     const int S = 1 << k;
-    const int W = t.words;
+    thread_local std::vector<int32_t> local_of;  // bond -> local index, -1 elsewhere
+    thread_local std::vector<int32_t> held;
+    thread_local std::vector<uint64_t> lbits;
+    if (local_of.size() < size_t(t.words) * 64) local_of.assign(size_t(t.words) * 64, -1);
+    held.clear();
+    for (int32_t x : fr) {
+        const uint64_t* bx = t.b(x);
+        for (int w = 0; w < t.words; ++w)
+            for (uint64_t word = bx[w]; word; word &= word - 1) {
+                const int32_t bnd = w * 64 + __builtin_ctzll(word);
+                if (local_of[size_t(bnd)] < 0) {
+                    local_of[size_t(bnd)] = int32_t(held.size());
+                    held.push_back(bnd);
+                }
+            }
+    }
+    const int W = int(held.size() + 63) / 64;
+    lbits.assign(size_t(k) * W, 0);
+    for (int i = 0; i < k; ++i) {
+        const uint64_t* bx = t.b(fr[size_t(i)]);
+        for (int w = 0; w < t.words; ++w)
+            for (uint64_t word = bx[w]; word; word &= word - 1) {
+                const int32_t l = local_of[size_t(w * 64 + __builtin_ctzll(word))];
+                lbits[size_t(i) * W + size_t(l) / 64] |= uint64_t(1) << (l % 64);
+            }
+    }
+    for (int32_t bnd : held) local_of[size_t(bnd)] = -1;
     sb.assign(size_t(S) * W, 0);
     sr.assign(size_t(S), 0);
     cost.assign(size_t(S), 0.0);
@@ -126,7 +155,7 @@ bool reconfigure(Tree& t, int32_t v, std::vector<char>& is_frontier, std::vector
     for (int m = 1; m < S; ++m) {
         const int low = __builtin_ctz(m);
         const int rest = m & (m - 1);
-        const uint64_t* lb = t.b(fr[size_t(low)]);
+        const uint64_t* lb = lbits.data() + size_t(low) * W;
         for (int i = 0; i < W; ++i) sb[size_t(m) * W + i] = sb[size_t(rest) * W + i] ^ lb[i];
         int c = 0;
         for (int i = 0; i < W; ++i) c += __builtin_popcountll(sb[size_t(m) * W + i]);
@@ -159,7 +188,6 @@ bool reconfigure(Tree& t, int32_t v, std::vector<char>& is_frontier, std::vector
             Tree& t;
             const std::vector<int32_t>& fr;
             const std::vector<int>& split;
-            const std::vector<uint64_t>& sb;
             std::vector<int32_t>& pool;
             int32_t make(int m, int32_t id) {
                 if ((m & (m - 1)) == 0) return fr[size_t(__builtin_ctz(m))];
@@ -172,7 +200,10 @@ bool reconfigure(Tree& t, int32_t v, std::vector<char>& is_frontier, std::vector
                 t.right[id] = nb;
                 t.parent[na] = id;
                 t.parent[nb] = id;
-                std::memcpy(t.b(id), sb.data() + size_t(m) * t.words, sizeof(uint64_t) * t.words);
+                // the node's bonds: its children's, less the shared ones
+                const uint64_t *ba = t.b(na), *bn = t.b(nb);
+                uint64_t* bi = t.b(id);
+                for (int w = 0; w < t.words; ++w) bi[w] = ba[w] ^ bn[w];
                 return id;
             }
             int32_t take() {
@@ -180,7 +211,7 @@ bool reconfigure(Tree& t, int32_t v, std::vector<char>& is_frontier, std::vector
                 pool.pop_back();
                 return x;
             }
-        } bld{t, fr, split, sb, pool};
+        } bld{t, fr, split, pool};
         bld.make(full, v);
         changed = true;
         rebuilt = old_internal;
