@@ -198,7 +198,12 @@ tn_status tn_network_info(const tn_network* net, int32_t* n_tensors, int32_t* n_
  * (bit order of every tensor, arena offsets, kernel choice) and its
  * predicted cost. ``seed`` drives the randomized bisections. ``model`` is
  * used by TN_ORDER_LEARNED (may be NULL otherwise; with NULL the learned
- * order falls back to the judge's choice). */
+ * order falls back to the judge's choice). With several host threads the
+ * judge (TN_ORDER_BEST, and TN_ORDER_LEARNED when it hands its plan on)
+ * also computes a tighter count bound for a boolean formula whose
+ * network's bound exceeds 64 bits, and the plan carries it: its
+ * contraction may then use fewer residue planes than tn_network_ranks'
+ * count_bits implies (never fewer than for 64 bits). */
 tn_status tn_order(const tn_network* net, tn_order_kind kind, uint64_t seed,
                    const tn_model* model, tn_plan** out, tn_plan_stats* stats);
 /* tn_order with a fixed search (Sec. 4: lazy evaluation, spending search where
