@@ -243,6 +243,33 @@ int32_t count_bound_bits_with(const tn_formula* f, int ib, bool weighted, int fi
     return int32_t(std::min<double>(double(n), std::ceil(bits + 1e-6)));
 }
 
+double disjoint_clause_bound_bits(const tn_formula* f) {
+    // The formula restricted to clauses taken greedily in order while they
+    // share no variable with those taken (and repeat none): its count,
+    // 2^(n - sum |c|) prod sat(c), is at least the formula's, since leaving
+    // clauses out only adds solutions.
+    std::vector<char> used(size_t(std::max(0, f->n_vars)), 0);
+    double bits = double(f->n_vars);
+    for (int32_t c = 0; c < f->n_clauses; ++c) {
+        const int32_t b = f->clause_ptr[c], e = f->clause_ptr[c + 1];
+        if (b == e) return 0.0;  // an empty clause: no solution
+        bool free = true;
+        for (int32_t i = b; i < e && free; ++i) {
+            const int32_t v = std::abs(f->lits[i]) - 1;
+            free = !used[size_t(v)];
+            for (int32_t j = b; j < i && free; ++j) free = std::abs(f->lits[j]) - 1 != v;
+        }
+        if (!free) continue;
+        const int k = e - b;
+        const double sat = f->kinds[c] == TN_CLAUSE_OR ? std::ldexp(1.0, k) - 1.0
+                           : f->kinds[c] == TN_CLAUSE_EXACTLY_ONE ? double(k)
+                                                                 : std::ldexp(1.0, k - 1);
+        bits += std::log2(sat) - double(k);
+        for (int32_t i = b; i < e; ++i) used[size_t(std::abs(f->lits[i]) - 1)] = 1;
+    }
+    return bits;
+}
+
 int32_t count_bound_bits(const tn_formula* f) {
     return count_bound_bits_with(f, f->n_vars >= kBigFrom ? kIBoundBig : kIBoundSmall, false, 0);
 }

@@ -131,6 +131,9 @@ tn_status verify_plan(const Plan& plan);
 // count_bound.cpp: ceil(log2) of an upper bound on the count of a boolean
 // formula (mini-bucket elimination; at most n_vars; 0 when a clause is empty)
 int32_t count_bound_bits(const tn_formula* f);
+// a quick bound (log2, not rounded): the count of the formula kept to a
+// greedy set of variable-disjoint clauses
+double disjoint_clause_bound_bits(const tn_formula* f);
 // the tighter, costlier variant (Hoelder norms per mini-bucket, larger
 // mini-buckets, least-fill order)
 // -1 when *cancel turns true before it ends

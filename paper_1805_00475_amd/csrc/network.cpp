@@ -181,7 +181,12 @@ tn_status build_network(const tn_formula* f, Network& net) {
         // beyond 63 variables, the elimination bound (count_bound.cpp) sizes the
         // residues; it is kept at 64 bits or more, so such formulas stay
         // with small moduli rather than 64-bit counts
-        if (f->n_vars > 63) net.count_bits = std::max<int32_t>(64, count_bound_bits(f));
+        // (a quick bound within 64 bits settles it without the elimination,
+        // as it does for most random 1-in-3 formulas of a few hundred clauses)
+        if (f->n_vars > 63)
+            net.count_bits = disjoint_clause_bound_bits(f) <= 64.0 - 1e-6
+                                 ? 64
+                                 : std::max<int32_t>(64, count_bound_bits(f));
         // the formula itself, for the order search's tighter bound
         net.f_ptr.assign(f->clause_ptr, f->clause_ptr + (f->n_clauses > 0 ? f->n_clauses + 1 : 0));
         net.f_lits.assign(f->lits, f->lits + nl);

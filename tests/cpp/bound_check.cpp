@@ -1,4 +1,5 @@
-// Host check of the count bounds on random small formulas: OR,
+// Host check of the count bounds (and the quick disjoint-clause bound) on
+// random small formulas: OR,
 // exactly-one and parity clauses of 1 to 4 literals with negations and
 // repeats, 4 to 20 variables. Every bound b (the library's two, and the
 // same elimination with mini-buckets of 1 to 4 other variables, with one
@@ -50,6 +51,12 @@ int main() {
             count += ok;
         }
         const double need = count ? std::log2(double(count)) : -1.0;
+        const double quick = disjoint_clause_bound_bits(&f);
+        if (quick < need - 1e-9) {
+            std::printf("trial %d (n %d, m %d): count %llu, disjoint-clause bound %.3f bits\n", trial, n, m,
+                        (unsigned long long)count, quick);
+            bad = 1;
+        }
         std::vector<int32_t> bs{count_bound_bits(&f), count_bound_bits_tight(&f)};
         for (int ib = 1; ib <= 4; ++ib)
             for (int w = 0; w < 2; ++w)
